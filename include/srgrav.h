@@ -1,0 +1,170 @@
+/*
+ * srgrav.h -- short-range TreePM gravity on AMD Instinct MI355X (gfx950).
+ *
+ * The short-range half of a Gadget-style TreePM gravity solver: for every
+ * target particle, a Barnes-Hut walk of an octree, opened by an angular (or
+ * relative) criterion, applying each accepted node or particle on the fly
+ * (the module the paper ports, Sec. 2 "OpenGadget3 infrastructure" and its
+ * GPU-porting subsection; the TreePM split with the long-range mesh on the
+ * CPU is stated in Sec. 3.1).  Per target i:
+ *
+ *   a_i = sum over accepted sources s with |d| < r_cut of  G M_s S_h(|d|) g(|d| / 2 r_s) d,
+ *   d   = min-image(x_s - x_i),   h = max(h_i, h_s),   h = 2.8 eps,
+ *   g(u) = erfc(u) + 2u/sqrt(pi) exp(-u^2)         (short-range part of the erfc split)
+ *   S_h(r) = cubic-spline softened 1/r^3           (= 1/r^3 for r >= h)
+ *
+ * The library builds the tree on the device (integer coordinates, 90-bit
+ * Morton keys, LDS radix sort, compressed octree, FP64 node moments) and
+ * walks it by wavefront-sized target groups.  The paper builds the tree on
+ * the host and re-uploads it every step (its GPU-porting subsection and
+ * Appendix A); here nothing but launches and one small status read cross the
+ * host-device boundary.
+ *
+ * Conventions for every entry point:
+ *   - Pointers marked DEVICE are device memory (HIP / torch.cuda tensors) of
+ *     the current device, contiguous, owned by the caller.  Nothing is
+ *     retained after a call except inside an sr_tree handle.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream).
+ *     Calls synchronise that stream only where stated.
+ *   - Every call returns SR_OK (0) or a negative error code and never throws;
+ *     srgrav_last_error() gives a message for the calling thread.
+ *   - Outputs are overwritten, never accumulated into.
+ *   - Particle arrays are in the caller's (input) order; outputs for a target
+ *     subset follow the order of the `active` array.
+ */
+#ifndef SRGRAV_H
+#define SRGRAV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+enum {
+    SR_OK = 0,
+    SR_EINVAL = -1,        /* invalid argument or input value (NaN/Inf, range) */
+    SR_ENOMEM = -2,        /* device allocation failed */
+    SR_EHIP = -3,          /* a HIP runtime call failed */
+    SR_ESTATE = -4,        /* handle does not match the call (e.g. never built) */
+    SR_EUNSUPPORTED = -5   /* argument combination not implemented */
+};
+
+/* opening criterion */
+enum {
+    SR_OPEN_BH = 0,        /* open iff l^2 > theta^2 r^2 (r to the node's centre of mass) */
+    SR_OPEN_RELATIVE = 1   /* open iff G M l^2 > alpha |a_old| r^4, or l^2 > theta^2 r^2 */
+};
+
+/* arithmetic of the walk */
+enum {
+    SR_FP64 = 0,           /* FP64 positions, decisions, forces and sums */
+    SR_FP32 = 1,           /* integer coordinates, FP32 decisions, forces and sums */
+    SR_FP32_ACC64 = 2      /* as SR_FP32 but every target sums its forces in FP64 */
+};
+
+typedef struct sr_tree sr_tree;
+
+typedef struct {
+    double G;              /* gravitational constant (1 in all synthetic workloads) */
+    double r_s;            /* PM split scale, r_s = 1.25 L / N_mesh in Gadget's default */
+    double r_cut;          /* short-range cutoff (4.5 r_s by default); 0 < r_cut < L/2 */
+    int32_t criterion;     /* SR_OPEN_BH or SR_OPEN_RELATIVE */
+    double theta;          /* opening angle (BH), or the geometric guard (RELATIVE); >= 0 */
+    double alpha;          /* relative tolerance (RELATIVE only); >= 0 */
+    int32_t precision;     /* SR_FP64, SR_FP32 or SR_FP32_ACC64 */
+} sr_params;
+
+/*
+ * tree_build -- keys, sort, octree and node moments for n particles.
+ *
+ *   pos   DEVICE double[n*3]  positions, any real values; wrapped into [0, box)
+ *   mass  DEVICE double[n]    masses (> 0)
+ *   eps   DEVICE double[n]    Plummer-equivalent softening per particle (> 0),
+ *                             or NULL to use eps_scalar for every particle
+ *   n     1 <= n <= 2^30
+ *   box   periodic box side L > 0
+ *   leaf_size  must be 1 (every particle is its own leaf)
+ *   tree  in/out: if *tree is NULL a new handle is created; otherwise that
+ *         handle is rebuilt in place, growing its workspace only when n
+ *         exceeds what it holds.  The handle keeps its own copy of every
+ *         sorted particle record, so callers may change pos/mass afterwards.
+ *
+ * The node set is the compressed octree of the 90-bit Morton keys (cells with
+ * at least two non-empty children, and level-30 buckets of identical keys), in
+ * pre-order.  Synchronises `stream` once, to read the node count and the
+ * finiteness flag.  SR_EINVAL on NaN/Inf positions, masses or softenings.
+ */
+int tree_build(const double* pos, const double* mass, const double* eps, double eps_scalar,
+               int64_t n, double box, int32_t leaf_size, void* stream, sr_tree** tree);
+
+/*
+ * shortrange_accel -- short-range accelerations of the targets.
+ *
+ *   active    DEVICE int32[n_active] distinct input indices of the targets, or
+ *             NULL for all particles (then n_active must equal n)
+ *   a_old     DEVICE double[n]  |a| of the previous step per particle (input
+ *             order); read only for SR_OPEN_RELATIVE, else may be NULL
+ *   acc       DEVICE [n_active*3] output, double unless p->precision == SR_FP32
+ *             (then float)
+ *   counts    DEVICE int32[n_active*2] output (particle-particle, particle-node
+ *             interactions per target), or NULL
+ *
+ * Per-target semantics are those of a depth-first walk of one particle; the
+ * group walk only shares the traversal.  Synchronises `stream` once when
+ * `active` is given, to report out-of-range or repeated indices.
+ */
+int shortrange_accel(sr_tree* tree, const sr_params* p, const int32_t* active, int64_t n_active,
+                     const double* a_old, void* acc, int32_t* counts, void* stream);
+
+/*
+ * shortrange_accel_adjoint -- gradient of L = sum_t w_t . a_t.
+ *
+ * The walk is repeated with the same inputs, so the tree topology, node
+ * membership, opening decisions and cutoff membership are those of the forward
+ * pass; L is differentiated with all of them held fixed.
+ *
+ *   w     DEVICE [n_active*3] cotangent, same element type as `acc`
+ *   dLdx  DEVICE double[n*3]  output, input order (w.r.t. the wrapped positions,
+ *                             which is the same as w.r.t. pos)
+ *   dLdm  DEVICE double[n]    output, input order
+ *
+ * Node terms are scattered with device atomics, so the low bits of the result
+ * may differ from run to run.
+ */
+int shortrange_accel_adjoint(sr_tree* tree, const sr_params* p, const int32_t* active,
+                             int64_t n_active, const double* a_old, const void* w, double* dLdx,
+                             double* dLdm, void* stream);
+
+/* Internal arrays of a built tree, copied into caller buffers (DEVICE; any may
+ * be NULL).  Node arrays need room for tree_node_count() entries. */
+typedef struct {
+    uint64_t* key_hi;      /* [n] sorted keys, digits 1..15 (45 bits) */
+    uint64_t* key_lo;      /* [n] digits 16..30 */
+    int32_t* perm;         /* [n] sorted position -> input index */
+    int32_t* level;        /* [nodes] octree level 0..30 */
+    int32_t* first;        /* [nodes] first sorted position */
+    int32_t* count;        /* [nodes] particles in the node */
+    int32_t* parent;       /* [nodes] parent node, -1 for the root */
+    int32_t* skip;         /* [nodes] first node after the subtree (pre-order) */
+    uint32_t* corner;      /* [nodes*3] cube corner in integer coordinates */
+    double* M;             /* [nodes] mass */
+    double* com;           /* [nodes*3] centre of mass */
+    float* M32;            /* [nodes] (float)M */
+    uint32_t* comX;        /* [nodes*3] rint(com / L * 2^32) mod 2^32 */
+} sr_tree_export;
+
+int tree_node_count(const sr_tree* tree, int64_t* n_nodes);
+int tree_export(const sr_tree* tree, const sr_tree_export* out, void* stream);
+
+/* Frees the handle and its device workspace (NULL is allowed). */
+void tree_free(sr_tree* tree);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* srgrav_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SRGRAV_H */

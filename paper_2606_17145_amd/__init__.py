@@ -1,0 +1,174 @@
+"""Short-range TreePM gravity on AMD Instinct MI355X.
+
+The short-range half of a Gadget-style TreePM solver -- Morton-key octree
+build, FP64 node moments, group-wise Barnes-Hut walk with the erfc-split,
+spline-softened, minimum-image pair force -- as hand-written HIP kernels for
+gfx950 behind a C ABI (``include/srgrav.h``).  This package is the thin torch
+binding: tensors in, tensors out, every step on the device.
+
+    tree = tree_build(pos, mass, eps=eps, box=1.0)
+    acc, counts = shortrange_accel(tree, params)              # params: dict
+    dLdx, dLdm = shortrange_accel_adjoint(tree, params, w)    # L = sum w . acc
+    acc = ShortRangeAccel.apply(pos, mass, eps, params)       # differentiable
+
+``params`` keys: G, r_s, r_cut, theta, criterion ("bh" | "relative"), alpha,
+precision ("fp64" | "fp32" | "fp32_acc64").
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import torch
+
+from . import _lib
+from ._lib import SrgravError  # noqa: F401
+
+__all__ = ["Tree", "tree_build", "shortrange_accel", "shortrange_accel_adjoint", "ShortRangeAccel",
+           "kdk_rollout", "SrgravError"]
+
+
+def _dev_f64(x, n=None, name="tensor"):
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    x = x.detach().to(torch.float64).contiguous()
+    return x
+
+
+class Tree:
+    """An sr_tree handle: the device-resident tree of one particle set."""
+
+    def __init__(self):
+        self._h = C.c_void_p(None)
+        self.n = 0
+        self.box = 1.0
+        self.device = None
+
+    def __del__(self):
+        try:
+            if self._h:
+                _lib.lib().tree_free(self._h)
+                self._h = C.c_void_p(None)
+        except Exception:
+            pass
+
+    def build(self, pos, mass, eps=None, eps_scalar=None, box=1.0):
+        pos = _dev_f64(pos, name="pos")
+        n = pos.shape[0]
+        if pos.shape != (n, 3):
+            raise ValueError("pos must have shape (N, 3)")
+        mass = torch.as_tensor(mass, dtype=torch.float64, device=pos.device)
+        mass = mass.expand(n).contiguous() if mass.dim() == 0 else mass.contiguous()
+        eps_t = None
+        if eps is not None and (not isinstance(eps, (int, float))):
+            eps_t = torch.as_tensor(eps, dtype=torch.float64, device=pos.device)
+            eps_t = eps_t.expand(n).contiguous() if eps_t.dim() == 0 else eps_t.contiguous()
+        else:
+            eps_scalar = float(eps if eps is not None else eps_scalar)
+        with torch.cuda.device(pos.device):
+            _lib.check(_lib.lib().tree_build(_lib.ptr(pos), _lib.ptr(mass), _lib.ptr(eps_t),
+                                             float(eps_scalar or 0.0), n, float(box), 1,
+                                             _lib.stream_handle(), C.byref(self._h)))
+        self.n, self.box, self.device = n, float(box), pos.device
+        return self
+
+    def node_count(self) -> int:
+        m = C.c_int64(0)
+        _lib.check(_lib.lib().tree_node_count(self._h, C.byref(m)))
+        return int(m.value)
+
+    def export(self) -> dict:
+        """Copies of the sorted keys, permutation and node arrays (device tensors)."""
+        n, m = self.n, self.node_count()
+        dev = self.device
+        i32 = dict(dtype=torch.int32, device=dev)
+        out = dict(key_hi=torch.empty(n, dtype=torch.int64, device=dev),
+                   key_lo=torch.empty(n, dtype=torch.int64, device=dev),
+                   perm=torch.empty(n, **i32), level=torch.empty(m, **i32),
+                   first=torch.empty(m, **i32), count=torch.empty(m, **i32),
+                   parent=torch.empty(m, **i32), skip=torch.empty(m, **i32),
+                   corner=torch.empty((m, 3), **i32),
+                   M=torch.empty(m, dtype=torch.float64, device=dev),
+                   com=torch.empty((m, 3), dtype=torch.float64, device=dev),
+                   M32=torch.empty(m, dtype=torch.float32, device=dev),
+                   comX=torch.empty((m, 3), **i32))
+        ex = _lib.SrTreeExport(*[_lib.ptr(out[k]) if out[k].numel() else None for k in
+                                 ("key_hi", "key_lo", "perm", "level", "first", "count", "parent",
+                                  "skip", "corner", "M", "com", "M32", "comX")])
+        with torch.cuda.device(dev):
+            _lib.check(_lib.lib().tree_export(self._h, C.byref(ex), _lib.stream_handle()))
+        return out
+
+
+def tree_build(pos, mass, eps=None, box=1.0, tree: Tree | None = None) -> Tree:
+    """Build (or rebuild in place) the tree of the particles (pos: (N, 3) CUDA tensor)."""
+    t = tree if tree is not None else Tree()
+    return t.build(pos, mass, eps=eps, box=box)
+
+
+def _targets(tree: Tree, active):
+    if active is None:
+        return None, tree.n
+    a = torch.as_tensor(active, device=tree.device).to(torch.int32).contiguous()
+    return a, a.shape[0]
+
+
+def shortrange_accel(tree: Tree, params: dict, active=None, a_old=None, counts: bool = True):
+    """Short-range accelerations of all particles, or of `active` (input indices)."""
+    prec = params.get("precision", "fp64")
+    act, n_t = _targets(tree, active)
+    dt = torch.float32 if prec == "fp32" else torch.float64
+    acc = torch.empty((n_t, 3), dtype=dt, device=tree.device)
+    cnt = torch.empty((n_t, 2), dtype=torch.int32, device=tree.device) if counts else None
+    ao = None if a_old is None else _dev_f64(torch.as_tensor(a_old, device=tree.device), name="a_old")
+    p = _lib.make_params(params)
+    with torch.cuda.device(tree.device):
+        _lib.check(_lib.lib().shortrange_accel(tree._h, C.byref(p), _lib.ptr(act), n_t, _lib.ptr(ao),
+                                               _lib.ptr(acc), _lib.ptr(cnt), _lib.stream_handle()))
+    return acc, cnt
+
+
+def shortrange_accel_adjoint(tree: Tree, params: dict, w, active=None, a_old=None):
+    """dL/dx (N, 3) and dL/dm (N) of L = sum_t w_t . a_t, decisions as in the forward."""
+    prec = params.get("precision", "fp64")
+    act, n_t = _targets(tree, active)
+    dt = torch.float32 if prec == "fp32" else torch.float64
+    w = torch.as_tensor(w, device=tree.device).to(dt).contiguous()
+    if w.shape != (n_t, 3):
+        raise ValueError(f"w must have shape ({n_t}, 3)")
+    dx = torch.empty((tree.n, 3), dtype=torch.float64, device=tree.device)
+    dm = torch.empty(tree.n, dtype=torch.float64, device=tree.device)
+    ao = None if a_old is None else _dev_f64(torch.as_tensor(a_old, device=tree.device), name="a_old")
+    p = _lib.make_params(params)
+    with torch.cuda.device(tree.device):
+        _lib.check(_lib.lib().shortrange_accel_adjoint(tree._h, C.byref(p), _lib.ptr(act), n_t,
+                                                       _lib.ptr(ao), _lib.ptr(w), _lib.ptr(dx),
+                                                       _lib.ptr(dm), _lib.stream_handle()))
+    return dx, dm
+
+
+class ShortRangeAccel(torch.autograd.Function):
+    """Differentiable short-range acceleration a(pos, mass).
+
+    The backward re-walks the tree built in the forward (kept on the context),
+    so topology, opening decisions and cutoff membership are those of the
+    forward pass.
+    """
+
+    @staticmethod
+    def forward(ctx, pos, mass, eps, params, box=1.0, active=None, a_old=None):
+        tree = tree_build(pos, mass, eps=eps, box=box)
+        acc, _ = shortrange_accel(tree, params, active=active, a_old=a_old, counts=False)
+        ctx.tree, ctx.params, ctx.active, ctx.a_old = tree, params, active, a_old
+        ctx.pos_dtype, ctx.mass_dtype = pos.dtype, torch.as_tensor(mass).dtype
+        return acc
+
+    @staticmethod
+    def backward(ctx, grad):
+        dx, dm = shortrange_accel_adjoint(ctx.tree, ctx.params, grad.contiguous(), active=ctx.active,
+                                          a_old=ctx.a_old)
+        return dx.to(ctx.pos_dtype), dm.to(ctx.mass_dtype), None, None, None, None, None
+
+
+def kdk_rollout(*args, **kwargs):
+    from .rollout import kdk_rollout as _k
+    return _k(*args, **kwargs)

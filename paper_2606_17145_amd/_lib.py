@@ -1,0 +1,87 @@
+"""ctypes binding of libsrgrav.so: argument marshalling only.
+
+Every step of the computation runs in the HIP library; this module converts
+torch tensors to device pointers and C structs and turns error codes into
+exceptions.  There is no fallback: if the library is missing, every call
+raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libsrgrav.so")
+
+SR_OPEN_BH, SR_OPEN_RELATIVE = 0, 1
+SR_FP64, SR_FP32, SR_FP32_ACC64 = 0, 1, 2
+PRECISIONS = {"fp64": SR_FP64, "fp32": SR_FP32, "fp32_acc64": SR_FP32_ACC64}
+CRITERIA = {"bh": SR_OPEN_BH, "relative": SR_OPEN_RELATIVE}
+EXPORTED = ("tree_build", "shortrange_accel", "shortrange_accel_adjoint", "tree_node_count",
+            "tree_export", "tree_free", "srgrav_last_error")
+
+
+class SrgravError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"srgrav error {code}: {msg}")
+        self.code = code
+
+
+class SrParams(C.Structure):
+    _fields_ = [("G", C.c_double), ("r_s", C.c_double), ("r_cut", C.c_double),
+                ("criterion", C.c_int32), ("theta", C.c_double), ("alpha", C.c_double),
+                ("precision", C.c_int32)]
+
+
+class SrTreeExport(C.Structure):
+    _fields_ = [(name, C.c_void_p) for name in
+                ("key_hi", "key_lo", "perm", "level", "first", "count", "parent", "skip", "corner",
+                 "M", "com", "M32", "comX")]
+
+
+_lib = None
+
+
+def lib():
+    """Load libsrgrav.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = C.CDLL(LIB_PATH)
+        vp, i64, d = C.c_void_p, C.c_int64, C.c_double
+        L.tree_build.argtypes = [vp, vp, vp, d, i64, d, C.c_int32, vp, C.POINTER(vp)]
+        L.shortrange_accel.argtypes = [vp, C.POINTER(SrParams), vp, i64, vp, vp, vp, vp]
+        L.shortrange_accel_adjoint.argtypes = [vp, C.POINTER(SrParams), vp, i64, vp, vp, vp, vp, vp]
+        L.tree_node_count.argtypes = [vp, C.POINTER(i64)]
+        L.tree_export.argtypes = [vp, C.POINTER(SrTreeExport), vp]
+        L.tree_free.argtypes = [vp]
+        L.tree_free.restype = None
+        L.srgrav_last_error.restype = C.c_char_p
+        for name in ("tree_build", "shortrange_accel", "shortrange_accel_adjoint", "tree_node_count",
+                     "tree_export"):
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def check(rc: int):
+    if rc != 0:
+        raise SrgravError(rc, lib().srgrav_last_error().decode())
+
+
+def ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def stream_handle():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def make_params(params: dict) -> SrParams:
+    return SrParams(float(params.get("G", 1.0)), float(params["r_s"]), float(params["r_cut"]),
+                    CRITERIA[params.get("criterion", "bh")], float(params.get("theta", 0.5)),
+                    float(params.get("alpha", 0.0)), PRECISIONS[params.get("precision", "fp64")])

@@ -1,0 +1,315 @@
+// C ABI of the short-range gravity library: argument checks, handle and
+// workspace management, and the calls into the build and walk launchers.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+
+#include "internal.h"
+
+namespace {
+thread_local char g_err[512] = "";
+
+template <class T>
+int alloc(T** p, int64_t count)
+{
+    *p = nullptr;
+    if (count <= 0) count = 1;
+    hipError_t e = hipMalloc((void**)p, sizeof(T) * (size_t)count);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return sr_fail(SR_ENOMEM, "hipMalloc of %lld bytes failed: %s", (long long)(sizeof(T) * count),
+                       hipGetErrorString(e));
+    }
+    return SR_OK;
+}
+
+template <class T>
+void release(T*& p)
+{
+    if (p) (void)hipFree((void*)p);
+    p = nullptr;
+}
+
+void free_workspace(sr_tree* t)
+{
+    for (int k = 0; k < 2; ++k) {
+        release(t->khi[k]);
+        release(t->klo[k]);
+        release(t->kidx[k]);
+    }
+    release(t->hist);
+    release(t->scan_tmp);
+    release(t->levelmask);
+    release(t->ucount);
+    release(t->base);
+    release(t->b_lo);
+    release(t->b_hi);
+    release(t->b_lambda);
+    release(t->b_parent);
+    release(t->b_pre);
+    release(t->leaf_bparent);
+    release(t->status);
+    release(t->depth_order);
+    release(t->depth_cursor);
+    release(t->perm);
+    release(t->invperm);
+    release(t->pparent);
+    release(t->prec64);
+    release(t->ph64);
+    release(t->prec32);
+    release(t->ph32);
+    release(t->n_level);
+    release(t->n_first);
+    release(t->n_count);
+    release(t->n_parent);
+    release(t->n_skip);
+    release(t->n_depth);
+    release(t->n_corner);
+    release(t->nrec64);
+    release(t->nS);
+    release(t->ngeo64);
+    release(t->nhmax);
+    release(t->nhmin);
+    release(t->nrec32);
+    release(t->nhmax32);
+    release(t->items);
+    release(t->tgt_sorted);
+    release(t->tgt_slot);
+    release(t->mark);
+    release(t->tgt_flag);
+    release(t->tgt_pos);
+    release(t->pbar);
+    release(t->tbar);
+    release(t->nbar);
+    t->cap = 0;
+}
+
+int allocate_workspace(sr_tree* t, int64_t cap)
+{
+    const int64_t nb_rs = (cap + 2047) / 2048;           // radix-sort tiles
+    const int64_t hist = 256 * nb_rs + 1;
+    const int64_t scan_tiles = (hist > cap + 1 ? hist : cap + 1) / 2048 + 2;
+    const int64_t nodes = cap > 1 ? cap - 1 : 1;
+    int rc = SR_OK;
+#define A(ptr, count)                     \
+    if ((rc = alloc(&(ptr), (count))) != SR_OK) { \
+        free_workspace(t);                \
+        return rc;                        \
+    }
+    for (int k = 0; k < 2; ++k) {
+        A(t->khi[k], cap);
+        A(t->klo[k], cap);
+        A(t->kidx[k], cap);
+    }
+    A(t->hist, hist);
+    A(t->scan_tmp, scan_tiles + 1);
+    A(t->levelmask, cap);
+    A(t->ucount, cap);
+    A(t->base, cap + 1);
+    A(t->b_lo, nodes);
+    A(t->b_hi, nodes);
+    A(t->b_lambda, nodes);
+    A(t->b_parent, nodes);
+    A(t->b_pre, nodes);
+    A(t->leaf_bparent, cap);
+    A(t->status, ST_WORDS);
+    A(t->depth_order, nodes);
+    A(t->depth_cursor, SR_MAX_DEPTH);
+    A(t->perm, cap);
+    A(t->invperm, cap);
+    A(t->pparent, cap);
+    A(t->prec64, cap);
+    A(t->ph64, cap);
+    A(t->prec32, cap);
+    A(t->ph32, cap);
+    A(t->n_level, nodes);
+    A(t->n_first, nodes);
+    A(t->n_count, nodes);
+    A(t->n_parent, nodes);
+    A(t->n_skip, nodes);
+    A(t->n_depth, nodes);
+    A(t->n_corner, 3 * nodes);
+    A(t->nrec64, nodes);
+    A(t->nS, 3 * nodes);
+    A(t->ngeo64, nodes);
+    A(t->nhmax, nodes);
+    A(t->nhmin, nodes);
+    A(t->nrec32, nodes);
+    A(t->nhmax32, nodes);
+    A(t->items, 2 * cap);
+    A(t->tgt_sorted, cap);
+    A(t->tgt_slot, cap);
+    A(t->mark, cap);
+    A(t->tgt_flag, cap);
+    A(t->tgt_pos, cap + 1);
+    A(t->pbar, 4 * cap);
+    A(t->tbar, 3 * cap);
+    A(t->nbar, 4 * nodes);
+#undef A
+    t->cap = cap;
+    return SR_OK;
+}
+
+int check_params(const sr_tree* t, const sr_params* p)
+{
+    if (!p) return sr_fail(SR_EINVAL, "params is NULL");
+    if (!(isfinite(p->G) && isfinite(p->r_s) && p->r_s > 0.0))
+        return sr_fail(SR_EINVAL, "G must be finite and r_s > 0");
+    if (!(p->r_cut > 0.0 && p->r_cut < 0.5 * t->box))
+        return sr_fail(SR_EINVAL, "r_cut must satisfy 0 < r_cut < box / 2 (got %g, box %g)", p->r_cut, t->box);
+    if (!(p->theta >= 0.0 && isfinite(p->theta))) return sr_fail(SR_EINVAL, "theta must be finite and >= 0");
+    if (p->criterion != SR_OPEN_BH && p->criterion != SR_OPEN_RELATIVE)
+        return sr_fail(SR_EINVAL, "unknown opening criterion %d", p->criterion);
+    if (p->criterion == SR_OPEN_RELATIVE && !(p->alpha >= 0.0 && isfinite(p->alpha)))
+        return sr_fail(SR_EINVAL, "alpha must be finite and >= 0");
+    if (p->precision != SR_FP64 && p->precision != SR_FP32 && p->precision != SR_FP32_ACC64)
+        return sr_fail(SR_EINVAL, "unknown precision %d", p->precision);
+    return SR_OK;
+}
+
+int check_call(sr_tree* t, const sr_params* p, const int32_t* active, int64_t n_active, const double* a_old)
+{
+    if (!t || t->n <= 0) return sr_fail(SR_ESTATE, "tree handle is NULL or was never built");
+    int rc = check_params(t, p);
+    if (rc) return rc;
+    if (!active && n_active != t->n)
+        return sr_fail(SR_EINVAL, "n_active (%lld) must equal n (%lld) when active is NULL", (long long)n_active,
+                       (long long)t->n);
+    if (active && (n_active < 0 || n_active > t->n))
+        return sr_fail(SR_EINVAL, "n_active must lie in [0, n]");
+    if (p->criterion == SR_OPEN_RELATIVE && !a_old) return sr_fail(SR_EINVAL, "relative criterion needs a_old");
+    return SR_OK;
+}
+}  // namespace
+
+int sr_fail(int code, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+extern "C" {
+
+const char* srgrav_last_error(void) { return g_err; }
+
+int tree_build(const double* pos, const double* mass, const double* eps, double eps_scalar, int64_t n, double box,
+               int32_t leaf_size, void* stream, sr_tree** tree)
+{
+    g_err[0] = 0;
+    if (!tree) return sr_fail(SR_EINVAL, "tree out-pointer is NULL");
+    if (!pos || !mass) return sr_fail(SR_EINVAL, "pos and mass are required");
+    if (n < 1 || n > SR_N_MAX) return sr_fail(SR_EINVAL, "n must lie in [1, 2^30] (got %lld)", (long long)n);
+    if (!(box > 0.0 && isfinite(box))) return sr_fail(SR_EINVAL, "box must be finite and > 0");
+    if (leaf_size != 1) return sr_fail(SR_EUNSUPPORTED, "only leaf_size == 1 is supported");
+    if (!eps && !(eps_scalar > 0.0 && isfinite(eps_scalar)))
+        return sr_fail(SR_EINVAL, "eps_scalar must be finite and > 0 when eps is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    sr_tree* t = *tree;
+    bool fresh = false;
+    if (!t) {
+        t = new (std::nothrow) sr_tree();
+        if (!t) return sr_fail(SR_ENOMEM, "host allocation of the handle failed");
+        fresh = true;
+        SR_HIP(hipGetDevice(&t->device));
+    }
+    if (n > t->cap) {
+        // wait for in-flight work on the old workspace before releasing it
+        if (!fresh) SR_HIP(hipStreamSynchronize(st));
+        free_workspace(t);
+        int rc = allocate_workspace(t, n);
+        if (rc) {
+            if (fresh) delete t;
+            return rc;
+        }
+    }
+    t->n = n;
+    t->box = box;
+    int rc = sr_build_device(t, pos, mass, eps, eps_scalar, st);
+    if (rc) {
+        t->n = 0;
+        if (fresh) {
+            free_workspace(t);
+            delete t;
+        }
+        return rc;
+    }
+    *tree = t;
+    return SR_OK;
+}
+
+int shortrange_accel(sr_tree* t, const sr_params* p, const int32_t* active, int64_t n_active, const double* a_old,
+                     void* acc, int32_t* counts, void* stream)
+{
+    g_err[0] = 0;
+    int rc = check_call(t, p, active, n_active, a_old);
+    if (rc) return rc;
+    if (!acc) return sr_fail(SR_EINVAL, "acc is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    if ((rc = sr_prepare_targets(t, active, n_active, st))) return rc;
+    return sr_walk_forward(t, p, n_active, a_old, acc, counts, st);
+}
+
+int shortrange_accel_adjoint(sr_tree* t, const sr_params* p, const int32_t* active, int64_t n_active,
+                             const double* a_old, const void* w, double* dLdx, double* dLdm, void* stream)
+{
+    g_err[0] = 0;
+    int rc = check_call(t, p, active, n_active, a_old);
+    if (rc) return rc;
+    if (!w || !dLdx || !dLdm) return sr_fail(SR_EINVAL, "w, dLdx and dLdm are required");
+    hipStream_t st = (hipStream_t)stream;
+    if ((rc = sr_prepare_targets(t, active, n_active, st))) return rc;
+    return sr_walk_adjoint(t, p, n_active, a_old, w, dLdx, dLdm, st);
+}
+
+int tree_node_count(const sr_tree* t, int64_t* n_nodes)
+{
+    if (!t || t->n <= 0) return sr_fail(SR_ESTATE, "tree handle is NULL or was never built");
+    if (!n_nodes) return sr_fail(SR_EINVAL, "n_nodes is NULL");
+    *n_nodes = t->n_nodes;
+    return SR_OK;
+}
+
+int tree_export(const sr_tree* t, const sr_tree_export* ex, void* stream)
+{
+    if (!t || t->n <= 0) return sr_fail(SR_ESTATE, "tree handle is NULL or was never built");
+    if (!ex) return sr_fail(SR_EINVAL, "export record is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t n = t->n, m = t->n_nodes;
+    auto cp = [&](void* dst, const void* src, size_t bytes) -> int {
+        if (dst && bytes) SR_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st));
+        return SR_OK;
+    };
+    int rc = SR_OK;
+    if ((rc = cp(ex->key_hi, t->khi[0], 8 * n)) || (rc = cp(ex->key_lo, t->klo[0], 8 * n)) ||
+        (rc = cp(ex->perm, t->perm, 4 * n)) || (rc = cp(ex->level, t->n_level, 4 * m)) ||
+        (rc = cp(ex->first, t->n_first, 4 * m)) || (rc = cp(ex->count, t->n_count, 4 * m)) ||
+        (rc = cp(ex->parent, t->n_parent, 4 * m)) || (rc = cp(ex->skip, t->n_skip, 4 * m)) ||
+        (rc = cp(ex->corner, t->n_corner, 12 * m)))
+        return rc;
+    if (m && (ex->M || ex->com || ex->M32 || ex->comX)) {
+        // strided fields: copy through a 2D copy of the records
+        if (ex->M) SR_HIP(hipMemcpy2DAsync(ex->M, 8, &t->nrec64[0].m, sizeof(Rec64), 8, m, hipMemcpyDeviceToDevice, st));
+        if (ex->com) SR_HIP(hipMemcpy2DAsync(ex->com, 24, t->nrec64, sizeof(Rec64), 24, m, hipMemcpyDeviceToDevice, st));
+        if (ex->M32) SR_HIP(hipMemcpy2DAsync(ex->M32, 4, &t->nrec32[0].m, sizeof(Rec32), 4, m, hipMemcpyDeviceToDevice, st));
+        if (ex->comX) SR_HIP(hipMemcpy2DAsync(ex->comX, 12, t->nrec32, sizeof(Rec32), 12, m, hipMemcpyDeviceToDevice, st));
+    }
+    return SR_OK;
+}
+
+void tree_free(sr_tree* t)
+{
+    if (!t) return;
+    (void)hipDeviceSynchronize();
+    free_workspace(t);
+    delete t;
+}
+
+}  // extern "C"

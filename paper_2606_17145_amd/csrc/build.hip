@@ -1,0 +1,615 @@
+// Tree build on the device: wrap + quantise + Morton keys, LDS radix sort,
+// compressed octree topology, pre-order numbering, FP64 node moments.
+//
+// All integer steps are exact, and the FP64 moment fold follows the fixed
+// child order with no fused multiply-add (the file is compiled with
+// -ffp-contract=off), so the result is reproducible bit for bit.
+#include <stdarg.h>
+#include <stdio.h>
+
+#include "internal.h"
+
+namespace {
+
+constexpr int TPB = 256;                 // threads per block for elementwise kernels
+constexpr int RS_ITEMS = 8;              // keys per thread in the radix sort
+constexpr int RS_TILE = TPB * RS_ITEMS;  // keys per block
+constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_TILE = TPB * SCAN_ITEMS;
+constexpr double TWO32 = 4294967296.0;
+
+__host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ------------------------------------------------------------------------------------
+// wrap, quantise, key
+// ------------------------------------------------------------------------------------
+
+// u = x/L - floor(x/L) in [0, 1) (a rounding to 1 maps to 0), X = floor(u 2^32).
+__device__ inline double wrap_unit(double x, double box)
+{
+    double u = x / box;
+    u = u - floor(u);
+    if (u >= 1.0) u = 0.0;
+    return u;
+}
+
+// Spread the low 15 bits of v to every third bit (bit b -> bit 3b).
+__device__ inline uint64_t spread3(uint64_t v)
+{
+    v &= 0x1fffffull;
+    v = (v | (v << 32)) & 0x1f00000000ffffull;
+    v = (v | (v << 16)) & 0x1f0000ff0000ffull;
+    v = (v | (v << 8)) & 0x100f00f00f00f00full;
+    v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+    v = (v | (v << 2)) & 0x1249249249249249ull;
+    return v;
+}
+
+__global__ void k_keys(const double* __restrict__ pos, const double* __restrict__ mass,
+                       const double* __restrict__ eps, double eps_scalar, int64_t n, double box,
+                       uint64_t* __restrict__ khi, uint64_t* __restrict__ klo,
+                       uint32_t* __restrict__ kidx, int32_t* __restrict__ status)
+{
+    int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x;
+    if (i >= n) return;
+    bool bad = false;
+    uint32_t c[3];
+    for (int k = 0; k < 3; ++k) {
+        double x = pos[3 * i + k];
+        if (!isfinite(x)) bad = true;
+        double u = isfinite(x) ? wrap_unit(x, box) : 0.0;
+        c[k] = ((uint32_t)floor(u * TWO32)) >> 2;   // 30-bit coordinate
+    }
+    double m = mass[i];
+    double e = eps ? eps[i] : eps_scalar;
+    if (!(isfinite(m) && m > 0.0) || !(isfinite(e) && e > 0.0)) bad = true;
+    if (bad) atomicOr(&status[ST_FLAGS], 1);
+    // digits 1..15 from coordinate bits 29..15, digits 16..30 from bits 14..0; x-major
+    khi[i] = (spread3(c[0] >> 15) << 2) | (spread3(c[1] >> 15) << 1) | spread3(c[2] >> 15);
+    klo[i] = (spread3(c[0] & 0x7fffu) << 2) | (spread3(c[1] & 0x7fffu) << 1) | spread3(c[2] & 0x7fffu);
+    kidx[i] = (uint32_t)i;
+}
+
+// ------------------------------------------------------------------------------------
+// exclusive scan of uint32 (three kernels: tile sums, scan of sums, tile scans)
+// ------------------------------------------------------------------------------------
+
+__device__ inline uint32_t wave_inclusive_scan(uint32_t v)
+{
+    const int lane = threadIdx.x & 63;
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(v, o, 64);
+        if (lane >= o) v += y;
+    }
+    return v;
+}
+
+// Block-wide exclusive scan of one value per thread (TPB threads); returns the
+// exclusive prefix and the block total.
+__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* total)
+{
+    __shared__ uint32_t s_w[TPB / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t inc = wave_inclusive_scan(v);
+    if (lane == 63) s_w[w] = inc;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+    for (int k = 0; k < TPB / 64; ++k) {
+        if (k < w) off += s_w[k];
+        tot += s_w[k];
+    }
+    __syncthreads();
+    *total = tot;
+    return off + inc - v;
+}
+
+__global__ void k_scan_sums(const uint32_t* __restrict__ in, int64_t n, uint32_t* __restrict__ sums)
+{
+    int64_t base = blockIdx.x * (int64_t)SCAN_TILE;
+    uint32_t acc = 0;
+    for (int r = 0; r < SCAN_ITEMS; ++r) {
+        int64_t i = base + (int64_t)threadIdx.x * SCAN_ITEMS + r;
+        if (i < n) acc += in[i];
+    }
+    uint32_t tot;
+    block_exclusive_scan(acc, &tot);
+    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+// One block scans all tile sums in place (exclusive).
+__global__ void k_scan_top(uint32_t* __restrict__ sums, int64_t nb)
+{
+    __shared__ uint32_t s_carry;
+    if (threadIdx.x == 0) s_carry = 0;
+    __syncthreads();
+    for (int64_t b0 = 0; b0 < nb; b0 += TPB) {
+        int64_t i = b0 + threadIdx.x;
+        uint32_t v = i < nb ? sums[i] : 0;
+        uint32_t tot;
+        uint32_t ex = block_exclusive_scan(v, &tot);
+        uint32_t carry = s_carry;
+        if (i < nb) sums[i] = carry + ex;
+        __syncthreads();
+        if (threadIdx.x == 0) s_carry = carry + tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sums[nb] = s_carry;
+}
+
+__global__ void k_scan_tiles(const uint32_t* __restrict__ in, uint32_t* __restrict__ out, int64_t n,
+                             const uint32_t* __restrict__ sums)
+{
+    int64_t base = blockIdx.x * (int64_t)SCAN_TILE;
+    uint32_t v[SCAN_ITEMS];
+    uint32_t acc = 0;
+    for (int r = 0; r < SCAN_ITEMS; ++r) {
+        int64_t i = base + (int64_t)threadIdx.x * SCAN_ITEMS + r;
+        v[r] = i < n ? in[i] : 0;
+        acc += v[r];
+    }
+    uint32_t tot;
+    uint32_t off = block_exclusive_scan(acc, &tot) + sums[blockIdx.x];
+    for (int r = 0; r < SCAN_ITEMS; ++r) {
+        int64_t i = base + (int64_t)threadIdx.x * SCAN_ITEMS + r;
+        if (i < n) out[i] = off;
+        off += v[r];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == TPB - 1) out[n] = off;
+}
+
+// ------------------------------------------------------------------------------------
+// LSD radix sort of 90-bit keys (two 45-bit words) with the original index as payload
+// ------------------------------------------------------------------------------------
+
+__device__ inline uint32_t rs_digit(uint64_t hi, uint64_t lo, int pass)
+{
+    return pass < 6 ? (uint32_t)(lo >> (8 * pass)) & 0xffu : (uint32_t)(hi >> (8 * (pass - 6))) & 0xffu;
+}
+
+__global__ void k_rs_hist(const uint64_t* __restrict__ hi, const uint64_t* __restrict__ lo, int64_t n,
+                          int pass, uint32_t* __restrict__ hist, int64_t nb)
+{
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t base = blockIdx.x * (int64_t)RS_TILE;
+    for (int r = 0; r < RS_ITEMS; ++r) {
+        int64_t i = base + r * TPB + threadIdx.x;
+        if (i < n) atomicAdd(&h[rs_digit(hi[i], lo[i], pass)], 1u);
+    }
+    __syncthreads();
+    hist[threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+}
+
+// Stable scatter: within a tile, keys keep their order (rounds in order, waves
+// in order, lanes in order); tiles take their offsets from the digit-major scan.
+__global__ void k_rs_scatter(const uint64_t* __restrict__ hi, const uint64_t* __restrict__ lo,
+                             const uint32_t* __restrict__ idx, uint64_t* __restrict__ ohi,
+                             uint64_t* __restrict__ olo, uint32_t* __restrict__ oidx, int64_t n,
+                             int pass, const uint32_t* __restrict__ offs, int64_t nb)
+{
+    __shared__ uint32_t s_off[256];
+    __shared__ uint32_t s_w[TPB / 64][256];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    s_off[threadIdx.x] = offs[threadIdx.x * nb + blockIdx.x];
+    const uint64_t lt = (1ull << lane) - 1ull;
+    int64_t base = blockIdx.x * (int64_t)RS_TILE;
+    for (int r = 0; r < RS_ITEMS; ++r) {
+        int64_t i = base + r * TPB + threadIdx.x;
+        bool valid = i < n;
+        uint64_t h = 0, l = 0;
+        uint32_t v = 0, d = 0;
+        if (valid) {
+            h = hi[i];
+            l = lo[i];
+            v = idx[i];
+            d = rs_digit(h, l, pass);
+        }
+        uint64_t peers = __ballot(valid);
+        for (int b = 0; b < 8; ++b) {
+            uint64_t bits = __ballot(valid && ((d >> b) & 1u));
+            peers &= ((d >> b) & 1u) ? bits : ~bits;
+        }
+        uint32_t rank = (uint32_t)__popcll(peers & lt);
+        for (int k = 0; k < 4; ++k) s_w[w][lane * 4 + k] = 0;
+        __syncthreads();
+        if (valid && rank == 0) s_w[w][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        uint32_t p = 0;
+        if (valid) {
+            p = s_off[d] + rank;
+            for (int k = 0; k < w; ++k) p += s_w[k][d];
+        }
+        __syncthreads();
+        uint32_t add = 0;
+        for (int k = 0; k < TPB / 64; ++k) add += s_w[k][threadIdx.x];
+        s_off[threadIdx.x] += add;
+        __syncthreads();
+        if (valid) {
+            ohi[p] = h;
+            olo[p] = l;
+            oidx[p] = v;
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// sorted records
+// ------------------------------------------------------------------------------------
+
+__global__ void k_gather(const double* __restrict__ pos, const double* __restrict__ mass,
+                         const double* __restrict__ eps, double eps_scalar, int64_t n, double box,
+                         const uint32_t* __restrict__ sidx, int32_t* __restrict__ perm,
+                         int32_t* __restrict__ invperm, Rec64* __restrict__ r64,
+                         double* __restrict__ h64, Rec32* __restrict__ r32, float* __restrict__ h32)
+{
+    int64_t s = blockIdx.x * (int64_t)TPB + threadIdx.x;
+    if (s >= n) return;
+    uint32_t i = sidx[s];
+    perm[s] = (int32_t)i;
+    invperm[i] = (int32_t)s;
+    double u[3];
+    uint32_t X[3];
+    for (int k = 0; k < 3; ++k) {
+        u[k] = wrap_unit(pos[3 * i + k], box);
+        X[k] = (uint32_t)floor(u[k] * TWO32);
+    }
+    double m = mass[i];
+    double h = 2.8 * (eps ? eps[i] : eps_scalar);
+    r64[s] = Rec64{u[0] * box, u[1] * box, u[2] * box, m};
+    h64[s] = h;
+    r32[s] = Rec32{X[0], X[1], X[2], (float)m};
+    h32[s] = (float)(h / box * TWO32);
+}
+
+// ------------------------------------------------------------------------------------
+// topology: binary radix tree of the keys (index-augmented), then its octree nodes
+// ------------------------------------------------------------------------------------
+
+// Common-prefix length in bits of sorted keys a and b, ties broken by position
+// (90 + leading equal bits of the positions); -1 outside [0, n).
+__device__ inline int delta(const uint64_t* __restrict__ hi, const uint64_t* __restrict__ lo,
+                            int64_t n, int64_t a, int64_t b)
+{
+    if (b < 0 || b >= n) return -1;
+    uint64_t x = hi[a] ^ hi[b];
+    if (x) return __clzll(x) - 19;
+    x = lo[a] ^ lo[b];
+    if (x) return 45 + __clzll(x) - 19;
+    return 90 + __clz((uint32_t)a ^ (uint32_t)b);
+}
+
+__device__ inline int level_of(int lambda) { return (lambda < 90 ? lambda : 90) / 3; }
+
+__global__ void k_radix_tree(const uint64_t* __restrict__ hi, const uint64_t* __restrict__ lo,
+                             int64_t n, int32_t* __restrict__ b_lo, int32_t* __restrict__ b_hi,
+                             int32_t* __restrict__ b_lambda, int32_t* __restrict__ b_parent,
+                             int32_t* __restrict__ leaf_bparent)
+{
+    int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x;
+    if (i >= n - 1) return;
+    int d = delta(hi, lo, n, i, i + 1) - delta(hi, lo, n, i, i - 1) > 0 ? 1 : -1;
+    int dmin = delta(hi, lo, n, i, i - d);
+    int64_t lmax = 2;
+    while (delta(hi, lo, n, i, i + lmax * d) > dmin) lmax <<= 1;
+    int64_t l = 0;
+    for (int64_t t = lmax >> 1; t >= 1; t >>= 1)
+        if (delta(hi, lo, n, i, i + (l + t) * d) > dmin) l += t;
+    int64_t j = i + l * d;
+    int dnode = delta(hi, lo, n, i, j);
+    int64_t s = 0, t = l;
+    do {
+        t = (t + 1) >> 1;
+        if (delta(hi, lo, n, i, i + (s + t) * d) > dnode) s += t;
+    } while (t > 1);
+    int64_t g = i + s * d + (d < 0 ? -1 : 0);
+    int64_t a = i < j ? i : j, b = i < j ? j : i;
+    b_lo[i] = (int32_t)a;
+    b_hi[i] = (int32_t)b;
+    b_lambda[i] = dnode;
+    if (a == g) leaf_bparent[g] = (int32_t)i;
+    else b_parent[g] = (int32_t)i;
+    if (b == g + 1) leaf_bparent[g + 1] = (int32_t)i;
+    else b_parent[g + 1] = (int32_t)i;
+    if (i == 0) b_parent[0] = -1;
+}
+
+// A binary node is an octree node when it is the root or its octree level is
+// deeper than its binary parent's: it is then the whole of its octree cell.
+__global__ void k_octree_flags(int64_t n, const int32_t* __restrict__ b_lo,
+                               const int32_t* __restrict__ b_lambda, const int32_t* __restrict__ b_parent,
+                               uint32_t* __restrict__ levelmask, int32_t* __restrict__ b_pre)
+{
+    int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x;
+    if (i >= n - 1) return;
+    int lev = level_of(b_lambda[i]);
+    bool oct = i == 0 || lev > level_of(b_lambda[b_parent[i]]);
+    b_pre[i] = oct ? 0 : -1;
+    if (oct) atomicOr(&levelmask[b_lo[i]], 1u << lev);
+}
+
+__global__ void k_popcount(const uint32_t* __restrict__ mask, int64_t n, uint32_t* __restrict__ cnt)
+{
+    int64_t s = blockIdx.x * (int64_t)TPB + threadIdx.x;
+    if (s < n) cnt[s] = (uint32_t)__popc(mask[s]);
+}
+
+// Pre-order = order by (first, level): all nodes that start before `first`, plus
+// the enclosing nodes that start at `first` with a smaller level.
+__global__ void k_preorder(int64_t n, const int32_t* __restrict__ b_lo, const int32_t* __restrict__ b_lambda,
+                           const uint32_t* __restrict__ levelmask, const int32_t* __restrict__ base,
+                           int32_t* __restrict__ b_pre)
+{
+    int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x;
+    if (i >= n - 1 || b_pre[i] < 0) return;
+    int lev = level_of(b_lambda[i]);
+    int32_t f = b_lo[i];
+    b_pre[i] = base[f] + __popc(levelmask[f] & ((1u << lev) - 1u));
+}
+
+__global__ void k_node_arrays(int64_t n, const int32_t* __restrict__ b_lo, const int32_t* __restrict__ b_hi,
+                              const int32_t* __restrict__ b_lambda, const int32_t* __restrict__ b_parent,
+                              const int32_t* __restrict__ b_pre, const int32_t* __restrict__ base,
+                              const Rec32* __restrict__ r32, int32_t* __restrict__ n_level,
+                              int32_t* __restrict__ n_first, int32_t* __restrict__ n_count,
+                              int32_t* __restrict__ n_parent, int32_t* __restrict__ n_skip,
+                              uint32_t* __restrict__ n_corner)
+{
+    int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x;
+    if (i >= n - 1) return;
+    int32_t pre = b_pre[i];
+    if (pre < 0) return;
+    int lev = level_of(b_lambda[i]);
+    int32_t f = b_lo[i], c = b_hi[i] - b_lo[i] + 1;
+    int32_t p = b_parent[i];
+    while (p >= 0 && b_pre[p] < 0) p = b_parent[p];
+    n_level[pre] = lev;
+    n_first[pre] = f;
+    n_count[pre] = c;
+    n_parent[pre] = p >= 0 ? b_pre[p] : -1;
+    n_skip[pre] = base[f + c];
+    uint64_t keep = lev == 0 ? 0ull : (~((1ull << (32 - lev)) - 1ull)) & 0xffffffffull;
+    Rec32 q = r32[f];
+    n_corner[3 * pre + 0] = (uint32_t)(q.X & keep);
+    n_corner[3 * pre + 1] = (uint32_t)(q.Y & keep);
+    n_corner[3 * pre + 2] = (uint32_t)(q.Z & keep);
+}
+
+__global__ void k_node_depth(int64_t m, const int32_t* __restrict__ n_parent, const int32_t* __restrict__ n_first,
+                             const int32_t* __restrict__ n_count, const int32_t* __restrict__ base,
+                             int32_t* __restrict__ n_depth, Item* __restrict__ items,
+                             int32_t* __restrict__ status)
+{
+    int64_t nd = blockIdx.x * (int64_t)TPB + threadIdx.x;
+    if (nd >= m) return;
+    int d = 0;
+    for (int32_t p = n_parent[nd]; p >= 0; p = n_parent[p]) ++d;
+    n_depth[nd] = d;
+    int32_t f = n_first[nd], c = n_count[nd];
+    items[f + nd] = Item{(uint32_t)nd, (uint32_t)(f + c + base[f + c]), (uint32_t)d, 0u};
+    atomicMax(&status[ST_MAXDEPTH], d);
+    atomicAdd(&status[ST_HIST + (d < SR_MAX_DEPTH ? d : SR_MAX_DEPTH - 1)], 1);
+}
+
+__global__ void k_particle_items(int64_t n, const int32_t* __restrict__ leaf_bparent,
+                                 const int32_t* __restrict__ b_parent, const int32_t* __restrict__ b_pre,
+                                 const int32_t* __restrict__ base, const int32_t* __restrict__ n_depth,
+                                 int32_t* __restrict__ pparent, Item* __restrict__ items)
+{
+    int64_t s = blockIdx.x * (int64_t)TPB + threadIdx.x;
+    if (s >= n) return;
+    int32_t pp = -1;
+    uint32_t depth = 0;
+    if (n > 1) {
+        int32_t p = leaf_bparent[s];
+        while (b_pre[p] < 0) p = b_parent[p];
+        pp = b_pre[p];
+        depth = (uint32_t)n_depth[pp] + 1u;
+    }
+    pparent[s] = pp;
+    uint32_t it = (uint32_t)(s + (n > 1 ? base[s + 1] : 0));
+    items[it] = Item{(uint32_t)s | ITEM_PARTICLE, it + 1u, depth, 0u};
+}
+
+// ------------------------------------------------------------------------------------
+// node moments, one depth at a time (deepest first)
+// ------------------------------------------------------------------------------------
+
+__global__ void k_depth_scatter(int64_t m, const int32_t* __restrict__ n_depth,
+                                const int32_t* __restrict__ offsets, int32_t* __restrict__ cursor,
+                                int32_t* __restrict__ order)
+{
+    int64_t nd = blockIdx.x * (int64_t)TPB + threadIdx.x;
+    if (nd >= m) return;
+    int d = n_depth[nd];
+    int slot = atomicAdd(&cursor[d], 1);
+    order[offsets[d] + slot] = (int32_t)nd;
+}
+
+// Fold the children of every node of one depth, left to right in digit order:
+// M <- c1, M <- M + c2, ...; S likewise with a particle contributing m x;
+// COM = S / M.  Also the FP32-path node record and the FP64 decision geometry.
+__global__ void k_moments(const int32_t* __restrict__ order, int64_t count, double box,
+                          const Item* __restrict__ items, const int32_t* __restrict__ n_first,
+                          const int32_t* __restrict__ n_level, const uint32_t* __restrict__ n_corner,
+                          const Rec64* __restrict__ r64, const double* __restrict__ h64,
+                          Rec64* __restrict__ nrec64, double* __restrict__ nS, Geo64* __restrict__ geo,
+                          double* __restrict__ nhmax, double* __restrict__ nhmin,
+                          Rec32* __restrict__ nrec32, float* __restrict__ nhmax32)
+{
+    int64_t t = blockIdx.x * (int64_t)TPB + threadIdx.x;
+    if (t >= count) return;
+    int32_t nd = order[t];
+    uint32_t it = (uint32_t)(n_first[nd] + nd);
+    uint32_t end = items[it].next;
+    double M = 0.0, S0 = 0.0, S1 = 0.0, S2 = 0.0, hx = 0.0, hn = 0.0;
+    bool first = true;
+    for (uint32_t j = it + 1; j < end;) {
+        Item c = items[j];
+        double cm, c0, c1, c2, cx, cn;
+        if (c.ref & ITEM_PARTICLE) {
+            Rec64 p = r64[c.ref & ~ITEM_PARTICLE];
+            cm = p.m;
+            c0 = p.m * p.x;
+            c1 = p.m * p.y;
+            c2 = p.m * p.z;
+            cx = cn = h64[c.ref & ~ITEM_PARTICLE];
+            j += 1;
+        } else {
+            cm = nrec64[c.ref].m;
+            c0 = nS[3 * c.ref + 0];
+            c1 = nS[3 * c.ref + 1];
+            c2 = nS[3 * c.ref + 2];
+            cx = nhmax[c.ref];
+            cn = nhmin[c.ref];
+            j = c.next;
+        }
+        if (first) {
+            M = cm;
+            S0 = c0;
+            S1 = c1;
+            S2 = c2;
+            hx = cx;
+            hn = cn;
+            first = false;
+        } else {
+            M = M + cm;
+            S0 = S0 + c0;
+            S1 = S1 + c1;
+            S2 = S2 + c2;
+            hx = cx > hx ? cx : hx;
+            hn = cn < hn ? cn : hn;
+        }
+    }
+    double com[3] = {S0 / M, S1 / M, S2 / M};
+    nrec64[nd] = Rec64{com[0], com[1], com[2], M};
+    nS[3 * nd + 0] = S0;
+    nS[3 * nd + 1] = S1;
+    nS[3 * nd + 2] = S2;
+    nhmax[nd] = hx;
+    nhmin[nd] = hn;
+    int lev = n_level[nd];
+    double l = ldexp(box, -lev);
+    double half = ldexp(1.0, -lev - 1);
+    geo[nd] = Geo64{box * (ldexp((double)n_corner[3 * nd + 0], -32) + half),
+                    box * (ldexp((double)n_corner[3 * nd + 1], -32) + half),
+                    box * (ldexp((double)n_corner[3 * nd + 2], -32) + half), l};
+    uint32_t q[3];
+    for (int k = 0; k < 3; ++k) q[k] = (uint32_t)(uint64_t)rint(com[k] / box * TWO32);
+    nrec32[nd] = Rec32{q[0], q[1], q[2], (float)M};
+    nhmax32[nd] = (float)(hx / box * TWO32);
+}
+
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v)
+{
+    int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v)
+{
+    int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+inline dim3 grid_for(int64_t n) { return dim3((unsigned)cdiv(n > 0 ? n : 1, TPB)); }
+
+}  // namespace
+
+int sr_scan_exclusive(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* tmp, hipStream_t st)
+{
+    int64_t nb = cdiv(n > 0 ? n : 1, SCAN_TILE);
+    hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)nb), dim3(TPB), 0, st, in, n, tmp);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(TPB), 0, st, tmp, nb);
+    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)nb), dim3(TPB), 0, st, in, out, n, tmp);
+    SR_HIP(hipGetLastError());
+    return SR_OK;
+}
+
+int sr_build_device(sr_tree* t, const double* pos, const double* mass, const double* eps,
+                    double eps_scalar, hipStream_t st)
+{
+    const int64_t n = t->n;
+    const double box = t->box;
+    hipLaunchKernelGGL(k_fill_i32, grid_for(ST_WORDS), dim3(TPB), 0, st, t->status, (int64_t)ST_WORDS, 0);
+    hipLaunchKernelGGL(k_keys, grid_for(n), dim3(TPB), 0, st, pos, mass, eps, eps_scalar, n, box,
+                       t->khi[0], t->klo[0], t->kidx[0], t->status);
+    // 12 passes of 8 bits: lo word bits 0..47, then hi word bits 0..47
+    const int64_t nb = cdiv(n, RS_TILE);
+    int cur = 0;
+    for (int pass = 0; pass < 12; ++pass) {
+        hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nb), dim3(TPB), 0, st, t->khi[cur], t->klo[cur], n, pass,
+                           t->hist, nb);
+        int rc = sr_scan_exclusive(t->hist, t->hist, 256 * nb, t->scan_tmp, st);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nb), dim3(TPB), 0, st, t->khi[cur], t->klo[cur],
+                           t->kidx[cur], t->khi[cur ^ 1], t->klo[cur ^ 1], t->kidx[cur ^ 1], n, pass,
+                           t->hist, nb);
+        cur ^= 1;
+    }
+    // 12 passes leave the sorted keys in buffer 0
+    hipLaunchKernelGGL(k_gather, grid_for(n), dim3(TPB), 0, st, pos, mass, eps, eps_scalar, n, box,
+                       t->kidx[0], t->perm, t->invperm, t->prec64, t->ph64, t->prec32, t->ph32);
+    if (n > 1) {
+        hipLaunchKernelGGL(k_radix_tree, grid_for(n - 1), dim3(TPB), 0, st, t->khi[0], t->klo[0], n, t->b_lo,
+                           t->b_hi, t->b_lambda, t->b_parent, t->leaf_bparent);
+        hipLaunchKernelGGL(k_fill_u32, grid_for(n), dim3(TPB), 0, st, t->levelmask, n, 0u);
+        hipLaunchKernelGGL(k_octree_flags, grid_for(n - 1), dim3(TPB), 0, st, n, t->b_lo, t->b_lambda,
+                           t->b_parent, t->levelmask, t->b_pre);
+        hipLaunchKernelGGL(k_popcount, grid_for(n), dim3(TPB), 0, st, t->levelmask, n, t->ucount);
+        int rc = sr_scan_exclusive(t->ucount, (uint32_t*)t->base, n, t->scan_tmp, st);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_preorder, grid_for(n - 1), dim3(TPB), 0, st, n, t->b_lo, t->b_lambda, t->levelmask,
+                           t->base, t->b_pre);
+        hipLaunchKernelGGL(k_node_arrays, grid_for(n - 1), dim3(TPB), 0, st, n, t->b_lo, t->b_hi, t->b_lambda,
+                           t->b_parent, t->b_pre, t->base, t->prec32, t->n_level, t->n_first, t->n_count,
+                           t->n_parent, t->n_skip, t->n_corner);
+        // the node count is base[n]; read it back with the status words
+        SR_HIP(hipMemcpyAsync(t->status + ST_NODES, t->base + n, sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    }
+    int32_t hstat[ST_WORDS];
+    SR_HIP(hipMemcpyAsync(hstat, t->status, sizeof(hstat), hipMemcpyDeviceToHost, st));
+    SR_HIP(hipStreamSynchronize(st));
+    if (hstat[ST_FLAGS] & 1) return sr_fail(SR_EINVAL, "tree_build: non-finite position or non-positive / non-finite mass or softening");
+    const int64_t m = n > 1 ? hstat[ST_NODES] : 0;
+    t->n_nodes = m;
+    if (m > 0) {
+        hipLaunchKernelGGL(k_fill_i32, grid_for(ST_WORDS), dim3(TPB), 0, st, t->status, (int64_t)ST_WORDS, 0);
+        hipLaunchKernelGGL(k_node_depth, grid_for(m), dim3(TPB), 0, st, m, t->n_parent, t->n_first, t->n_count,
+                           t->base, t->n_depth, t->items, t->status);
+        SR_HIP(hipMemcpyAsync(hstat, t->status, sizeof(hstat), hipMemcpyDeviceToHost, st));
+    }
+    hipLaunchKernelGGL(k_particle_items, grid_for(n), dim3(TPB), 0, st, n, t->leaf_bparent, t->b_parent,
+                       t->b_pre, t->base, t->n_depth, t->pparent, t->items);
+    SR_HIP(hipStreamSynchronize(st));
+    if (m == 0) {
+        t->max_depth = 0;
+        return SR_OK;
+    }
+    t->max_depth = hstat[ST_MAXDEPTH];
+    if (t->max_depth >= SR_MAX_DEPTH) return sr_fail(SR_EUNSUPPORTED, "tree_build: tree deeper than %d", SR_MAX_DEPTH);
+    int32_t offs[SR_MAX_DEPTH];
+    int32_t acc = 0;
+    for (int d = 0; d < SR_MAX_DEPTH; ++d) {
+        t->depth_hist[d] = hstat[ST_HIST + d];
+        offs[d] = acc;
+        acc += hstat[ST_HIST + d];
+    }
+    // offsets go through the status words (free again) to the device
+    SR_HIP(hipMemcpyAsync(t->status, offs, sizeof(offs), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_fill_i32, grid_for(SR_MAX_DEPTH), dim3(TPB), 0, st, t->depth_cursor,
+                       (int64_t)SR_MAX_DEPTH, 0);
+    hipLaunchKernelGGL(k_depth_scatter, grid_for(m), dim3(TPB), 0, st, m, t->n_depth, t->status, t->depth_cursor,
+                       t->depth_order);
+    for (int d = t->max_depth; d >= 0; --d) {
+        int64_t cnt = t->depth_hist[d];
+        if (!cnt) continue;
+        hipLaunchKernelGGL(k_moments, grid_for(cnt), dim3(TPB), 0, st, t->depth_order + offs[d], cnt, box, t->items,
+                           t->n_first, t->n_level, t->n_corner, t->prec64, t->ph64, t->nrec64, t->nS, t->ngeo64,
+                           t->nhmax, t->nhmin, t->nrec32, t->nhmax32);
+    }
+    SR_HIP(hipGetLastError());
+    // the host copy of the offsets must outlive the copy above
+    SR_HIP(hipStreamSynchronize(st));
+    return SR_OK;
+}

@@ -1,0 +1,131 @@
+// Internal data layout of the short-range gravity library (device side and handle).
+//
+// Particle data live in Morton order ("sorted position" s); nodes of the
+// compressed octree live in pre-order.  The walk reads a single combined
+// pre-order "item" sequence in which every internal node is followed by its
+// children -- particles and nodes interleaved in digit order -- so that one
+// forward scan with skip pointers visits exactly what a depth-first walk
+// visits.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "srgrav.h"
+
+// Sorted particle record, FP64 path: wrapped position and mass (32 B).
+struct Rec64 {
+    double x, y, z, m;
+};
+
+// Sorted particle / node record, FP32 path: integer position and FP32 mass (16 B).
+struct Rec32 {
+    uint32_t X, Y, Z;
+    float m;
+};
+
+// Node geometry for FP64 decisions: cube centre and side.
+struct Geo64 {
+    double cx, cy, cz, l;
+};
+
+// One entry of the combined pre-order sequence.
+//   ref:   node index, or (sorted particle position | ITEM_PARTICLE)
+//   next:  item index after this entry's subtree
+//   depth: depth below the root (root = 0)
+struct Item {
+    uint32_t ref;
+    uint32_t next;
+    uint32_t depth;
+    uint32_t pad;
+};
+
+#define ITEM_PARTICLE 0x80000000u
+#define SR_MAX_DEPTH 32
+#define SR_N_MAX (int64_t(1) << 30)
+
+// Device status words written by the build and read back once per build.
+enum {
+    ST_FLAGS = 0,      // bit 0: non-finite / non-positive input
+    ST_NODES = 1,      // number of internal nodes
+    ST_MAXDEPTH = 2,   // deepest node depth
+    ST_HIST = 3,       // [SR_MAX_DEPTH] nodes per depth
+    ST_WORDS = ST_HIST + SR_MAX_DEPTH
+};
+
+struct sr_tree {
+    int64_t n = 0;            // particles in the current tree
+    int64_t cap = 0;          // particle capacity of the workspace
+    double box = 1.0;
+    int device = 0;
+
+    // build workspace (cap)
+    uint64_t *khi[2] = {}, *klo[2] = {};
+    uint32_t* kidx[2] = {};
+    uint32_t* hist = nullptr;         // radix histograms / offsets
+    uint32_t* scan_tmp = nullptr;     // block sums of the scans
+    uint32_t* levelmask = nullptr;    // levels of the nodes starting at each sorted position
+    uint32_t* ucount = nullptr;       // per-position counts for the scans
+    int32_t* base = nullptr;          // (cap+1) nodes with first < s
+    int32_t *b_lo = nullptr, *b_hi = nullptr, *b_lambda = nullptr, *b_parent = nullptr;
+    int32_t* b_pre = nullptr;         // pre-order index, -1 if not an octree node
+    int32_t* leaf_bparent = nullptr;
+    int32_t* status = nullptr;        // ST_WORDS
+    int32_t* depth_order = nullptr;   // node indices grouped by depth
+    int32_t* depth_cursor = nullptr;  // SR_MAX_DEPTH
+
+    // tree (particles: cap, nodes: cap - 1, items: 2 cap)
+    int32_t *perm = nullptr, *invperm = nullptr, *pparent = nullptr;
+    Rec64* prec64 = nullptr;
+    double* ph64 = nullptr;           // spline support h = 2.8 eps
+    Rec32* prec32 = nullptr;
+    float* ph32 = nullptr;            // h in integer-coordinate units
+    int32_t *n_level = nullptr, *n_first = nullptr, *n_count = nullptr, *n_parent = nullptr,
+            *n_skip = nullptr, *n_depth = nullptr;
+    uint32_t* n_corner = nullptr;
+    Rec64* nrec64 = nullptr;          // centre of mass and mass
+    double* nS = nullptr;             // first moments (3 per node)
+    Geo64* ngeo64 = nullptr;
+    double *nhmax = nullptr, *nhmin = nullptr;
+    Rec32* nrec32 = nullptr;
+    float* nhmax32 = nullptr;
+    Item* items = nullptr;
+
+    // walk workspace (cap)
+    int32_t *tgt_sorted = nullptr, *tgt_slot = nullptr, *mark = nullptr;
+    uint32_t* tgt_flag = nullptr;
+    int32_t* tgt_pos = nullptr;       // (cap+1)
+    // adjoint workspace
+    double* pbar = nullptr;           // 4 per particle (x, y, z, m) source terms
+    double* tbar = nullptr;           // 3 per particle target terms
+    double* nbar = nullptr;           // 4 per node
+
+    // host mirrors
+    int64_t n_nodes = 0;
+    int max_depth = 0;
+    int depth_hist[SR_MAX_DEPTH] = {};
+};
+
+// error helpers shared by the host files
+int sr_fail(int code, const char* fmt, ...);
+#define SR_HIP(call)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return sr_fail(SR_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));   \
+    } while (0)
+
+// build.hip
+int sr_build_device(sr_tree* t, const double* pos, const double* mass, const double* eps,
+                    double eps_scalar, hipStream_t st);
+int sr_scan_exclusive(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* tmp, hipStream_t st);
+
+// walk.hip
+struct WalkPlan {
+    int64_t n_t;             // targets
+    const double* a_old;     // |a_old| per particle, input order (relative criterion)
+};
+int sr_prepare_targets(sr_tree* t, const int32_t* active, int64_t n_active, hipStream_t st);
+int sr_walk_forward(sr_tree* t, const sr_params* p, int64_t n_t, const double* a_old, void* acc,
+                    int32_t* counts, hipStream_t st);
+int sr_walk_adjoint(sr_tree* t, const sr_params* p, int64_t n_t, const double* a_old,
+                    const void* w, double* dLdx, double* dLdm, hipStream_t st);
