@@ -1,0 +1,184 @@
+"""Benchmark of the short-range TreePM gravity hot path on one MI355X.
+
+Workload: 64^3 = 262,144 equal-mass particles, 70% in 200 Plummer spheres on a
+uniform background, PM mesh 128^3 (r_s = 1.25/128, r_cut = 4.5 r_s),
+eps = 1/1920, Barnes-Hut theta = 0.5 (synthetic, seeded).
+
+One step = tree build (keys, radix sort, octree, moments) + FP32 forward walk
++ FP32 adjoint walk and push-down, i.e. a differentiated force evaluation.
+`value` = forward short-range interactions per second of whole step time.
+Outside the timed region the same run measures the FP64 walk, the FP32 force
+error against the FP64 oracle on a sample of targets, and the oracle itself on
+the host (cpu_baseline).
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "short-range interactions/s, FP32 vs FP64 at stated force error; fwd+adjoint"
+FP32_PEAK_TFLOPS = 157.3           # MI355X FP32 vector peak
+FLOP_PER_INTERACTION = 24          # algorithmic count per pair force
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-error-check", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (the library has no multi-GPU path); got --gpus {args.gpus}",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2606_17145_amd as sg
+    from paper_2606_17145_amd import _lib
+    from paper_2606_17145_amd import workloads as WL
+
+    _lib.lib()   # fail loudly if the HIP library is missing
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    w = WL.clustered_262k()
+    p32 = w.params("fp32")
+    p64 = w.params("fp64")
+    pos = torch.tensor(w.pos, device=dev)
+    mass = torch.tensor(w.mass, device=dev)
+    eps = torch.tensor(w.eps, device=dev)
+    cot = torch.tensor(WL.adjoint_weights(w.n), device=dev, dtype=torch.float32)
+    log(f"bench: {w.name} N={w.n}")
+
+    tree = sg.Tree()
+
+    def step(ev=None):
+        if ev:
+            ev[0].record()
+        sg.tree_build(pos, mass, eps=eps, box=w.box, tree=tree)
+        if ev:
+            ev[1].record()
+        acc, cnt = sg.shortrange_accel(tree, p32)
+        if ev:
+            ev[2].record()
+        dx, dm = sg.shortrange_accel_adjoint(tree, p32, cot)
+        if ev:
+            ev[3].record()
+        return acc, cnt
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        acc, cnt = step(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    build_ms = np.mean([e[0].elapsed_time(e[1]) for e in evs])
+    fwd_ms = np.mean([e[1].elapsed_time(e[2]) for e in evs])
+    adj_ms = np.mean([e[2].elapsed_time(e[3]) for e in evs])
+    ms_step = wall / args.steps * 1e3
+    counts = cnt.cpu().numpy().astype(np.int64)
+    inter = int(counts.sum())
+    log(f"bench: step {ms_step:.3f} ms (build {build_ms:.3f}, fwd32 {fwd_ms:.3f}, adj32 {adj_ms:.3f}), "
+        f"interactions {inter}")
+
+    # FP64 leg (not in the step): same tree, FP64 walk
+    e64 = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    for _ in range(2):
+        a64, c64 = sg.shortrange_accel(tree, p64)
+    reps = max(3, args.steps // 2)
+    t64 = []
+    for _ in range(reps):
+        e64[0].record()
+        a64, c64 = sg.shortrange_accel(tree, p64)
+        e64[1].record()
+        torch.cuda.synchronize()
+        t64.append(e64[0].elapsed_time(e64[1]))
+    fwd64_ms = float(np.mean(t64))
+    inter64 = int(c64.cpu().numpy().astype(np.int64).sum())
+    log(f"bench: fwd64 {fwd64_ms:.3f} ms")
+
+    out = {
+        "metric": METRIC,
+        "value": inter / (ms_step * 1e-3),
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32",
+        "data": "synthetic",
+        "config": {"workload": "clustered_262k", "n": w.n, "spheres": 200, "cluster_fraction": 0.7,
+                   "n_mesh": 128, "r_s": w.r_s, "r_cut": w.r_cut, "eps": float(w.eps[0]),
+                   "theta": w.theta, "criterion": "bh", "step": "build + fp32 walk + fp32 adjoint",
+                   "parallelism": "single GPU"},
+        "phases_ms": {"tree_build": build_ms, "walk_fp32": fwd_ms, "adjoint_fp32": adj_ms, "walk_fp64": fwd64_ms},
+        "interactions_per_step": inter,
+        "walk_fp32_interactions_per_s": inter / (fwd_ms * 1e-3),
+        "adjoint_fp32_interactions_per_s": inter / (adj_ms * 1e-3),
+        "walk_fp64_interactions_per_s": inter64 / (fwd64_ms * 1e-3),
+        "fp32_over_fp64_walk_speedup": fwd64_ms / fwd_ms,
+        "particles_per_s": w.n / (ms_step * 1e-3),
+    }
+    # dominant kernel: the larger of the two walks (each is a single launch)
+    dom_ms, dom_name = max((fwd_ms, "walk_fp32"), (adj_ms, "adjoint_fp32"))
+    flops = FLOP_PER_INTERACTION * inter * (1 if dom_name == "walk_fp32" else 2)
+    achieved = flops / (dom_ms * 1e-3) / 1e12
+    out["roofline"] = {"kernel": dom_name, "bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
+                       "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None}
+
+    if not args.no_error_check:
+        from oracle import oracle as O
+        ref = O.Tree(w.pos, w.mass, w.eps)
+        sample = np.sort(np.random.default_rng(9).choice(w.n, 16384, replace=False))
+        acc_ref, _ = O.walk(ref, p64, targets=sample)
+        a32 = acc.double().cpu().numpy()[sample]
+        nr = np.linalg.norm(acc_ref, axis=1)
+        e32 = np.linalg.norm(a32 - acc_ref, axis=1) / np.maximum(nr, 1e-6 * np.median(nr))
+        e64 = np.linalg.norm(a64.cpu().numpy()[sample] - acc_ref, axis=1) / np.maximum(nr, 1e-6 * np.median(nr))
+        out["force_error"] = {"vs": "fp64 oracle", "sample_targets": int(sample.size),
+                              "fp32_median": float(np.median(e32)), "fp32_p999": float(np.quantile(e32, 0.999)),
+                              "fp64_max": float(e64.max())}
+        log(f"bench: fp32 error median {np.median(e32):.2e} p99.9 {np.quantile(e32, 0.999):.2e}")
+
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        rng = np.random.default_rng(31)
+        sample = np.sort(rng.choice(w.n, 65536, replace=False))
+        wt = WL.adjoint_weights(w.n)[sample]
+        t0 = time.perf_counter()
+        ref = O.Tree(w.pos, w.mass, w.eps)
+        _, cs = O.walk(ref, p64, targets=sample)
+        O.adjoint(ref, p64, wt, targets=sample)
+        cpu_s = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": float(cs.sum()) / cpu_s, "unit": "interactions/s",
+                               "cores": O.num_threads(), "kind": "oracle",
+                               "sample": "FP64 oracle: tree build of all 262,144 particles + walk and adjoint "
+                                         "of 65,536 random targets (same step definition, sampled targets)"}
+        log(f"bench: oracle {cpu_s:.2f} s on {O.num_threads()} threads")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

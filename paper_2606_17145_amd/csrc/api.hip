@@ -35,6 +35,23 @@ void release(T*& p)
     p = nullptr;
 }
 
+void free_lists(sr_tree* t)
+{
+    release(t->ent_src);
+    release(t->ent_mask);
+    release(t->chunk_next);
+    release(t->chunk_cnt);
+    release(t->unit_group);
+    release(t->unit_chunk);
+    release(t->unit_nch);
+    release(t->unit_next);
+    release(t->group_head);
+    release(t->list_counters);
+    release(t->partials);
+    t->cap_chunks = t->cap_units = t->cap_groups = 0;
+    t->lkey.valid = false;
+}
+
 void free_workspace(sr_tree* t)
 {
     for (int k = 0; k < 2; ++k) {
@@ -87,6 +104,7 @@ void free_workspace(sr_tree* t)
     release(t->tbar);
     release(t->nbar);
     t->cap = 0;
+    free_lists(t);
 }
 
 int allocate_workspace(sr_tree* t, int64_t cap)
@@ -187,6 +205,37 @@ int check_call(sr_tree* t, const sr_params* p, const int32_t* active, int64_t n_
 }
 }  // namespace
 
+int sr_list_reserve(sr_tree* t, int64_t groups, int64_t chunks, int64_t chunks_per_unit)
+{
+    const int64_t units = groups + chunks / chunks_per_unit + 1;
+    if (groups <= t->cap_groups && chunks <= t->cap_chunks && units <= t->cap_units) return SR_OK;
+    // the old lists may still be read by queued work
+    SR_HIP(hipDeviceSynchronize());
+    free_lists(t);
+    int rc = SR_OK;
+#define A(ptr, count)                              \
+    if ((rc = alloc(&(ptr), (count))) != SR_OK) { \
+        free_lists(t);                             \
+        return rc;                                 \
+    }
+    A(t->ent_src, 64 * chunks);
+    A(t->ent_mask, 64 * chunks);
+    A(t->chunk_next, chunks);
+    A(t->chunk_cnt, chunks);
+    A(t->unit_group, units);
+    A(t->unit_chunk, units);
+    A(t->unit_nch, units);
+    A(t->unit_next, units);
+    A(t->group_head, groups);
+    A(t->list_counters, 4);
+    A(t->partials, 64 * (3 * 8 + 2 * 4) * units);
+#undef A
+    t->cap_groups = groups;
+    t->cap_chunks = chunks;
+    t->cap_units = units;
+    return SR_OK;
+}
+
 int sr_fail(int code, const char* fmt, ...)
 {
     va_list ap;
@@ -232,6 +281,7 @@ int tree_build(const double* pos, const double* mass, const double* eps, double 
     }
     t->n = n;
     t->box = box;
+    ++t->build_gen;
     int rc = sr_build_device(t, pos, mass, eps, eps_scalar, st);
     if (rc) {
         t->n = 0;
@@ -254,7 +304,7 @@ int shortrange_accel(sr_tree* t, const sr_params* p, const int32_t* active, int6
     if (!acc) return sr_fail(SR_EINVAL, "acc is NULL");
     hipStream_t st = (hipStream_t)stream;
     if ((rc = sr_prepare_targets(t, active, n_active, st))) return rc;
-    return sr_walk_forward(t, p, n_active, a_old, acc, counts, st);
+    return sr_walk_forward(t, p, n_active, active, a_old, acc, counts, st);
 }
 
 int shortrange_accel_adjoint(sr_tree* t, const sr_params* p, const int32_t* active, int64_t n_active,
@@ -266,7 +316,7 @@ int shortrange_accel_adjoint(sr_tree* t, const sr_params* p, const int32_t* acti
     if (!w || !dLdx || !dLdm) return sr_fail(SR_EINVAL, "w, dLdx and dLdm are required");
     hipStream_t st = (hipStream_t)stream;
     if ((rc = sr_prepare_targets(t, active, n_active, st))) return rc;
-    return sr_walk_adjoint(t, p, n_active, a_old, w, dLdx, dLdm, st);
+    return sr_walk_adjoint(t, p, n_active, active, a_old, w, dLdx, dLdm, st);
 }
 
 int tree_node_count(const sr_tree* t, int64_t* n_nodes)

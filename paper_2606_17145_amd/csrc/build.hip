@@ -380,15 +380,25 @@ __global__ void k_node_depth(int64_t m, const int32_t* __restrict__ n_parent, co
                              int32_t* __restrict__ n_depth, Item* __restrict__ items,
                              int32_t* __restrict__ status)
 {
+    // per-block depth histogram in LDS, one global atomic per non-empty bin
+    __shared__ int32_t h[SR_MAX_DEPTH];
+    __shared__ int32_t dmax;
+    if (threadIdx.x < SR_MAX_DEPTH) h[threadIdx.x] = 0;
+    if (threadIdx.x == 0) dmax = 0;
+    __syncthreads();
     int64_t nd = blockIdx.x * (int64_t)TPB + threadIdx.x;
-    if (nd >= m) return;
-    int d = 0;
-    for (int32_t p = n_parent[nd]; p >= 0; p = n_parent[p]) ++d;
-    n_depth[nd] = d;
-    int32_t f = n_first[nd], c = n_count[nd];
-    items[f + nd] = Item{(uint32_t)nd, (uint32_t)(f + c + base[f + c]), (uint32_t)d, 0u};
-    atomicMax(&status[ST_MAXDEPTH], d);
-    atomicAdd(&status[ST_HIST + (d < SR_MAX_DEPTH ? d : SR_MAX_DEPTH - 1)], 1);
+    if (nd < m) {
+        int d = 0;
+        for (int32_t p = n_parent[nd]; p >= 0; p = n_parent[p]) ++d;
+        n_depth[nd] = d;
+        int32_t f = n_first[nd], c = n_count[nd];
+        items[f + nd] = Item{(uint32_t)nd, (uint32_t)(f + c + base[f + c]), (uint32_t)d, 0u};
+        atomicAdd(&h[d < SR_MAX_DEPTH ? d : SR_MAX_DEPTH - 1], 1);
+        atomicMax(&dmax, d);
+    }
+    __syncthreads();
+    if (threadIdx.x < SR_MAX_DEPTH && h[threadIdx.x]) atomicAdd(&status[ST_HIST + threadIdx.x], h[threadIdx.x]);
+    if (threadIdx.x == 0) atomicMax(&status[ST_MAXDEPTH], dmax);
 }
 
 __global__ void k_particle_items(int64_t n, const int32_t* __restrict__ leaf_bparent,
@@ -419,11 +429,21 @@ __global__ void k_depth_scatter(int64_t m, const int32_t* __restrict__ n_depth,
                                 const int32_t* __restrict__ offsets, int32_t* __restrict__ cursor,
                                 int32_t* __restrict__ order)
 {
+    // ranks within the block from LDS counters; one global reservation per depth and block
+    __shared__ int32_t cnt[SR_MAX_DEPTH], off[SR_MAX_DEPTH];
+    if (threadIdx.x < SR_MAX_DEPTH) cnt[threadIdx.x] = 0;
+    __syncthreads();
     int64_t nd = blockIdx.x * (int64_t)TPB + threadIdx.x;
-    if (nd >= m) return;
-    int d = n_depth[nd];
-    int slot = atomicAdd(&cursor[d], 1);
-    order[offsets[d] + slot] = (int32_t)nd;
+    int d = -1, r = 0;
+    if (nd < m) {
+        d = n_depth[nd];
+        r = atomicAdd(&cnt[d], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < SR_MAX_DEPTH && cnt[threadIdx.x])
+        off[threadIdx.x] = atomicAdd(&cursor[threadIdx.x], cnt[threadIdx.x]);
+    __syncthreads();
+    if (d >= 0) order[offsets[d] + off[d] + r] = (int32_t)nd;
 }
 
 // Fold the children of every node of one depth, left to right in digit order:

@@ -52,6 +52,18 @@ enum {
     ST_WORDS = ST_HIST + SR_MAX_DEPTH
 };
 
+// What a traversal's lists were made for; the adjoint reuses them only on a match.
+struct ListKey {
+    bool valid = false;
+    int64_t gen = -1;
+    int dec64 = 0;
+    double G = 0, r_s = 0, r_cut = 0, theta = 0, alpha = 0;
+    int criterion = 0;
+    int64_t n_t = 0;
+    const void* active = nullptr;
+    const void* a_old = nullptr;
+};
+
 struct sr_tree {
     int64_t n = 0;            // particles in the current tree
     int64_t cap = 0;          // particle capacity of the workspace
@@ -99,6 +111,19 @@ struct sr_tree {
     double* tbar = nullptr;           // 3 per particle target terms
     double* nbar = nullptr;           // 4 per node
 
+    // interaction lists of the last traversal (capacity-managed)
+    int64_t cap_chunks = 0, cap_units = 0, cap_groups = 0;
+    uint32_t* ent_src = nullptr;      // 64 per chunk
+    uint64_t* ent_mask = nullptr;
+    int32_t *chunk_next = nullptr, *chunk_cnt = nullptr;
+    int32_t *unit_group = nullptr, *unit_chunk = nullptr, *unit_nch = nullptr, *unit_next = nullptr;
+    int32_t* group_head = nullptr;
+    int32_t* list_counters = nullptr;  // chunks, units, overflow
+    char* partials = nullptr;          // per unit
+    int64_t n_units = 0, n_chunks = 0;
+    ListKey lkey;
+    int64_t build_gen = 0;
+
     // host mirrors
     int64_t n_nodes = 0;
     int max_depth = 0;
@@ -120,12 +145,11 @@ int sr_build_device(sr_tree* t, const double* pos, const double* mass, const dou
 int sr_scan_exclusive(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* tmp, hipStream_t st);
 
 // walk.hip
-struct WalkPlan {
-    int64_t n_t;             // targets
-    const double* a_old;     // |a_old| per particle, input order (relative criterion)
-};
 int sr_prepare_targets(sr_tree* t, const int32_t* active, int64_t n_active, hipStream_t st);
-int sr_walk_forward(sr_tree* t, const sr_params* p, int64_t n_t, const double* a_old, void* acc,
-                    int32_t* counts, hipStream_t st);
-int sr_walk_adjoint(sr_tree* t, const sr_params* p, int64_t n_t, const double* a_old,
+int sr_walk_forward(sr_tree* t, const sr_params* p, int64_t n_t, const int32_t* active, const double* a_old,
+                    void* acc, int32_t* counts, hipStream_t st);
+int sr_walk_adjoint(sr_tree* t, const sr_params* p, int64_t n_t, const int32_t* active, const double* a_old,
                     const void* w, double* dLdx, double* dLdm, hipStream_t st);
+
+// api.hip: make room for the lists of `groups` target groups and `chunks` chunks
+int sr_list_reserve(sr_tree* t, int64_t groups, int64_t chunks, int64_t chunks_per_unit);

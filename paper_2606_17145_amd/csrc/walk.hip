@@ -1,18 +1,14 @@
-// Group-wise Barnes-Hut walk (forward and adjoint) for the short-range force.
-//
-// One wavefront walks the tree for up to 64 targets that are consecutive in
-// Morton order.  Each lane takes exactly the decisions a depth-first walk of
-// its own target would take (prune, open, accept); the wave only shares the
-// traversal: it scans the combined pre-order item sequence, entering a node's
-// children when at least one lane opened it (a ballot), and skipping the whole
-// subtree otherwise.  The open masks of the current path sit in LDS, indexed
-// by depth.  Accepted nodes and reached particles are appended, with the mask
-// of lanes they apply to, to an interaction list in LDS; when the list holds a
-// wavefront's worth of entries their records are staged in LDS with one
-// coalesced load and every lane sweeps the list, evaluating the pair force for
-// the entries whose mask holds it.  This is the chunked neighbour processing
-// of the paper's GPU port (chunks of neighbours evaluated before the walk
-// continues, its GPU-porting subsection) mapped onto a 64-wide wavefront.
+// Group-wise Barnes-Hut walk (forward and adjoint) of the short-range force,
+// in three phases:
+//   1. traverse: one wavefront per 64 Morton-consecutive targets takes every
+//      lane's depth-first-walk decisions (ballots over the pre-order item
+//      sequence) and writes the interaction list as (source, lane mask)
+//      entries in chunks of 64;
+//   2. evaluate: one wavefront per unit of up to UCH chunks sweeps the entries,
+//      evaluating the pair force for the lanes in each mask;
+//   3. reduce: the units' partial sums are added per group in a fixed order.
+// The adjoint reuses the forward's lists (the frozen decisions) and scatters
+// source terms with wave sums and FP64 atomics.
 #include <stdio.h>
 
 #include <type_traits>
@@ -23,7 +19,7 @@
 namespace {
 
 constexpr int WAVE = 64;
-constexpr int CHUNK = 64;               // list entries per flush (one per lane when staging)
+constexpr int WIN = 64;                 // items held by the register window (one per lane)
 constexpr double TWO32 = 4294967296.0;
 constexpr double TWO_OVER_SQRTPI = 1.12837916709551257390;
 constexpr float LOG2E_F = 1.44269504088896340736f;
@@ -146,245 +142,564 @@ __device__ inline float spline_h4dS_32(float q)
     return __builtin_fmaf(t, __builtin_fmaf(t, -32.0f, -12.8f), -3.2f) + 1.0f / (5.0f * q2 * q2);
 }
 
-// ---- wave reduction --------------------------------------------------------------
+// ---- wave reductions (DPP row shifts and row broadcasts; the total lands in lane 63) ----
 
-template <class T>
-__device__ inline T wave_sum(T v)
+template <int CTRL, int ROWMASK, int BANKMASK>
+__device__ inline float dpp_f32(float v)
 {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWMASK, BANKMASK, false));
+}
+
+template <int CTRL, int ROWMASK, int BANKMASK>
+__device__ inline double dpp_f64(double v)
+{
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, ROWMASK, BANKMASK, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, ROWMASK, BANKMASK, false);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+
+template <class T, int CTRL, int ROWMASK, int BANKMASK>
+__device__ inline T dppm(T v)
+{
+    if constexpr (sizeof(T) == 4) return dpp_f32<CTRL, ROWMASK, BANKMASK>(v);
+    else return dpp_f64<CTRL, ROWMASK, BANKMASK>(v);
+}
+
+// Sum over the 64 lanes: rows of 16 by shifts of 1, 2, 3, 4, 8, then rows
+// chained by broadcasts of lanes 15 and 31.  Only lane 63 holds the total.
+template <class T>
+__device__ inline T wave_sum63(T x)
+{
+    T v = x + dppm<T, 0x111, 0xf, 0xf>(x);
+    v = v + dppm<T, 0x112, 0xf, 0xf>(x);
+    v = v + dppm<T, 0x113, 0xf, 0xf>(x);
+    v = v + dppm<T, 0x114, 0xf, 0xe>(v);
+    v = v + dppm<T, 0x118, 0xf, 0xc>(v);
+    v = v + dppm<T, 0x142, 0xa, 0xf>(v);
+    v = v + dppm<T, 0x143, 0xc, 0xf>(v);
     return v;
 }
 
 // ----------------------------------------------------------------------------------
-// the walk
+// register-resident wave state
 // ----------------------------------------------------------------------------------
+//
+// Everything a wave keeps lives in VGPRs, one slot per lane, and is read back
+// as a scalar with v_readlane at a uniform index (or written with a lane
+// select): the window of the item sequence (lane l = item w0 + l, with its
+// node's decision data), the open masks of the current path (lane d = depth
+// d), and the pending list entries (lane e = entry e).
 
-template <int PREC>
-struct Stage;
-
-template <>
-struct Stage<PR64> {
-    double x[CHUNK], y[CHUNK], z[CHUNK], m[CHUNK], h[CHUNK];
-};
-
-template <>
-struct Stage<PR32> {
-    uint32_t X[CHUNK], Y[CHUNK], Z[CHUNK];
-    float m[CHUNK], h[CHUNK];
-};
-
-template <>
-struct Stage<PR32A> : Stage<PR32> {};
-
-template <int PREC>
-struct WalkShared {
-    uint64_t open[SR_MAX_DEPTH];
-    uint64_t mask[CHUNK];
-    uint32_t src[CHUNK];
-    Stage<PREC> rec;
-};
-
-template <int PREC, bool ADJ>
-__global__ __launch_bounds__(WAVE) void k_walk(WalkArgs a)
+__device__ inline uint32_t rl(uint32_t v, uint32_t l) { return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)l); }
+__device__ inline float rlf(float v, uint32_t l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), (int)l)); }
+__device__ inline uint64_t rl64(uint64_t v, uint32_t l)
 {
-    using acc_t = typename std::conditional<PREC == PR32, float, double>::type;
-    __shared__ WalkShared<PREC> sh;
-    const int lane = threadIdx.x;
-    const int64_t t = (int64_t)blockIdx.x * WAVE + lane;
-    const bool valid = t < a.n_t;
+    return ((uint64_t)rl((uint32_t)(v >> 32), l) << 32) | rl((uint32_t)v, l);
+}
+__device__ inline double rld(double v, uint32_t l)
+{
+    return __longlong_as_double((long long)rl64((uint64_t)__double_as_longlong(v), l));
+}
+template <class T>
+__device__ inline T wl(T v, uint32_t l, T old)
+{
+    return (uint32_t)threadIdx.x == l ? v : old;
+}
 
-    // target state
-    int32_t s_i = valid ? a.tgt_sorted[t] : 0;
-    int32_t slot = valid ? a.tgt_slot[t] : 0;
-    double x64 = 0, y64 = 0, z64 = 0, h64 = 0, aold = 0;
+struct Node64 {
+    double cx = 0, cy = 0, cz = 0, l = 0, X = 0, Y = 0, Z = 0, M = 0, hx = 0, hn = 0;
+};
+struct Node32 {
+    uint32_t cX = 0, cY = 0, cZ = 0, tin = 0, X = 0, Y = 0, Z = 0, mixed = 0;
+    float M = 0, half = 0, l2 = 0, hx = 0;
+};
+
+// ----------------------------------------------------------------------------------
+// phase 1: traversal -> interaction lists
+// ----------------------------------------------------------------------------------
+//
+// One wave per group of 64 Morton-consecutive targets.  Each lane takes the
+// decisions of a depth-first walk of its own target; the wave shares the
+// traversal through ballots over the pre-order item sequence (a node's
+// children are entered when any lane opens it, its subtree skipped otherwise).
+// Accepted nodes and reached particles become list entries (source, lane
+// mask); the target's own particle is removed from its mask here.  Entries go
+// to global memory in chunks of 64; up to UCH consecutive chunks of a group
+// form a unit, the work item of the evaluation phase.  This is the paper's
+// chunked neighbour processing (neighbours gathered in chunks and evaluated
+// chunk by chunk, its GPU-porting subsection) with chunks of a wavefront's
+// width, decoupled from the walk so that heavy groups spread over many waves.
+
+constexpr int UCH = 8;   // chunks per evaluation unit
+
+struct ListArgs {
+    uint32_t* ent_src;
+    uint64_t* ent_mask;
+    int32_t* chunk_next;
+    int32_t* chunk_cnt;
+    int32_t* unit_group;
+    int32_t* unit_chunk;
+    int32_t* unit_nch;
+    int32_t* unit_next;
+    int32_t* group_head;
+    int32_t* counters;      // [0] chunks, [1] units, [2] overflow
+    int64_t cap_chunks;
+    int64_t cap_units;
+};
+
+template <bool DEC64>
+__global__ __launch_bounds__(WAVE) void k_traverse(WalkArgs a, ListArgs L)
+{
+    const int lane = threadIdx.x;
+    const int64_t g = blockIdx.x;
+    const int64_t t = g * WAVE + lane;
+    const bool valid = t < a.n_t;
+    const int32_t s_i = valid ? a.tgt_sorted[t] : -1;
+    double x64 = 0, y64 = 0, z64 = 0, aold = 0, atau = 0;
     uint32_t X = 0, Y = 0, Z = 0;
-    float h32 = 0;
-    double atau = 0;
     if (valid) {
-        if constexpr (PREC == PR64) {
-            Rec64 r = a.prec64[s_i];
+        if constexpr (DEC64) {
+            const Rec64 r = a.prec64[s_i];
             x64 = r.x;
             y64 = r.y;
             z64 = r.z;
-            h64 = a.ph64[s_i];
         } else {
-            Rec32 r = a.prec32[s_i];
+            const Rec32 r = a.prec32[s_i];
             X = r.X;
             Y = r.Y;
             Z = r.Z;
-            h32 = a.ph32[s_i];
         }
         if (a.relative) {
             aold = a.a_old[a.perm[s_i]];
             atau = (a.alpha * aold) * a.tau2;
         }
     }
-    acc_t ax = 0, ay = 0, az = 0;
-    int npp = 0, npn = 0;
-    // adjoint cotangent and target-side adjoint
-    acc_t wx = 0, wy = 0, wz = 0, tbx = 0, tby = 0, tbz = 0;
-    if (ADJ && valid) {
-        const acc_t* w = (const acc_t*)a.w;
-        wx = w[3 * slot];
-        wy = w[3 * slot + 1];
-        wz = w[3 * slot + 2];
-    }
     const uint64_t active = __ballot(valid);
-    const bool mixed = a.n_nodes > 0 && a.nhmax[0] != a.nhmin[0];
+    const bool mixed = a.nhmax[0] != a.nhmin[0];
 
-    auto flush = [&](int nl) {
-        __syncthreads();
-        if (lane < nl) {
-            uint32_t src = sh.src[lane];
-            if constexpr (PREC == PR64) {
-                Rec64 r;
-                double h;
-                if (src & ITEM_PARTICLE) {
-                    r = a.prec64[src & ~ITEM_PARTICLE];
-                    h = a.ph64[src & ~ITEM_PARTICLE];
-                } else {
-                    r = a.nrec64[src];
-                    h = a.nhmax[src];
-                }
-                sh.rec.x[lane] = r.x;
-                sh.rec.y[lane] = r.y;
-                sh.rec.z[lane] = r.z;
-                sh.rec.m[lane] = r.m;
-                sh.rec.h[lane] = h;
+    // ---- pending entries and their emission in chunks ----
+    uint32_t lsrc = 0;
+    uint64_t lmask = 0;
+    uint32_t nl = 0;
+    int32_t prev_chunk = -1, cur_unit = -1, prev_unit = -1;
+    uint32_t nch = 0, unit_nch = 0;
+    bool overflow = false;
+    auto emit = [&]() {
+        int32_t c0 = 0, u0 = 0;
+        const bool new_unit = (nch % UCH) == 0;
+        if (lane == 0) {
+            c0 = atomicAdd(&L.counters[0], 1);
+            if (new_unit) u0 = atomicAdd(&L.counters[1], 1);
+        }
+        const int32_t c = (int32_t)rl((uint32_t)c0, 0);
+        const int32_t u = (int32_t)rl((uint32_t)u0, 0);
+        if (c >= L.cap_chunks || (new_unit && u >= L.cap_units)) {
+            if (lane == 0) atomicOr(&L.counters[2], 1);
+            overflow = true;
+            nl = 0;
+            return;
+        }
+        if ((uint32_t)lane < nl) {
+            L.ent_src[64 * (int64_t)c + lane] = lsrc;
+            L.ent_mask[64 * (int64_t)c + lane] = lmask;
+        }
+        if (lane == 0) {
+            L.chunk_cnt[c] = (int32_t)nl;
+            L.chunk_next[c] = -1;
+            if (new_unit) {
+                if (cur_unit >= 0) L.unit_nch[cur_unit] = (int32_t)unit_nch;
+                L.unit_group[u] = (int32_t)g;
+                L.unit_chunk[u] = c;
+                L.unit_next[u] = -1;
+                if (prev_unit >= 0) L.unit_next[prev_unit] = u;
+                else L.group_head[g] = u;
             } else {
-                Rec32 r;
-                float h;
-                if (src & ITEM_PARTICLE) {
-                    r = a.prec32[src & ~ITEM_PARTICLE];
-                    h = a.ph32[src & ~ITEM_PARTICLE];
-                } else {
-                    r = a.nrec32[src];
-                    h = a.nhmax32[src];
-                }
-                sh.rec.X[lane] = r.X;
-                sh.rec.Y[lane] = r.Y;
-                sh.rec.Z[lane] = r.Z;
-                sh.rec.m[lane] = r.m * TWO64_F;
-                sh.rec.h[lane] = h;
+                L.chunk_next[prev_chunk] = c;
             }
         }
-        __syncthreads();
-        for (int e = 0; e < nl; ++e) {
-            const uint64_t m = uniform64(sh.mask[e]);
-            const uint32_t src = uniform32(sh.src[e]);
+        if (new_unit) {
+            prev_unit = u;
+            cur_unit = u;
+            unit_nch = 0;
+        }
+        ++unit_nch;
+        prev_chunk = c;
+        ++nch;
+        nl = 0;
+    };
+
+    // ---- the window ----
+    uint32_t wref = 0xffffffffu, wnext = 0u, wdepth = 0xffffffffu;
+    uint64_t wrun = 0;   // bit l: item l is a particle continued by a sibling particle at l + 1
+    typename std::conditional<DEC64, Node64, Node32>::type wn;
+    auto load_window = [&](uint32_t k0) {
+        const uint32_t idx = k0 + (uint32_t)lane;
+        wref = 0xffffffffu;
+        wnext = 0u;
+        wdepth = 0xffffffffu;
+        if (idx < a.n_items) {
+            const Item it = a.items[idx];
+            wref = it.ref;
+            wnext = it.next;
+            wdepth = it.depth;
+            if (!(wref & ITEM_PARTICLE)) {
+                const uint32_t nd = wref;
+                if constexpr (DEC64) {
+                    const Geo64 gg = a.ngeo64[nd];
+                    const Rec64 c = a.nrec64[nd];
+                    wn.cx = gg.cx;
+                    wn.cy = gg.cy;
+                    wn.cz = gg.cz;
+                    wn.l = gg.l;
+                    wn.X = c.x;
+                    wn.Y = c.y;
+                    wn.Z = c.z;
+                    wn.M = c.m;
+                    wn.hx = a.nhmax[nd];
+                    wn.hn = a.nhmin[nd];
+                } else {
+                    const Rec32 c = a.nrec32[nd];
+                    const int lev = a.n_level[nd];
+                    const uint32_t half = 1u << (31 - lev);
+                    const uint64_t lint = 1ull << (32 - lev);
+                    wn.cX = a.n_corner[3 * nd + 0] + half;
+                    wn.cY = a.n_corner[3 * nd + 1] + half;
+                    wn.cZ = a.n_corner[3 * nd + 2] + half;
+                    wn.tin = (uint32_t)((3ull * lint - 1ull) / 5ull);
+                    wn.X = c.X;
+                    wn.Y = c.Y;
+                    wn.Z = c.Z;
+                    wn.M = c.m;
+                    wn.half = (float)half;
+                    wn.l2 = (float)lint * (float)lint;
+                    wn.hx = a.nhmax32[nd];
+                    wn.mixed = mixed && a.nhmin[nd] != a.nhmax[nd];
+                }
+            }
+        }
+        const uint32_t nref = (uint32_t)__shfl_down((int)wref, 1, 64);
+        const uint32_t ndep = (uint32_t)__shfl_down((int)wdepth, 1, 64);
+        wrun = __ballot(lane < 63 && (wref & ITEM_PARTICLE) && wdepth != 0xffffffffu && (nref & ITEM_PARTICLE) &&
+                        ndep == wdepth);
+    };
+
+    uint64_t openv = 0;   // lane d: open mask of the path node at depth d
+    uint32_t k = 0, w0 = 0xffffffffu;
+    while (k < a.n_items && !overflow) {
+        if (k < w0 || k - w0 >= (uint32_t)WIN) {
+            load_window(k);
+            w0 = k;
+        }
+        const uint32_t j = k - w0;
+        const uint32_t ref = rl(wref, j);
+        const uint32_t depth = rl(wdepth, j);
+        const uint64_t reach = depth ? rl64(openv, depth - 1) : active;
+        if (ref & ITEM_PARTICLE) {
+            // a run of sibling particles (consecutive sorted positions) shares the reach mask
+            const uint32_t R = (uint32_t)__builtin_ctzll(~(wrun >> j)) + 1u;
+            if (nl + R > (uint32_t)WAVE) emit();
+            const uint32_t p0 = ref & ~ITEM_PARTICLE;
+            if ((uint32_t)lane >= nl && (uint32_t)lane < nl + R) {
+                lsrc = (p0 + ((uint32_t)lane - nl)) | ITEM_PARTICLE;
+                lmask = reach;
+            }
+            // targets whose own particle lies in the run leave that entry
+            uint64_t self = __ballot(valid && (uint32_t)s_i - p0 < R) & reach;
+            while (self) {
+                const uint32_t tl = (uint32_t)__builtin_ctzll(self);
+                self &= self - 1;
+                const uint32_t e = nl + (rl((uint32_t)s_i, tl) - p0);
+                if ((uint32_t)lane == e) lmask &= ~(1ull << tl);
+            }
+            nl += R;
+            k += R;
+            continue;
+        }
+        int dec = D_PRUNE;
+        if ((reach >> lane) & 1ull) {
+            if constexpr (DEC64) {
+                const double l = rld(wn.l, j);
+                const double dcx = min_image(rld(wn.cx, j) - x64, a.box);
+                const double dcy = min_image(rld(wn.cy, j) - y64, a.box);
+                const double dcz = min_image(rld(wn.cz, j) - z64, a.box);
+                double t2 = 0.0, tt;
+                tt = fabs(dcx) - 0.5 * l;
+                if (tt > 0) t2 += tt * tt;
+                tt = fabs(dcy) - 0.5 * l;
+                if (tt > 0) t2 += tt * tt;
+                tt = fabs(dcz) - 0.5 * l;
+                if (tt > 0) t2 += tt * tt;
+                if (!(t2 > a.rc2 * (1.0 + 1e-6))) {
+                    const bool inside = fabs(dcx) < 0.6 * l && fabs(dcy) < 0.6 * l && fabs(dcz) < 0.6 * l;
+                    const double dx = min_image(rld(wn.X, j) - x64, a.box);
+                    const double dy = min_image(rld(wn.Y, j) - y64, a.box);
+                    const double dz = min_image(rld(wn.Z, j) - z64, a.box);
+                    const double r2 = (dx * dx + dy * dy) + dz * dz;
+                    bool open = inside || l * l > a.theta2 * r2;
+                    if (a.relative && (a.G * rld(wn.M, j)) * (l * l) > (a.alpha * aold) * (r2 * r2)) open = true;
+                    if (mixed) {
+                        const double hx = rld(wn.hx, j);
+                        if (rld(wn.hn, j) != hx && r2 < hx * hx) open = true;
+                    }
+                    dec = open ? D_OPEN : (r2 < a.rc2 ? D_ACCEPT : D_ACCEPT_FAR);
+                }
+            } else {
+                const int32_t dcx = (int32_t)(rl(wn.cX, j) - X);
+                const int32_t dcy = (int32_t)(rl(wn.cY, j) - Y);
+                const int32_t dcz = (int32_t)(rl(wn.cZ, j) - Z);
+                const uint32_t bx = dcx < 0 ? 0u - (uint32_t)dcx : (uint32_t)dcx;
+                const uint32_t by = dcy < 0 ? 0u - (uint32_t)dcy : (uint32_t)dcy;
+                const uint32_t bz = dcz < 0 ? 0u - (uint32_t)dcz : (uint32_t)dcz;
+                const float half = rlf(wn.half, j);
+                const float tx = fmaxf((float)bx - half, 0.0f);
+                const float ty = fmaxf((float)by - half, 0.0f);
+                const float tz = fmaxf((float)bz - half, 0.0f);
+                const float t2 = __builtin_fmaf(tx, tx, __builtin_fmaf(ty, ty, tz * tz));
+                if (!(t2 > a.rc2t * 1.0001f)) {
+                    const uint32_t tin = rl(wn.tin, j);
+                    const bool inside = bx <= tin && by <= tin && bz <= tin;
+                    const float dx = (float)(int32_t)(rl(wn.X, j) - X);
+                    const float dy = (float)(int32_t)(rl(wn.Y, j) - Y);
+                    const float dz = (float)(int32_t)(rl(wn.Z, j) - Z);
+                    const float r2 = r2_ticks(dx, dy, dz);
+                    const float l2 = rlf(wn.l2, j);
+                    bool open = inside || l2 > a.theta2f * r2;
+                    if (a.relative) {
+                        const double r2d = (double)r2;
+                        if ((a.G * (double)rlf(wn.M, j)) * (double)l2 > atau * (r2d * r2d)) open = true;
+                    }
+                    if (mixed) {
+                        const float hx = rlf(wn.hx, j);
+                        if (rl(wn.mixed, j) && r2 < hx * hx) open = true;
+                    }
+                    dec = open ? D_OPEN : (r2 < a.rc2t ? D_ACCEPT : D_ACCEPT_FAR);
+                }
+            }
+        }
+        const uint64_t om = __ballot(dec == D_OPEN);
+        const uint64_t am = __ballot(dec == D_ACCEPT);
+        if (am) {
+            if (nl == (uint32_t)WAVE) emit();
+            lsrc = wl(ref, nl, lsrc);
+            lmask = wl(am, nl, lmask);
+            ++nl;
+        }
+        if (om) {
+            openv = wl(om, depth, openv);
+            ++k;
+        } else {
+            k = rl(wnext, j);
+        }
+    }
+    if (nl && !overflow) emit();
+    if (lane == 0 && cur_unit >= 0 && !overflow) L.unit_nch[cur_unit] = (int32_t)unit_nch;
+}
+
+// ----------------------------------------------------------------------------------
+// phase 2: evaluation of one unit (up to UCH chunks of one group)
+// ----------------------------------------------------------------------------------
+
+struct Src64 {
+    double x = 0, y = 0, z = 0, m = 0, h = 0;
+};
+struct Src32 {
+    uint32_t X = 0, Y = 0, Z = 0;
+    float m = 0, h = 0;
+};
+
+// per-unit partial results: acc_t[3][64] then int32[2][64] (forward) or acc_t[3][64] (adjoint)
+constexpr int PARTIAL_BYTES = 64 * (3 * 8 + 2 * 4);
+
+template <int PREC, bool ADJ>
+__global__ __launch_bounds__(WAVE) void k_eval(WalkArgs a, ListArgs L, char* __restrict__ partials)
+{
+    using acc_t = typename std::conditional<PREC == PR32, float, double>::type;
+    constexpr bool F64 = PREC == PR64;
+    using SrcT = typename std::conditional<F64, Src64, Src32>::type;
+    const int lane = threadIdx.x;
+    const int32_t u = blockIdx.x;
+    const int64_t g = L.unit_group[u];
+    const int64_t t = g * WAVE + lane;
+    const bool valid = t < a.n_t;
+    const int32_t s_i = valid ? a.tgt_sorted[t] : 0;
+    double x64 = 0, y64 = 0, z64 = 0, h64 = 0;
+    uint32_t X = 0, Y = 0, Z = 0;
+    float h32 = 0, h32sq = 0;
+    if constexpr (F64) {
+        const Rec64 r = a.prec64[s_i];
+        x64 = r.x;
+        y64 = r.y;
+        z64 = r.z;
+        h64 = a.ph64[s_i];
+    } else {
+        const Rec32 r = a.prec32[s_i];
+        X = r.X;
+        Y = r.Y;
+        Z = r.Z;
+        h32 = a.ph32[s_i];
+        h32sq = h32 * h32;
+    }
+    acc_t ax = 0, ay = 0, az = 0;
+    int npp = 0, npn = 0;
+    acc_t wx = 0, wy = 0, wz = 0, tbx = 0, tby = 0, tbz = 0;
+    if constexpr (ADJ) {
+        if (valid) {
+            const int32_t slot = a.tgt_slot[t];
+            const acc_t* w = (const acc_t*)a.w;
+            wx = w[3 * (int64_t)slot];
+            wy = w[3 * (int64_t)slot + 1];
+            wz = w[3 * (int64_t)slot + 2];
+        }
+    }
+
+    int32_t c = L.unit_chunk[u];
+    const int32_t nch = L.unit_nch[u];
+    for (int32_t q = 0; q < nch; ++q) {
+        const uint32_t cnt = (uint32_t)L.chunk_cnt[c];
+        uint32_t lsrc = 0;
+        uint64_t lmask = 0;
+        SrcT mine;
+        if ((uint32_t)lane < cnt) {
+            lsrc = L.ent_src[64 * (int64_t)c + lane];
+            lmask = L.ent_mask[64 * (int64_t)c + lane];
+            const bool isp = lsrc & ITEM_PARTICLE;
+            const uint32_t idx = lsrc & ~ITEM_PARTICLE;
+            if constexpr (F64) {
+                const Rec64 r = isp ? a.prec64[idx] : a.nrec64[idx];
+                mine.x = r.x;
+                mine.y = r.y;
+                mine.z = r.z;
+                mine.m = r.m;
+                mine.h = isp ? a.ph64[idx] : a.nhmax[idx];
+            } else {
+                const Rec32 r = isp ? a.prec32[idx] : a.nrec32[idx];
+                const float hs = isp ? a.ph32[idx] : a.nhmax32[idx];
+                mine.X = r.X;
+                mine.Y = r.Y;
+                mine.Z = r.Z;
+                mine.m = r.m * TWO64_F;
+                mine.h = hs * hs;   // squared support of the source
+            }
+        }
+        const int32_t cnext = L.chunk_next[c];
+        for (uint32_t e = 0; e < cnt; ++e) {
+            const uint32_t src = rl(lsrc, e);
+            const uint64_t m = rl64(lmask, e);
             const bool isp = (src & ITEM_PARTICLE) != 0;
             const bool on = (m >> lane) & 1ull;
-            // source-side adjoint terms of this entry (0 on lanes that do not use it)
             acc_t vx = 0, vy = 0, vz = 0, vm = 0;
-            if (on) {
-                if constexpr (PREC == PR64) {
-                    double dx = min_image(sh.rec.x[e] - x64, a.box);
-                    double dy = min_image(sh.rec.y[e] - y64, a.box);
-                    double dz = min_image(sh.rec.z[e] - z64, a.box);
-                    double r2 = (dx * dx + dy * dy) + dz * dz;
+            if constexpr (F64) {
+                const double qx = rld(mine.x, e), qy = rld(mine.y, e), qz = rld(mine.z, e);
+                const double qm = rld(mine.m, e), qh = rld(mine.h, e);
+                if (on) {
+                    const double dx = min_image(qx - x64, a.box);
+                    const double dy = min_image(qy - y64, a.box);
+                    const double dz = min_image(qz - z64, a.box);
+                    const double r2 = (dx * dx + dy * dy) + dz * dz;
                     if (r2 < a.rc2) {
                         if (isp) ++npp;
                         else ++npn;
-                        double r = sqrt(r2);
-                        double u = r * a.inv2rs;
-                        double ex = exp(-u * u);
-                        double g = erfc(u) + TWO_OVER_SQRTPI * u * ex;
-                        double hp = h64 > sh.rec.h[e] ? h64 : sh.rec.h[e];
+                        const double r = sqrt(r2);
+                        const double uu = r * a.inv2rs;
+                        const double ex = exp(-uu * uu);
+                        const double gg = erfc(uu) + TWO_OVER_SQRTPI * uu * ex;
+                        const double hp = h64 > qh ? h64 : qh;
                         double S, dS;
                         spline64(r, hp, S, dS);
-                        double K = a.G * S * g;
-                        double Mg = sh.rec.m[e];
+                        const double K = a.G * S * gg;
                         if constexpr (!ADJ) {
-                            double f = Mg * K;
+                            const double f = qm * K;
                             ax += f * dx;
                             ay += f * dy;
                             az += f * dz;
                         } else {
-                            double dg = -2.0 * TWO_OVER_SQRTPI * u * u * ex;
-                            double dK = a.G * (dS * g + S * dg * a.inv2rs);
-                            double c2 = r > 0.0 ? dK / r : 0.0;
-                            double wd = (wx * dx + wy * dy) + wz * dz;
-                            vx = Mg * (K * wx + c2 * wd * dx);
-                            vy = Mg * (K * wy + c2 * wd * dy);
-                            vz = Mg * (K * wz + c2 * wd * dz);
+                            const double dg = -2.0 * TWO_OVER_SQRTPI * uu * uu * ex;
+                            const double dK = a.G * (dS * gg + S * dg * a.inv2rs);
+                            const double c2 = r > 0.0 ? dK / r : 0.0;
+                            const double wd = (wx * dx + wy * dy) + wz * dz;
+                            vx = qm * (K * wx + c2 * wd * dx);
+                            vy = qm * (K * wy + c2 * wd * dy);
+                            vz = qm * (K * wz + c2 * wd * dz);
                             vm = K * wd;
                             tbx -= vx;
                             tby -= vy;
                             tbz -= vz;
                         }
                     }
-                } else {
-                    float dx = (float)(int32_t)(sh.rec.X[e] - X);
-                    float dy = (float)(int32_t)(sh.rec.Y[e] - Y);
-                    float dz = (float)(int32_t)(sh.rec.Z[e] - Z);
-                    float r2 = r2_ticks(dx, dy, dz);
-                    if (r2 < a.rc2t) {
-                        if (isp) ++npp;
-                        else ++npn;
-                        float rinv = __builtin_amdgcn_rsqf(r2);
-                        float r = r2 > 0.0f ? r2 * rinv : 0.0f;
-                        float u = r * a.inv2rs_t;
-                        float ex;
-                        float g = gshort32(u, ex);
-                        float hp = fmaxf(h32, sh.rec.h[e]);
-                        float S, Srd;   // S and r dS/dr
-                        if (r2 < hp * hp) {
-                            float ih = __builtin_amdgcn_rcpf(hp);
-                            float q = r * ih;
-                            float ih3 = ih * ih * ih;
-                            S = spline_h3S_32(q) * ih3;
-                            Srd = ADJ ? spline_h4dS_32(q) * q * ih3 : 0.0f;
-                        } else {
-                            S = rinv * rinv * rinv;
-                            Srd = -3.0f * S;
-                        }
-                        float Mg = sh.rec.m[e];
-                        float K = S * g;
-                        if constexpr (!ADJ) {
-                            float f = Mg * K;
-                            ax += (acc_t)(f * dx);
-                            ay += (acc_t)(f * dy);
-                            az += (acc_t)(f * dz);
-                        } else {
-                            // K' r = r dS/dr g + S g'(u) u
-                            float dg = -2.0f * TWO_OVER_SQRTPI_F * u * u * ex;
-                            float Kr = Srd * g + S * dg * u;
-                            float nrm = r2 > 0.0f ? rinv : 0.0f;
-                            float nx = dx * nrm, ny = dy * nrm, nz = dz * nrm;
-                            float fw = (float)wx, fy = (float)wy, fz = (float)wz;
-                            float wn = __builtin_fmaf(fw, nx, __builtin_fmaf(fy, ny, fz * nz));
-                            float wd = __builtin_fmaf(fw, dx, __builtin_fmaf(fy, dy, fz * dz));
-                            float c = Kr * wn;
-                            float px = Mg * __builtin_fmaf(K, fw, c * nx);
-                            float py = Mg * __builtin_fmaf(K, fy, c * ny);
-                            float pz = Mg * __builtin_fmaf(K, fz, c * nz);
-                            vx = px;
-                            vy = py;
-                            vz = pz;
-                            vm = K * wd;
-                            tbx -= (acc_t)px;
-                            tby -= (acc_t)py;
-                            tbz -= (acc_t)pz;
-                        }
+                }
+            } else {
+                // branch-free: every lane computes, lanes outside the entry select zero
+                const float qm = rlf(mine.m, e), qh2 = rlf(mine.h, e);
+                const float dx = (float)(int32_t)(rl(mine.X, e) - X);
+                const float dy = (float)(int32_t)(rl(mine.Y, e) - Y);
+                const float dz = (float)(int32_t)(rl(mine.Z, e) - Z);
+                const float r2 = r2_ticks(dx, dy, dz);
+                const bool in = on && r2 < a.rc2t;
+                const float rinv = __builtin_amdgcn_rsqf(r2);
+                const float r = r2 > 0.0f ? r2 * rinv : 0.0f;
+                const float uu = r * a.inv2rs_t;
+                float ex;
+                const float gg = gshort32(uu, ex);
+                float S = rinv * rinv * rinv;
+                float Srd = -3.0f * S;
+                const bool soft = in && r2 < fmaxf(h32sq, qh2);
+                if (__ballot(soft)) {
+                    if (soft) {
+                        const float hp = __builtin_sqrtf(fmaxf(h32sq, qh2));
+                        const float ih = __builtin_amdgcn_rcpf(hp);
+                        const float qq = r * ih;
+                        const float ih3 = ih * ih * ih;
+                        S = spline_h3S_32(qq) * ih3;
+                        if constexpr (ADJ) Srd = spline_h4dS_32(qq) * qq * ih3;
                     }
+                }
+                if (isp) npp += in ? 1 : 0;
+                else npn += in ? 1 : 0;
+                const float K = in ? S * gg : 0.0f;
+                if constexpr (!ADJ) {
+                    const float f = qm * K;
+                    ax += (acc_t)(f * dx);
+                    ay += (acc_t)(f * dy);
+                    az += (acc_t)(f * dz);
+                } else {
+                    // J w = K w + (K' r)(w . n) n,  K' r = r S' g + S g'(u) u
+                    const float dg = -2.0f * TWO_OVER_SQRTPI_F * uu * uu * ex;
+                    const float Kr = in ? Srd * gg + S * dg * uu : 0.0f;
+                    const float nrm = r2 > 0.0f ? rinv : 0.0f;
+                    const float nx = dx * nrm, ny = dy * nrm, nz = dz * nrm;
+                    const float fx = (float)wx, fy = (float)wy, fz = (float)wz;
+                    const float wn = __builtin_fmaf(fx, nx, __builtin_fmaf(fy, ny, fz * nz));
+                    const float wd = __builtin_fmaf(fx, dx, __builtin_fmaf(fy, dy, fz * dz));
+                    const float cc = Kr * wn;
+                    const float px = qm * __builtin_fmaf(K, fx, cc * nx);
+                    const float py = qm * __builtin_fmaf(K, fy, cc * ny);
+                    const float pz = qm * __builtin_fmaf(K, fz, cc * nz);
+                    vx = px;
+                    vy = py;
+                    vz = pz;
+                    vm = K * wd;
+                    tbx -= (acc_t)px;
+                    tby -= (acc_t)py;
+                    tbz -= (acc_t)pz;
                 }
             }
             if constexpr (ADJ) {
-                // one atomic per (wave, source) after a wave reduction
+                // source terms: wave sum, then one atomic per (wave, source, component)
                 double sx, sy, sz, smass;
-                if constexpr (PREC == PR64) {
-                    sx = wave_sum<double>(vx);
-                    sy = wave_sum<double>(vy);
-                    sz = wave_sum<double>(vz);
-                    smass = wave_sum<double>(vm);
+                if constexpr (F64) {
+                    sx = wave_sum63<double>(vx);
+                    sy = wave_sum63<double>(vy);
+                    sz = wave_sum63<double>(vz);
+                    smass = wave_sum63<double>(vm);
                 } else {
-                    sx = wave_sum<float>((float)vx);
-                    sy = wave_sum<float>((float)vy);
-                    sz = wave_sum<float>((float)vz);
-                    smass = wave_sum<float>((float)vm);
+                    sx = wave_sum63<float>((float)vx);
+                    sy = wave_sum63<float>((float)vy);
+                    sz = wave_sum63<float>((float)vz);
+                    smass = wave_sum63<float>((float)vm);
                 }
-                if (lane == 0) {
+                if (lane == 63) {
                     double* dst = isp ? a.pbar + 4 * (int64_t)(src & ~ITEM_PARTICLE) : a.nbar + 4 * (int64_t)src;
                     unsafeAtomicAdd(dst + 0, sx);
                     unsafeAtomicAdd(dst + 1, sy);
@@ -393,145 +708,76 @@ __global__ __launch_bounds__(WAVE) void k_walk(WalkArgs a)
                 }
             }
         }
-        __syncthreads();
-    };
-
-    if (a.n_nodes > 0) {
-        int nl = 0;
-        uint32_t k = 0;
-        while (k < a.n_items) {
-            const Item it = a.items[k];
-            const uint32_t ref = uniform32(it.ref), depth = uniform32(it.depth), next = uniform32(it.next);
-            const uint64_t reach = depth ? uniform64(sh.open[depth - 1]) : active;
-            if (ref & ITEM_PARTICLE) {
-                const uint64_t self = __ballot(valid && (uint32_t)s_i == (ref & ~ITEM_PARTICLE));
-                const uint64_t m = reach & ~self;
-                if (m) {
-                    if (lane == 0) {
-                        sh.src[nl] = ref;
-                        sh.mask[nl] = m;
-                    }
-                    ++nl;
-                }
-                ++k;
-            } else {
-                const uint32_t nd = ref;
-                int dec = D_PRUNE;
-                if ((reach >> lane) & 1ull) {
-                    if constexpr (PREC == PR64) {
-                        const Geo64 g = a.ngeo64[nd];
-                        const Rec64 c = a.nrec64[nd];
-                        const double l = g.l;
-                        double dcx = min_image(g.cx - x64, a.box);
-                        double dcy = min_image(g.cy - y64, a.box);
-                        double dcz = min_image(g.cz - z64, a.box);
-                        double t2 = 0.0, tt;
-                        tt = fabs(dcx) - 0.5 * l;
-                        if (tt > 0) t2 += tt * tt;
-                        tt = fabs(dcy) - 0.5 * l;
-                        if (tt > 0) t2 += tt * tt;
-                        tt = fabs(dcz) - 0.5 * l;
-                        if (tt > 0) t2 += tt * tt;
-                        if (!(t2 > a.rc2 * (1.0 + 1e-6))) {
-                            bool inside = fabs(dcx) < 0.6 * l && fabs(dcy) < 0.6 * l && fabs(dcz) < 0.6 * l;
-                            double dx = min_image(c.x - x64, a.box);
-                            double dy = min_image(c.y - y64, a.box);
-                            double dz = min_image(c.z - z64, a.box);
-                            double r2 = (dx * dx + dy * dy) + dz * dz;
-                            bool open = inside || l * l > a.theta2 * r2;
-                            if (a.relative && (a.G * c.m) * (l * l) > (a.alpha * aold) * (r2 * r2)) open = true;
-                            if (mixed) {
-                                double hx = a.nhmax[nd];
-                                if (a.nhmin[nd] != hx && r2 < hx * hx) open = true;
-                            }
-                            dec = open ? D_OPEN : (r2 < a.rc2 ? D_ACCEPT : D_ACCEPT_FAR);
-                        }
-                    } else {
-                        const Rec32 c = a.nrec32[nd];
-                        const int lev = a.n_level[nd];
-                        const uint32_t half = 1u << (31 - lev);
-                        const float lt = (float)(1ull << (32 - lev));
-                        const uint64_t lint = 1ull << (32 - lev);
-                        int32_t dcx = (int32_t)(a.n_corner[3 * nd + 0] + half - X);
-                        int32_t dcy = (int32_t)(a.n_corner[3 * nd + 1] + half - Y);
-                        int32_t dcz = (int32_t)(a.n_corner[3 * nd + 2] + half - Z);
-                        uint64_t ax_ = (uint64_t)(dcx < 0 ? -(int64_t)dcx : (int64_t)dcx);
-                        uint64_t ay_ = (uint64_t)(dcy < 0 ? -(int64_t)dcy : (int64_t)dcy);
-                        uint64_t az_ = (uint64_t)(dcz < 0 ? -(int64_t)dcz : (int64_t)dcz);
-                        float tx = fmaxf((float)ax_ - 0.5f * lt, 0.0f);
-                        float ty = fmaxf((float)ay_ - 0.5f * lt, 0.0f);
-                        float tz = fmaxf((float)az_ - 0.5f * lt, 0.0f);
-                        float t2 = tx * tx + ty * ty + tz * tz;
-                        if (!(t2 > a.rc2t * 1.0001f)) {
-                            bool inside = 5 * ax_ < 3 * lint && 5 * ay_ < 3 * lint && 5 * az_ < 3 * lint;
-                            float dx = (float)(int32_t)(c.X - X);
-                            float dy = (float)(int32_t)(c.Y - Y);
-                            float dz = (float)(int32_t)(c.Z - Z);
-                            float r2 = r2_ticks(dx, dy, dz);
-                            bool open = inside || lt * lt > a.theta2f * r2;
-                            if (a.relative) {
-                                double r2d = (double)r2;
-                                if ((a.G * (double)c.m) * ((double)lt * (double)lt) > atau * (r2d * r2d)) open = true;
-                            }
-                            if (mixed) {
-                                float hx = a.nhmax32[nd];
-                                if (a.nhmin[nd] != a.nhmax[nd] && r2 < hx * hx) open = true;
-                            }
-                            dec = open ? D_OPEN : (r2 < a.rc2t ? D_ACCEPT : D_ACCEPT_FAR);
-                        }
-                    }
-                }
-                const uint64_t om = __ballot(dec == D_OPEN);
-                const uint64_t am = __ballot(dec == D_ACCEPT);
-                if (am) {
-                    if (lane == 0) {
-                        sh.src[nl] = nd;
-                        sh.mask[nl] = am;
-                    }
-                    ++nl;
-                }
-                if (om) {
-                    if (lane == 0) sh.open[depth] = om;
-                    ++k;
-                } else {
-                    k = next;
-                }
-            }
-            if (nl == CHUNK) {
-                flush(nl);
-                nl = 0;
-            }
-        }
-        if (nl) flush(nl);
+        c = cnext;
     }
-
-    if (!valid) return;
+    acc_t* pa = (acc_t*)(partials + (int64_t)u * PARTIAL_BYTES);
     if constexpr (!ADJ) {
+        pa[lane] = ax;
+        pa[64 + lane] = ay;
+        pa[128 + lane] = az;
+        int32_t* pc = (int32_t*)(pa + 192);
+        pc[lane] = npp;
+        pc[64 + lane] = npn;
+    } else {
+        pa[lane] = tbx;
+        pa[64 + lane] = tby;
+        pa[128 + lane] = tbz;
+    }
+}
+
+// ----------------------------------------------------------------------------------
+// phase 3: per group, sum the units' partials in their order and write the outputs
+// ----------------------------------------------------------------------------------
+
+template <int PREC, bool ADJ>
+__global__ __launch_bounds__(WAVE) void k_reduce(WalkArgs a, ListArgs L, const char* __restrict__ partials)
+{
+    using acc_t = typename std::conditional<PREC == PR32, float, double>::type;
+    const int lane = threadIdx.x;
+    const int64_t g = blockIdx.x;
+    const int64_t t = g * WAVE + lane;
+    if (t >= a.n_t) return;
+    acc_t ax = 0, ay = 0, az = 0;
+    int npp = 0, npn = 0;
+    for (int32_t u = L.group_head[g]; u >= 0; u = L.unit_next[u]) {
+        const acc_t* pa = (const acc_t*)(partials + (int64_t)u * PARTIAL_BYTES);
+        ax += pa[lane];
+        ay += pa[64 + lane];
+        az += pa[128 + lane];
+        if constexpr (!ADJ) {
+            const int32_t* pc = (const int32_t*)(pa + 192);
+            npp += pc[lane];
+            npn += pc[64 + lane];
+        }
+    }
+    if constexpr (ADJ) {
+        const int32_t s_i = a.tgt_sorted[t];
+        a.tbar[3 * (int64_t)s_i + 0] = (double)ax;
+        a.tbar[3 * (int64_t)s_i + 1] = (double)ay;
+        a.tbar[3 * (int64_t)s_i + 2] = (double)az;
+    } else {
+        const int64_t slot = a.tgt_slot[t];
         if constexpr (PREC == PR64) {
             double* o = (double*)a.acc;
-            o[3 * (int64_t)slot + 0] = ax;
-            o[3 * (int64_t)slot + 1] = ay;
-            o[3 * (int64_t)slot + 2] = az;
+            o[3 * slot + 0] = ax;
+            o[3 * slot + 1] = ay;
+            o[3 * slot + 2] = az;
         } else if constexpr (PREC == PR32) {
             float* o = (float*)a.acc;
             const float sc = (float)a.out_scale;
-            o[3 * (int64_t)slot + 0] = (float)ax * sc;
-            o[3 * (int64_t)slot + 1] = (float)ay * sc;
-            o[3 * (int64_t)slot + 2] = (float)az * sc;
+            o[3 * slot + 0] = ax * sc;
+            o[3 * slot + 1] = ay * sc;
+            o[3 * slot + 2] = az * sc;
         } else {
             double* o = (double*)a.acc;
-            o[3 * (int64_t)slot + 0] = (double)ax * a.out_scale;
-            o[3 * (int64_t)slot + 1] = (double)ay * a.out_scale;
-            o[3 * (int64_t)slot + 2] = (double)az * a.out_scale;
+            o[3 * slot + 0] = ax * a.out_scale;
+            o[3 * slot + 1] = ay * a.out_scale;
+            o[3 * slot + 2] = az * a.out_scale;
         }
         if (a.counts) {
-            a.counts[2 * (int64_t)slot] = npp;
-            a.counts[2 * (int64_t)slot + 1] = npn;
+            a.counts[2 * slot] = npp;
+            a.counts[2 * slot + 1] = npn;
         }
-    } else {
-        a.tbar[3 * (int64_t)s_i + 0] = (double)tbx;
-        a.tbar[3 * (int64_t)s_i + 1] = (double)tby;
-        a.tbar[3 * (int64_t)s_i + 2] = (double)tbz;
     }
 }
 
@@ -665,18 +911,96 @@ WalkArgs make_args(const sr_tree* t, const sr_params* p, int64_t n_t, const doub
     return a;
 }
 
-template <bool ADJ>
-int launch_walk(const sr_tree* t, const sr_params* p, const WalkArgs& a, hipStream_t st)
+ListArgs list_args(const sr_tree* t)
 {
-    dim3 grid((unsigned)((a.n_t + WAVE - 1) / WAVE));
-    if (a.n_t == 0) return SR_OK;
+    ListArgs L{};
+    L.ent_src = t->ent_src;
+    L.ent_mask = t->ent_mask;
+    L.chunk_next = t->chunk_next;
+    L.chunk_cnt = t->chunk_cnt;
+    L.unit_group = t->unit_group;
+    L.unit_chunk = t->unit_chunk;
+    L.unit_nch = t->unit_nch;
+    L.unit_next = t->unit_next;
+    L.group_head = t->group_head;
+    L.counters = t->list_counters;
+    L.cap_chunks = t->cap_chunks;
+    L.cap_units = t->cap_units;
+    return L;
+}
+
+bool same_lists(const sr_tree* t, const sr_params* p, int64_t n_t, const int32_t* active, const double* a_old)
+{
+    const ListKey& k = t->lkey;
+    const int dec64 = p->precision == SR_FP64;
+    return k.valid && k.gen == t->build_gen && k.dec64 == dec64 && k.G == p->G && k.r_s == p->r_s &&
+           k.r_cut == p->r_cut && k.theta == p->theta && k.alpha == p->alpha && k.criterion == p->criterion &&
+           k.n_t == n_t && k.active == (const void*)active && k.a_old == (const void*)a_old;
+}
+
+// Phase 1, growing the list buffers until every group's entries fit.
+int traverse(sr_tree* t, const sr_params* p, int64_t n_t, const int32_t* active, const double* a_old,
+             hipStream_t st)
+{
+    t->lkey.valid = false;
+    const int64_t groups = (n_t + WAVE - 1) / WAVE;
+    int64_t want = 32 * n_t;
+    if (want < (int64_t)1 << 16) want = (int64_t)1 << 16;
+    for (int attempt = 0; attempt < 8; ++attempt) {
+        int rc = sr_list_reserve(t, groups, (want + 63) / 64, (int64_t)UCH);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_fill_i32w, g256(groups), dim3(256), 0, st, t->group_head, groups, -1);
+        hipLaunchKernelGGL(k_fill_i32w, g256(4), dim3(256), 0, st, t->list_counters, (int64_t)4, 0);
+        const WalkArgs a = make_args(t, p, n_t, a_old);
+        const ListArgs L = list_args(t);
+        if (p->precision == SR_FP64) hipLaunchKernelGGL(k_traverse<true>, dim3((unsigned)groups), dim3(WAVE), 0, st, a, L);
+        else hipLaunchKernelGGL(k_traverse<false>, dim3((unsigned)groups), dim3(WAVE), 0, st, a, L);
+        SR_HIP(hipGetLastError());
+        int32_t cnt[4];
+        SR_HIP(hipMemcpyAsync(cnt, t->list_counters, sizeof(cnt), hipMemcpyDeviceToHost, st));
+        SR_HIP(hipStreamSynchronize(st));
+        if (!cnt[2]) {
+            t->n_units = cnt[1];
+            t->n_chunks = cnt[0];
+            ListKey& k = t->lkey;
+            k.valid = true;
+            k.gen = t->build_gen;
+            k.dec64 = p->precision == SR_FP64;
+            k.G = p->G;
+            k.r_s = p->r_s;
+            k.r_cut = p->r_cut;
+            k.theta = p->theta;
+            k.alpha = p->alpha;
+            k.criterion = p->criterion;
+            k.n_t = n_t;
+            k.active = active;
+            k.a_old = a_old;
+            return SR_OK;
+        }
+        want = 2 * t->cap_chunks * 64;
+    }
+    return sr_fail(SR_ENOMEM, "interaction lists did not fit after repeated growth");
+}
+
+template <bool ADJ>
+int eval_and_reduce(sr_tree* t, const sr_params* p, const WalkArgs& a, hipStream_t st)
+{
+    const int64_t groups = (a.n_t + WAVE - 1) / WAVE;
+    const ListArgs L = list_args(t);
+    const dim3 gu((unsigned)(t->n_units > 0 ? t->n_units : 1)), gg((unsigned)groups);
+    if (t->n_units > 0) {
+        switch (p->precision) {
+        case SR_FP64: hipLaunchKernelGGL((k_eval<PR64, ADJ>), gu, dim3(WAVE), 0, st, a, L, t->partials); break;
+        case SR_FP32: hipLaunchKernelGGL((k_eval<PR32, ADJ>), gu, dim3(WAVE), 0, st, a, L, t->partials); break;
+        default: hipLaunchKernelGGL((k_eval<PR32A, ADJ>), gu, dim3(WAVE), 0, st, a, L, t->partials); break;
+        }
+    }
     switch (p->precision) {
-    case SR_FP64: hipLaunchKernelGGL((k_walk<PR64, ADJ>), grid, dim3(WAVE), 0, st, a); break;
-    case SR_FP32: hipLaunchKernelGGL((k_walk<PR32, ADJ>), grid, dim3(WAVE), 0, st, a); break;
-    default: hipLaunchKernelGGL((k_walk<PR32A, ADJ>), grid, dim3(WAVE), 0, st, a); break;
+    case SR_FP64: hipLaunchKernelGGL((k_reduce<PR64, ADJ>), gg, dim3(WAVE), 0, st, a, L, t->partials); break;
+    case SR_FP32: hipLaunchKernelGGL((k_reduce<PR32, ADJ>), gg, dim3(WAVE), 0, st, a, L, t->partials); break;
+    default: hipLaunchKernelGGL((k_reduce<PR32A, ADJ>), gg, dim3(WAVE), 0, st, a, L, t->partials); break;
     }
     SR_HIP(hipGetLastError());
-    (void)t;
     return SR_OK;
 }
 
@@ -707,29 +1031,49 @@ int sr_prepare_targets(sr_tree* t, const int32_t* active, int64_t n_active, hipS
     return SR_OK;
 }
 
-int sr_walk_forward(sr_tree* t, const sr_params* p, int64_t n_t, const double* a_old, void* acc,
-                    int32_t* counts, hipStream_t st)
+int sr_walk_forward(sr_tree* t, const sr_params* p, int64_t n_t, const int32_t* active, const double* a_old,
+                    void* acc, int32_t* counts, hipStream_t st)
 {
+    if (n_t == 0) return SR_OK;
     WalkArgs a = make_args(t, p, n_t, a_old);
     a.acc = acc;
     a.counts = counts;
-    return launch_walk<false>(t, p, a, st);
+    if (t->n_nodes == 0) {
+        // a single particle: no sources, every group list is empty
+        const int64_t groups = (n_t + WAVE - 1) / WAVE;
+        int rc = sr_list_reserve(t, groups, 1, (int64_t)UCH);
+        if (rc) return rc;
+        t->n_units = 0;
+        t->lkey.valid = false;
+        hipLaunchKernelGGL(k_fill_i32w, g256(groups), dim3(256), 0, st, t->group_head, groups, -1);
+        return eval_and_reduce<false>(t, p, a, st);
+    }
+    int rc = traverse(t, p, n_t, active, a_old, st);
+    if (rc) return rc;
+    return eval_and_reduce<false>(t, p, a, st);
 }
 
-int sr_walk_adjoint(sr_tree* t, const sr_params* p, int64_t n_t, const double* a_old, const void* w,
-                    double* dLdx, double* dLdm, hipStream_t st)
+int sr_walk_adjoint(sr_tree* t, const sr_params* p, int64_t n_t, const int32_t* active, const double* a_old,
+                    const void* w, double* dLdx, double* dLdm, hipStream_t st)
 {
     const int64_t n = t->n, m = t->n_nodes;
     hipLaunchKernelGGL(k_zero_f64, g256(4 * n), dim3(256), 0, st, t->pbar, 4 * n);
     hipLaunchKernelGGL(k_zero_f64, g256(3 * n), dim3(256), 0, st, t->tbar, 3 * n);
     if (m) hipLaunchKernelGGL(k_zero_f64, g256(4 * m), dim3(256), 0, st, t->nbar, 4 * m);
-    WalkArgs a = make_args(t, p, n_t, a_old);
-    a.w = w;
-    a.pbar = t->pbar;
-    a.tbar = t->tbar;
-    a.nbar = t->nbar;
-    int rc = launch_walk<true>(t, p, a, st);
-    if (rc) return rc;
+    if (n_t > 0 && m > 0) {
+        // the forward's lists carry the frozen decisions; walk again only if they are not those of this call
+        if (!same_lists(t, p, n_t, active, a_old)) {
+            int rc = traverse(t, p, n_t, active, a_old, st);
+            if (rc) return rc;
+        }
+        WalkArgs a = make_args(t, p, n_t, a_old);
+        a.w = w;
+        a.pbar = t->pbar;
+        a.tbar = t->tbar;
+        a.nbar = t->nbar;
+        int rc = eval_and_reduce<true>(t, p, a, st);
+        if (rc) return rc;
+    }
     double sx = 1.0, sm = 1.0;
     if (p->precision != SR_FP64) {
         // FP32 terms carry masses scaled by 2^64 and integer-coordinate lengths
