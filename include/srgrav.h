@@ -121,9 +121,12 @@ int shortrange_accel(sr_tree* tree, const sr_params* p, const int32_t* active, i
 /*
  * shortrange_accel_adjoint -- gradient of L = sum_t w_t . a_t.
  *
- * The walk is repeated with the same inputs, so the tree topology, node
- * membership, opening decisions and cutoff membership are those of the forward
- * pass; L is differentiated with all of them held fixed.
+ * The tree topology, node membership, opening decisions and cutoff membership
+ * are those of the forward pass and L is differentiated with all of them held
+ * fixed: when the last shortrange_accel on this handle had the same parameters,
+ * `active` and `a_old` pointers (and the tree was not rebuilt since), its
+ * interaction lists are reused; otherwise the same deterministic walk is
+ * repeated.  The caller must not change `active` or `a_old` in between.
  *
  *   w     DEVICE [n_active*3] cotangent, same element type as `acc`
  *   dLdx  DEVICE double[n*3]  output, input order (w.r.t. the wrapped positions,
@@ -136,6 +139,19 @@ int shortrange_accel(sr_tree* tree, const sr_params* p, const int32_t* active, i
 int shortrange_accel_adjoint(sr_tree* tree, const sr_params* p, const int32_t* active,
                              int64_t n_active, const double* a_old, const void* w, double* dLdx,
                              double* dLdm, void* stream);
+
+/*
+ * sr_axpy -- y[i] += a * x[i] for i < n, the elementwise update of a
+ * kick-drift-kick leapfrog step (kick: v += dt/2 a(x); drift: x += dt v) and
+ * of its transpose in a rollout's backward pass.  (The paper's GPU steps drift
+ * every particle at the start of the step: its GPU-porting subsection and
+ * Appendix A.)  Errors: SR_EINVAL for n < 0, NULL pointers or unknown types.
+ *
+ *   y       DEVICE, element type y_type (SR_F64 or SR_F32), n elements, updated in place
+ *   x       DEVICE, element type x_type, n elements (may not alias y)
+ */
+enum { SR_F64 = 0, SR_F32 = 1 };
+int sr_axpy(void* y, int32_t y_type, const void* x, int32_t x_type, double a, int64_t n, void* stream);
 
 /* Internal arrays of a built tree, copied into caller buffers (DEVICE; any may
  * be NULL).  Node arrays need room for tree_node_count() entries. */

@@ -20,7 +20,7 @@ SR_FP64, SR_FP32, SR_FP32_ACC64 = 0, 1, 2
 PRECISIONS = {"fp64": SR_FP64, "fp32": SR_FP32, "fp32_acc64": SR_FP32_ACC64}
 CRITERIA = {"bh": SR_OPEN_BH, "relative": SR_OPEN_RELATIVE}
 EXPORTED = ("tree_build", "shortrange_accel", "shortrange_accel_adjoint", "tree_node_count",
-            "tree_export", "tree_free", "srgrav_last_error")
+            "tree_export", "tree_free", "srgrav_last_error", "sr_axpy")
 
 
 class SrgravError(RuntimeError):
@@ -58,6 +58,8 @@ def lib():
         L.shortrange_accel_adjoint.argtypes = [vp, C.POINTER(SrParams), vp, i64, vp, vp, vp, vp, vp]
         L.tree_node_count.argtypes = [vp, C.POINTER(i64)]
         L.tree_export.argtypes = [vp, C.POINTER(SrTreeExport), vp]
+        L.sr_axpy.argtypes = [vp, C.c_int32, vp, C.c_int32, d, i64, vp]
+        L.sr_axpy.restype = C.c_int
         L.tree_free.argtypes = [vp]
         L.tree_free.restype = None
         L.srgrav_last_error.restype = C.c_char_p

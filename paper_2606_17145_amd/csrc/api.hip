@@ -354,6 +354,17 @@ int tree_export(const sr_tree* t, const sr_tree_export* ex, void* stream)
     return SR_OK;
 }
 
+int sr_axpy(void* y, int32_t y_type, const void* x, int32_t x_type, double a, int64_t n, void* stream)
+{
+    g_err[0] = 0;
+    if (n < 0) return sr_fail(SR_EINVAL, "n must be >= 0");
+    if (n == 0) return SR_OK;
+    if (!y || !x) return sr_fail(SR_EINVAL, "x and y are required");
+    if ((y_type != SR_F64 && y_type != SR_F32) || (x_type != SR_F64 && x_type != SR_F32))
+        return sr_fail(SR_EINVAL, "element types must be SR_F64 or SR_F32");
+    return sr_axpy_device(y, y_type, x, x_type, a, n, (hipStream_t)stream);
+}
+
 void tree_free(sr_tree* t)
 {
     if (!t) return;

@@ -151,5 +151,8 @@ int sr_walk_forward(sr_tree* t, const sr_params* p, int64_t n_t, const int32_t* 
 int sr_walk_adjoint(sr_tree* t, const sr_params* p, int64_t n_t, const int32_t* active, const double* a_old,
                     const void* w, double* dLdx, double* dLdm, hipStream_t st);
 
+// walk.hip: elementwise y += a x
+int sr_axpy_device(void* y, int y_type, const void* x, int x_type, double a, int64_t n, hipStream_t st);
+
 // api.hip: make room for the lists of `groups` target groups and `chunks` chunks
 int sr_list_reserve(sr_tree* t, int64_t groups, int64_t chunks, int64_t chunks_per_unit);

@@ -386,8 +386,13 @@ __global__ __launch_bounds__(WAVE) void k_traverse(WalkArgs a, ListArgs L)
     };
 
     uint64_t openv = 0;   // lane d: open mask of the path node at depth d
-    uint32_t k = 0, w0 = 0xffffffffu;
+    uint32_t k = 0, w0 = 0xffffffffu, iters = 0;
     while (k < a.n_items && !overflow) {
+        // the longest traversals set the kernel's duration: raise their issue priority as they age
+        ++iters;
+        if (iters == 1024u) __builtin_amdgcn_s_setprio(1);
+        if (iters == 2048u) __builtin_amdgcn_s_setprio(2);
+        if (iters == 3072u) __builtin_amdgcn_s_setprio(3);
         if (k < w0 || k - w0 >= (uint32_t)WIN) {
             load_window(k);
             w0 = k;
@@ -417,67 +422,58 @@ __global__ __launch_bounds__(WAVE) void k_traverse(WalkArgs a, ListArgs L)
             k += R;
             continue;
         }
-        int dec = D_PRUNE;
-        if ((reach >> lane) & 1ull) {
-            if constexpr (DEC64) {
-                const double l = rld(wn.l, j);
-                const double dcx = min_image(rld(wn.cx, j) - x64, a.box);
-                const double dcy = min_image(rld(wn.cy, j) - y64, a.box);
-                const double dcz = min_image(rld(wn.cz, j) - z64, a.box);
-                double t2 = 0.0, tt;
-                tt = fabs(dcx) - 0.5 * l;
-                if (tt > 0) t2 += tt * tt;
-                tt = fabs(dcy) - 0.5 * l;
-                if (tt > 0) t2 += tt * tt;
-                tt = fabs(dcz) - 0.5 * l;
-                if (tt > 0) t2 += tt * tt;
-                if (!(t2 > a.rc2 * (1.0 + 1e-6))) {
-                    const bool inside = fabs(dcx) < 0.6 * l && fabs(dcy) < 0.6 * l && fabs(dcz) < 0.6 * l;
-                    const double dx = min_image(rld(wn.X, j) - x64, a.box);
-                    const double dy = min_image(rld(wn.Y, j) - y64, a.box);
-                    const double dz = min_image(rld(wn.Z, j) - z64, a.box);
-                    const double r2 = (dx * dx + dy * dy) + dz * dz;
-                    bool open = inside || l * l > a.theta2 * r2;
-                    if (a.relative && (a.G * rld(wn.M, j)) * (l * l) > (a.alpha * aold) * (r2 * r2)) open = true;
-                    if (mixed) {
-                        const double hx = rld(wn.hx, j);
-                        if (rld(wn.hn, j) != hx && r2 < hx * hx) open = true;
-                    }
-                    dec = open ? D_OPEN : (r2 < a.rc2 ? D_ACCEPT : D_ACCEPT_FAR);
-                }
-            } else {
-                const int32_t dcx = (int32_t)(rl(wn.cX, j) - X);
-                const int32_t dcy = (int32_t)(rl(wn.cY, j) - Y);
-                const int32_t dcz = (int32_t)(rl(wn.cZ, j) - Z);
-                const uint32_t bx = dcx < 0 ? 0u - (uint32_t)dcx : (uint32_t)dcx;
-                const uint32_t by = dcy < 0 ? 0u - (uint32_t)dcy : (uint32_t)dcy;
-                const uint32_t bz = dcz < 0 ? 0u - (uint32_t)dcz : (uint32_t)dcz;
-                const float half = rlf(wn.half, j);
-                const float tx = fmaxf((float)bx - half, 0.0f);
-                const float ty = fmaxf((float)by - half, 0.0f);
-                const float tz = fmaxf((float)bz - half, 0.0f);
-                const float t2 = __builtin_fmaf(tx, tx, __builtin_fmaf(ty, ty, tz * tz));
-                if (!(t2 > a.rc2t * 1.0001f)) {
-                    const uint32_t tin = rl(wn.tin, j);
-                    const bool inside = bx <= tin && by <= tin && bz <= tin;
-                    const float dx = (float)(int32_t)(rl(wn.X, j) - X);
-                    const float dy = (float)(int32_t)(rl(wn.Y, j) - Y);
-                    const float dz = (float)(int32_t)(rl(wn.Z, j) - Z);
-                    const float r2 = r2_ticks(dx, dy, dz);
-                    const float l2 = rlf(wn.l2, j);
-                    bool open = inside || l2 > a.theta2f * r2;
-                    if (a.relative) {
-                        const double r2d = (double)r2;
-                        if ((a.G * (double)rlf(wn.M, j)) * (double)l2 > atau * (r2d * r2d)) open = true;
-                    }
-                    if (mixed) {
-                        const float hx = rlf(wn.hx, j);
-                        if (rl(wn.mixed, j) && r2 < hx * hx) open = true;
-                    }
-                    dec = open ? D_OPEN : (r2 < a.rc2t ? D_ACCEPT : D_ACCEPT_FAR);
-                }
+        // decisions of every lane, branch-free (lanes outside `reach` are masked by the ballots)
+        bool keep, open, near;
+        if constexpr (DEC64) {
+            const double l = rld(wn.l, j);
+            const double dcx = min_image(rld(wn.cx, j) - x64, a.box);
+            const double dcy = min_image(rld(wn.cy, j) - y64, a.box);
+            const double dcz = min_image(rld(wn.cz, j) - z64, a.box);
+            const double tx = fmax(fabs(dcx) - 0.5 * l, 0.0);
+            const double ty = fmax(fabs(dcy) - 0.5 * l, 0.0);
+            const double tz = fmax(fabs(dcz) - 0.5 * l, 0.0);
+            keep = !((tx * tx + ty * ty) + tz * tz > a.rc2 * (1.0 + 1e-6));
+            const bool inside = fabs(dcx) < 0.6 * l && fabs(dcy) < 0.6 * l && fabs(dcz) < 0.6 * l;
+            const double dx = min_image(rld(wn.X, j) - x64, a.box);
+            const double dy = min_image(rld(wn.Y, j) - y64, a.box);
+            const double dz = min_image(rld(wn.Z, j) - z64, a.box);
+            const double r2 = (dx * dx + dy * dy) + dz * dz;
+            open = inside || l * l > a.theta2 * r2;
+            if (a.relative) open = open || (a.G * rld(wn.M, j)) * (l * l) > (a.alpha * aold) * (r2 * r2);
+            if (mixed) {
+                const double hx = rld(wn.hx, j);
+                open = open || (rld(wn.hn, j) != hx && r2 < hx * hx);
             }
+            near = r2 < a.rc2;
+        } else {
+            const uint32_t bx = (uint32_t)abs((int32_t)(rl(wn.cX, j) - X));
+            const uint32_t by = (uint32_t)abs((int32_t)(rl(wn.cY, j) - Y));
+            const uint32_t bz = (uint32_t)abs((int32_t)(rl(wn.cZ, j) - Z));
+            const float half = rlf(wn.half, j);
+            const float tx = fmaxf((float)bx - half, 0.0f);
+            const float ty = fmaxf((float)by - half, 0.0f);
+            const float tz = fmaxf((float)bz - half, 0.0f);
+            keep = !(__builtin_fmaf(tx, tx, __builtin_fmaf(ty, ty, tz * tz)) > a.rc2t * 1.0001f);
+            const uint32_t tin = rl(wn.tin, j);
+            const bool inside = bx <= tin && by <= tin && bz <= tin;
+            const float dx = (float)(int32_t)(rl(wn.X, j) - X);
+            const float dy = (float)(int32_t)(rl(wn.Y, j) - Y);
+            const float dz = (float)(int32_t)(rl(wn.Z, j) - Z);
+            const float r2 = r2_ticks(dx, dy, dz);
+            const float l2 = rlf(wn.l2, j);
+            open = inside || l2 > a.theta2f * r2;
+            if (a.relative) {
+                const double r2d = (double)r2;
+                open = open || (a.G * (double)rlf(wn.M, j)) * (double)l2 > atau * (r2d * r2d);
+            }
+            if (mixed) {
+                const float hx = rlf(wn.hx, j);
+                open = open || (rl(wn.mixed, j) && r2 < hx * hx);
+            }
+            near = r2 < a.rc2t;
         }
+        const bool live = ((reach >> lane) & 1ull) && keep;
+        const int dec = !live ? D_PRUNE : (open ? D_OPEN : (near ? D_ACCEPT : D_ACCEPT_FAR));
         const uint64_t om = __ballot(dec == D_OPEN);
         const uint64_t am = __ballot(dec == D_ACCEPT);
         if (am) {
@@ -817,6 +813,13 @@ __global__ void k_pushdown(int64_t n, const int32_t* __restrict__ perm, const in
     dLdm[j] = gm;
 }
 
+template <class Y, class X>
+__global__ void k_axpy(Y* __restrict__ y, const X* __restrict__ x, double a, int64_t n)
+{
+    const int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x;
+    if (i < n) y[i] = (Y)((double)y[i] + a * (double)x[i]);
+}
+
 __global__ void k_zero_f64(double* p, int64_t n)
 {
     int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x;
@@ -1028,6 +1031,17 @@ int sr_prepare_targets(sr_tree* t, const int32_t* active, int64_t n_active, hipS
     SR_HIP(hipStreamSynchronize(st));
     if (flags & 2) return sr_fail(SR_EINVAL, "active: index out of range [0, n)");
     if (flags & 4) return sr_fail(SR_EINVAL, "active: repeated index");
+    return SR_OK;
+}
+
+int sr_axpy_device(void* y, int y_type, const void* x, int x_type, double a, int64_t n, hipStream_t st)
+{
+    const dim3 g = g256(n);
+    if (y_type == SR_F64 && x_type == SR_F64) hipLaunchKernelGGL((k_axpy<double, double>), g, dim3(256), 0, st, (double*)y, (const double*)x, a, n);
+    else if (y_type == SR_F64) hipLaunchKernelGGL((k_axpy<double, float>), g, dim3(256), 0, st, (double*)y, (const float*)x, a, n);
+    else if (x_type == SR_F64) hipLaunchKernelGGL((k_axpy<float, double>), g, dim3(256), 0, st, (float*)y, (const double*)x, a, n);
+    else hipLaunchKernelGGL((k_axpy<float, float>), g, dim3(256), 0, st, (float*)y, (const float*)x, a, n);
+    SR_HIP(hipGetLastError());
     return SR_OK;
 }
 

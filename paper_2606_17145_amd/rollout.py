@@ -1,0 +1,98 @@
+"""Kick-drift-kick leapfrog rollouts of the short-range force, differentiated
+with checkpointing and recomputation of the tree.
+
+One step (state x, v; the state is kept unwrapped, only the tree wraps):
+
+    v_half = v + dt/2 a(x)
+    x'     = x + dt v_half        (tree rebuilt at x')
+    v'     = v_half + dt/2 a(x')
+
+The backward pass walks the steps in reverse.  For step k it restores the
+checkpoint (x_k, v_k), rebuilds the trees at x_k and x_k' and re-runs the two
+forward walks (so the adjoint walks see the forward's decisions), then applies
+the transposed step:
+
+    x'bar += A'(x')^T (dt/2 v'bar),  v_half bar = v'bar + dt x'bar,
+    x bar  = x'bar + A'(x)^T (dt/2 v_half bar),  v bar = v_half bar.
+
+Every arithmetic step runs in the HIP library: the force and its adjoint
+(shortrange_accel / shortrange_accel_adjoint) and the elementwise updates
+(sr_axpy).  This module only sequences the calls and holds the checkpoints.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import torch
+
+from . import _lib
+from . import Tree, shortrange_accel, shortrange_accel_adjoint
+
+
+def _axpy(y: torch.Tensor, x: torch.Tensor, a: float):
+    """y += a x on the device (sr_axpy)."""
+    codes = {torch.float64: 0, torch.float32: 1}
+    assert y.is_contiguous() and x.is_contiguous() and y.numel() == x.numel()
+    with torch.cuda.device(y.device):
+        _lib.check(_lib.lib().sr_axpy(_lib.ptr(y), codes[y.dtype], _lib.ptr(x), codes[x.dtype], float(a),
+                                      y.numel(), _lib.stream_handle()))
+
+
+def _accel(tree: Tree, x, mass, eps, params, box):
+    tree.build(x, mass, eps=eps, box=box)
+    a, _ = shortrange_accel(tree, params, counts=False)
+    return a
+
+
+def kdk_rollout(pos, vel, mass, eps, params: dict, n_steps: int, dt: float, box: float = 1.0,
+                checkpoints: bool = False):
+    """Forward rollout.  Returns (x, v) after n_steps, plus the list of (x_k, v_k)
+    checkpoints when `checkpoints` is set.  a(x_{k+1}) of one step's closing kick
+    is the next step's opening kick, so n_steps + 1 force evaluations are made."""
+    x = pos.detach().to(torch.float64).contiguous().clone()
+    v = vel.detach().to(torch.float64).contiguous().clone()
+    tree = Tree()
+    saved = []
+    a = _accel(tree, x, mass, eps, params, box)
+    for _ in range(n_steps):
+        if checkpoints:
+            saved.append((x.clone(), v.clone()))
+        _axpy(v, a, 0.5 * dt)
+        _axpy(x, v, dt)
+        a = _accel(tree, x, mass, eps, params, box)
+        _axpy(v, a, 0.5 * dt)
+    return (x, v, saved) if checkpoints else (x, v)
+
+
+def kdk_rollout_grad(pos, vel, mass, eps, params: dict, n_steps: int, dt: float, wx, wv=None,
+                     box: float = 1.0):
+    """Gradient of L = sum(wx . x_final) + sum(wv . v_final) with respect to the
+    initial positions and velocities.  Returns (dL/dx0, dL/dv0, x_final, v_final)."""
+    x_fin, v_fin, saved = kdk_rollout(pos, vel, mass, eps, params, n_steps, dt, box, checkpoints=True)
+    dev = x_fin.device
+    wdt = torch.float32 if params.get("precision", "fp64") == "fp32" else torch.float64
+    xb = wx.detach().to(torch.float64).contiguous().clone()
+    vb = (torch.zeros_like(xb) if wv is None else wv.detach().to(torch.float64).contiguous().clone())
+    t0, t1 = Tree(), Tree()
+    w = torch.empty(xb.shape, dtype=wdt, device=dev)
+    for k in reversed(range(n_steps)):
+        x0, v0 = saved[k]
+        # recompute step k: trees and forward walks at x0 and x1
+        a0 = _accel(t0, x0, mass, eps, params, box)
+        x1 = x0.clone()
+        vh = v0.clone()
+        _axpy(vh, a0, 0.5 * dt)
+        _axpy(x1, vh, dt)
+        _accel(t1, x1, mass, eps, params, box)
+        # closing kick: v' = v_half + dt/2 a(x1)
+        w.zero_()
+        _axpy(w, vb, 0.5 * dt)
+        g1, _ = shortrange_accel_adjoint(t1, params, w)
+        _axpy(xb, g1, 1.0)                      # x1 bar
+        _axpy(vb, xb, dt)                       # v_half bar = v' bar + dt x1 bar
+        # opening kick: v_half = v + dt/2 a(x0)
+        w.zero_()
+        _axpy(w, vb, 0.5 * dt)
+        g0, _ = shortrange_accel_adjoint(t0, params, w)
+        _axpy(xb, g0, 1.0)                      # x0 bar = x1 bar + A'(x0)^T w
+    return xb, vb, x_fin, v_fin

@@ -1,0 +1,69 @@
+"""Checkpointed leapfrog rollouts on the GPU against the oracle's rollouts."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2606_17145_amd import workloads as WL
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def rl():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2606_17145_amd import rollout
+    return rollout
+
+
+def _case(n=4000, seed=41):
+    rng = np.random.default_rng(seed)
+    w = WL.clustered(n, seed=seed, n_spheres=6)
+    w.eps = np.where(rng.random(n) < 0.5, w.eps, w.eps / 4)
+    vel = 0.2 * rng.standard_normal((n, 3))
+    return w, vel
+
+
+def _t(a):
+    return torch.tensor(a, device=DEV)
+
+
+def test_rollout_fp64_matches_oracle(rl, oracle):
+    from oracle import rollout as R
+    w, vel = _case()
+    p = w.params("fp64")
+    print(f"rollout fp64: N={w.n}, 2 steps", flush=True)
+    x, v = rl.kdk_rollout(_t(w.pos), _t(vel), _t(w.mass), _t(w.eps), p, 2, 1e-3)
+    xr, vr = R.rollout(w.pos, vel, w.mass, w.eps, p, 2, 1e-3)
+    assert np.allclose(x.cpu().numpy(), xr, rtol=0, atol=1e-14)
+    assert np.allclose(v.cpu().numpy(), vr, rtol=1e-11, atol=1e-11 * np.abs(vr).max())
+
+
+def test_rollout_gradient_fp64_matches_oracle(rl, oracle):
+    from oracle import rollout as R
+    w, vel = _case(n=3000, seed=42)
+    p = w.params("fp64")
+    wx = np.random.default_rng(43).standard_normal((w.n, 3))
+    print(f"rollout gradient fp64: N={w.n}, 3 steps", flush=True)
+    gx, gv, _, _ = rl.kdk_rollout_grad(_t(w.pos), _t(vel), _t(w.mass), _t(w.eps), p, 3, 1e-3, _t(wx))
+    rx, rv = R.rollout_grad(w.pos, vel, w.mass, w.eps, p, 3, 1e-3, wx)
+    assert np.allclose(gx.cpu().numpy(), rx, rtol=1e-9, atol=1e-10 * np.abs(rx).max())
+    assert np.allclose(gv.cpu().numpy(), rv, rtol=1e-9, atol=1e-10 * np.abs(rv).max())
+
+
+def test_zoom_rollout_fp32_close_to_fp64(rl, oracle):
+    from oracle import rollout as R
+    w = WL.zoom_small()
+    vel = w.extra["vel"]
+    print(f"zoom rollout: N={w.n}, 1 step fp64 vs oracle, fp32 vs fp64", flush=True)
+    x64, v64 = rl.kdk_rollout(_t(w.pos), _t(vel), _t(w.mass), _t(w.eps), w.params("fp64"), 1, 1e-3)
+    xr, vr = R.rollout(w.pos, vel, w.mass, w.eps, w.params("fp64"), 1, 1e-3)
+    assert np.allclose(x64.cpu().numpy(), xr, rtol=0, atol=1e-14)
+    nr = np.linalg.norm(vr, axis=1)
+    ev = np.linalg.norm(v64.cpu().numpy() - vr, axis=1) / np.maximum(nr, 1e-6 * np.median(nr))
+    assert ev.max() < 1e-10
+    x32, v32 = rl.kdk_rollout(_t(w.pos), _t(vel), _t(w.mass), _t(w.eps), w.params("fp32"), 1, 1e-3)
+    e32 = np.linalg.norm(v32.cpu().numpy() - vr, axis=1) / np.maximum(nr, 1e-6 * np.median(nr))
+    print(f"   fp32 velocity error median {np.median(e32):.2e} p99.9 {np.quantile(e32, 0.999):.2e}", flush=True)
+    assert np.median(e32) < 1e-5 and np.quantile(e32, 0.999) < 1e-4
