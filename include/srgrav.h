@@ -153,6 +153,27 @@ int shortrange_accel_adjoint(sr_tree* tree, const sr_params* p, const int32_t* a
 enum { SR_F64 = 0, SR_F32 = 1 };
 int sr_axpy(void* y, int32_t y_type, const void* x, int32_t x_type, double a, int64_t n, void* stream);
 
+/*
+ * Phase timing with HIP events recorded on the launch stream around every
+ * phase of the path (for profiling; off by default).  srgrav_timing(1) resets
+ * the accumulators and starts recording, srgrav_timing(0) stops;
+ * srgrav_timing_read() waits for the recorded events and returns, per phase,
+ * the summed duration in milliseconds and the number of launches.
+ *   ms, calls  HOST arrays of SR_T_COUNT entries
+ */
+enum {
+    SR_T_BUILD = 0,        /* tree_build: keys, sort, topology, moments */
+    SR_T_TRAVERSE = 1,     /* walk decisions -> interaction lists */
+    SR_T_EVAL = 2,         /* pair forces of the lists */
+    SR_T_REDUCE = 3,       /* per-target sums of the evaluation units */
+    SR_T_ADJ_EVAL = 4,     /* adjoint pair terms */
+    SR_T_ADJ_REDUCE = 5,   /* per-target adjoint sums */
+    SR_T_PUSHDOWN = 6,     /* node adjoints to particles */
+    SR_T_COUNT = 7
+};
+int srgrav_timing(int32_t enable);
+int srgrav_timing_read(double* ms, int64_t* calls);
+
 /* Internal arrays of a built tree, copied into caller buffers (DEVICE; any may
  * be NULL).  Node arrays need room for tree_node_count() entries. */
 typedef struct {

@@ -20,7 +20,9 @@ SR_FP64, SR_FP32, SR_FP32_ACC64 = 0, 1, 2
 PRECISIONS = {"fp64": SR_FP64, "fp32": SR_FP32, "fp32_acc64": SR_FP32_ACC64}
 CRITERIA = {"bh": SR_OPEN_BH, "relative": SR_OPEN_RELATIVE}
 EXPORTED = ("tree_build", "shortrange_accel", "shortrange_accel_adjoint", "tree_node_count",
-            "tree_export", "tree_free", "srgrav_last_error", "sr_axpy")
+            "tree_export", "tree_free", "srgrav_last_error", "sr_axpy", "srgrav_timing",
+            "srgrav_timing_read")
+PHASES = ("tree_build", "traverse", "eval", "reduce", "adjoint_eval", "adjoint_reduce", "pushdown")
 
 
 class SrgravError(RuntimeError):
@@ -60,6 +62,10 @@ def lib():
         L.tree_export.argtypes = [vp, C.POINTER(SrTreeExport), vp]
         L.sr_axpy.argtypes = [vp, C.c_int32, vp, C.c_int32, d, i64, vp]
         L.sr_axpy.restype = C.c_int
+        L.srgrav_timing.argtypes = [C.c_int32]
+        L.srgrav_timing.restype = C.c_int
+        L.srgrav_timing_read.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        L.srgrav_timing_read.restype = C.c_int
         L.tree_free.argtypes = [vp]
         L.tree_free.restype = None
         L.srgrav_last_error.restype = C.c_char_p
@@ -87,3 +93,16 @@ def make_params(params: dict) -> SrParams:
     return SrParams(float(params.get("G", 1.0)), float(params["r_s"]), float(params["r_cut"]),
                     CRITERIA[params.get("criterion", "bh")], float(params.get("theta", 0.5)),
                     float(params.get("alpha", 0.0)), PRECISIONS[params.get("precision", "fp64")])
+
+
+def timing(enable: bool):
+    """Start (resetting) or stop phase timing with HIP events in the library."""
+    check(lib().srgrav_timing(1 if enable else 0))
+
+
+def timing_read() -> dict:
+    """{phase: (total_ms, launches)} of the phases timed since timing(True)."""
+    ms = (C.c_double * len(PHASES))()
+    calls = (C.c_int64 * len(PHASES))()
+    check(lib().srgrav_timing_read(ms, calls))
+    return {name: (ms[k], calls[k]) for k, name in enumerate(PHASES)}

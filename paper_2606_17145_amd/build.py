@@ -14,7 +14,7 @@ SOURCES = ["api.hip", "build.hip", "walk.hip"]
 # bit, so nothing may be fused behind the source's back (FP32 code asks for FMA
 # explicitly).  Packed FP32 instructions are disabled on purpose.
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
-         "-munsafe-fp-atomics", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-munsafe-fp-atomics", "-mllvm", "-amdgpu-atomic-optimizer-strategy=None", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function"]
 
 

@@ -6,12 +6,26 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
+#include <vector>
 
 #include "internal.h"
 
 namespace {
 thread_local char g_err[512] = "";
+
+// phase timing state (process-wide)
+struct TimedLaunch {
+    int phase;
+    hipEvent_t start, stop;
+};
+std::mutex g_tmu;
+bool g_timing = false;
+std::vector<TimedLaunch> g_pending;
+std::vector<hipEvent_t> g_open(SR_T_COUNT, nullptr);
+double g_ms[SR_T_COUNT] = {};
+int64_t g_calls[SR_T_COUNT] = {};
 
 template <class T>
 int alloc(T** p, int64_t count)
@@ -95,6 +109,8 @@ void free_workspace(sr_tree* t)
     release(t->nrec32);
     release(t->nhmax32);
     release(t->items);
+    release(t->n_kids);
+    release(t->n_meta);
     release(t->tgt_sorted);
     release(t->tgt_slot);
     release(t->mark);
@@ -105,6 +121,8 @@ void free_workspace(sr_tree* t)
     release(t->nbar);
     t->cap = 0;
     free_lists(t);
+    release(t->frontier);
+    t->cap_front = t->n_front_waves = 0;
 }
 
 int allocate_workspace(sr_tree* t, int64_t cap)
@@ -160,6 +178,8 @@ int allocate_workspace(sr_tree* t, int64_t cap)
     A(t->nrec32, nodes);
     A(t->nhmax32, nodes);
     A(t->items, 2 * cap);
+    A(t->n_kids, 8 * nodes);
+    A(t->n_meta, nodes);
     A(t->tgt_sorted, cap);
     A(t->tgt_slot, cap);
     A(t->mark, cap);
@@ -205,6 +225,22 @@ int check_call(sr_tree* t, const sr_params* p, const int32_t* active, int64_t n_
 }
 }  // namespace
 
+int sr_front_reserve(sr_tree* t, int64_t waves, int64_t cap)
+{
+    if (waves <= t->n_front_waves && cap <= t->cap_front) return SR_OK;
+    SR_HIP(hipDeviceSynchronize());
+    release(t->frontier);
+    // per wave: two levels of node ids (u32) and masks (u64)
+    int rc = alloc(&t->frontier, waves * cap * 6);
+    if (rc) {
+        t->cap_front = t->n_front_waves = 0;
+        return rc;
+    }
+    t->n_front_waves = waves;
+    t->cap_front = cap;
+    return SR_OK;
+}
+
 int sr_list_reserve(sr_tree* t, int64_t groups, int64_t chunks, int64_t chunks_per_unit)
 {
     const int64_t units = groups + chunks / chunks_per_unit + 1;
@@ -234,6 +270,25 @@ int sr_list_reserve(sr_tree* t, int64_t groups, int64_t chunks, int64_t chunks_p
     t->cap_chunks = chunks;
     t->cap_units = units;
     return SR_OK;
+}
+
+bool sr_timing_on() { return g_timing; }
+
+void sr_timing_mark(int phase, bool start, hipStream_t st)
+{
+    std::lock_guard<std::mutex> lk(g_tmu);
+    if (!g_timing) return;
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    (void)hipEventRecord(e, st);
+    if (start) {
+        g_open[phase] = e;
+    } else if (g_open[phase]) {
+        g_pending.push_back(TimedLaunch{phase, g_open[phase], e});
+        g_open[phase] = nullptr;
+    } else {
+        (void)hipEventDestroy(e);
+    }
 }
 
 int sr_fail(int code, const char* fmt, ...)
@@ -282,7 +337,9 @@ int tree_build(const double* pos, const double* mass, const double* eps, double 
     t->n = n;
     t->box = box;
     ++t->build_gen;
+    sr_timing_mark(SR_T_BUILD, true, st);
     int rc = sr_build_device(t, pos, mass, eps, eps_scalar, st);
+    sr_timing_mark(SR_T_BUILD, false, st);
     if (rc) {
         t->n = 0;
         if (fresh) {
@@ -363,6 +420,43 @@ int sr_axpy(void* y, int32_t y_type, const void* x, int32_t x_type, double a, in
     if ((y_type != SR_F64 && y_type != SR_F32) || (x_type != SR_F64 && x_type != SR_F32))
         return sr_fail(SR_EINVAL, "element types must be SR_F64 or SR_F32");
     return sr_axpy_device(y, y_type, x, x_type, a, n, (hipStream_t)stream);
+}
+
+int srgrav_timing(int32_t enable)
+{
+    std::lock_guard<std::mutex> lk(g_tmu);
+    for (auto& p : g_pending) {
+        (void)hipEventDestroy(p.start);
+        (void)hipEventDestroy(p.stop);
+    }
+    g_pending.clear();
+    for (auto& e : g_open)
+        if (e) (void)hipEventDestroy(e), e = nullptr;
+    if (enable)
+        for (int k = 0; k < SR_T_COUNT; ++k) g_ms[k] = 0.0, g_calls[k] = 0;
+    g_timing = enable != 0;
+    return SR_OK;
+}
+
+int srgrav_timing_read(double* ms, int64_t* calls)
+{
+    if (!ms || !calls) return sr_fail(SR_EINVAL, "ms and calls are required");
+    std::lock_guard<std::mutex> lk(g_tmu);
+    for (auto& p : g_pending) {
+        float x = 0.0f;
+        SR_HIP(hipEventSynchronize(p.stop));
+        SR_HIP(hipEventElapsedTime(&x, p.start, p.stop));
+        g_ms[p.phase] += x;
+        g_calls[p.phase] += 1;
+        (void)hipEventDestroy(p.start);
+        (void)hipEventDestroy(p.stop);
+    }
+    g_pending.clear();
+    for (int k = 0; k < SR_T_COUNT; ++k) {
+        ms[k] = g_ms[k];
+        calls[k] = g_calls[k];
+    }
+    return SR_OK;
 }
 
 void tree_free(sr_tree* t)

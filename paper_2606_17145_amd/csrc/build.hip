@@ -455,7 +455,8 @@ __global__ void k_moments(const int32_t* __restrict__ order, int64_t count, doub
                           const Rec64* __restrict__ r64, const double* __restrict__ h64,
                           Rec64* __restrict__ nrec64, double* __restrict__ nS, Geo64* __restrict__ geo,
                           double* __restrict__ nhmax, double* __restrict__ nhmin,
-                          Rec32* __restrict__ nrec32, float* __restrict__ nhmax32)
+                          Rec32* __restrict__ nrec32, float* __restrict__ nhmax32, uint32_t* __restrict__ kids,
+                          uint32_t* __restrict__ meta, const int32_t* __restrict__ n_count)
 {
     int64_t t = blockIdx.x * (int64_t)TPB + threadIdx.x;
     if (t >= count) return;
@@ -464,8 +465,17 @@ __global__ void k_moments(const int32_t* __restrict__ order, int64_t count, doub
     uint32_t end = items[it].next;
     double M = 0.0, S0 = 0.0, S1 = 0.0, S2 = 0.0, hx = 0.0, hn = 0.0;
     bool first = true;
+    // child table: up to 8 children in digit order; a bucket (level 30) keeps its particle range
+    const bool bucket = n_level[nd] == 30;
+    uint32_t nk = 0;
+    if (bucket) {
+        kids[8 * (int64_t)nd + 0] = (uint32_t)n_first[nd];
+        kids[8 * (int64_t)nd + 1] = (uint32_t)n_count[nd];
+    }
     for (uint32_t j = it + 1; j < end;) {
         Item c = items[j];
+        if (!bucket) kids[8 * (int64_t)nd + nk] = c.ref;
+        ++nk;
         double cm, c0, c1, c2, cx, cn;
         if (c.ref & ITEM_PARTICLE) {
             Rec64 p = r64[c.ref & ~ITEM_PARTICLE];
@@ -518,6 +528,7 @@ __global__ void k_moments(const int32_t* __restrict__ order, int64_t count, doub
     for (int k = 0; k < 3; ++k) q[k] = (uint32_t)(uint64_t)rint(com[k] / box * TWO32);
     nrec32[nd] = Rec32{q[0], q[1], q[2], (float)M};
     nhmax32[nd] = (float)(hx / box * TWO32);
+    meta[nd] = bucket ? META_BUCKET : nk;
 }
 
 __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v)
@@ -626,7 +637,7 @@ int sr_build_device(sr_tree* t, const double* pos, const double* mass, const dou
         if (!cnt) continue;
         hipLaunchKernelGGL(k_moments, grid_for(cnt), dim3(TPB), 0, st, t->depth_order + offs[d], cnt, box, t->items,
                            t->n_first, t->n_level, t->n_corner, t->prec64, t->ph64, t->nrec64, t->nS, t->ngeo64,
-                           t->nhmax, t->nhmin, t->nrec32, t->nhmax32);
+                           t->nhmax, t->nhmin, t->nrec32, t->nhmax32, t->n_kids, t->n_meta, t->n_count);
     }
     SR_HIP(hipGetLastError());
     // the host copy of the offsets must outlive the copy above

@@ -40,6 +40,9 @@ struct Item {
 };
 
 #define ITEM_PARTICLE 0x80000000u
+// node meta word: number of children (<= 8), or META_BUCKET for a level-30 bucket
+// whose children are the particles kids[0] .. kids[0] + kids[1] - 1
+#define META_BUCKET 0x100u
 #define SR_MAX_DEPTH 32
 #define SR_N_MAX (int64_t(1) << 30)
 
@@ -101,6 +104,8 @@ struct sr_tree {
     Rec32* nrec32 = nullptr;
     float* nhmax32 = nullptr;
     Item* items = nullptr;
+    uint32_t* n_kids = nullptr;       // 8 per node: children (node index or particle | ITEM_PARTICLE)
+    uint32_t* n_meta = nullptr;
 
     // walk workspace (cap)
     int32_t *tgt_sorted = nullptr, *tgt_slot = nullptr, *mark = nullptr;
@@ -120,6 +125,8 @@ struct sr_tree {
     int32_t* group_head = nullptr;
     int32_t* list_counters = nullptr;  // chunks, units, overflow
     char* partials = nullptr;          // per unit
+    uint32_t* frontier = nullptr;      // per traversal wave: 2 x cap_front node ids + 2 x cap_front masks
+    int64_t cap_front = 0, n_front_waves = 0;
     int64_t n_units = 0, n_chunks = 0;
     ListKey lkey;
     int64_t build_gen = 0;
@@ -154,5 +161,11 @@ int sr_walk_adjoint(sr_tree* t, const sr_params* p, int64_t n_t, const int32_t* 
 // walk.hip: elementwise y += a x
 int sr_axpy_device(void* y, int y_type, const void* x, int x_type, double a, int64_t n, hipStream_t st);
 
+// api.hip: phase timing (HIP events around launches while enabled)
+bool sr_timing_on();
+void sr_timing_mark(int phase, bool start, hipStream_t st);
+
 // api.hip: make room for the lists of `groups` target groups and `chunks` chunks
 int sr_list_reserve(sr_tree* t, int64_t groups, int64_t chunks, int64_t chunks_per_unit);
+// api.hip: frontier scratch of `waves` persistent traversal waves, `cap` entries per level
+int sr_front_reserve(sr_tree* t, int64_t waves, int64_t cap);

@@ -249,248 +249,310 @@ struct ListArgs {
     int64_t cap_units;
 };
 
+struct FrontArgs {
+    uint32_t* buf;          // per wave: ids[2][cap], then masks[2][cap]
+    int64_t cap;
+    int32_t* next_group;    // work counter of the persistent waves
+    int32_t* overflow;      // set when a level does not fit
+    const uint32_t* kids;
+    const uint32_t* meta;
+    int64_t groups;
+};
+
+// Node decision data of the frontier entry a lane holds.
 template <bool DEC64>
-__global__ __launch_bounds__(WAVE) void k_traverse(WalkArgs a, ListArgs L)
+struct FNode;
+template <>
+struct FNode<true> {
+    double cx = 0, cy = 0, cz = 0, l = 0, X = 0, Y = 0, Z = 0, M = 0, hx = 0, hn = 0;
+};
+template <>
+struct FNode<false> {
+    uint32_t cX = 0, cY = 0, cZ = 0, tin = 0, X = 0, Y = 0, Z = 0, mixed = 0;
+    float M = 0, half = 0, l2 = 0, hx = 0;
+};
+
+// Breadth-first per group: a level's frontier entries (node, reach mask) are
+// loaded 64 at a time (one per lane) and their decisions, all independent, are
+// taken one after the other; opened nodes put their child nodes on the next
+// level and their child particles on the list.
+template <bool DEC64>
+__global__ __launch_bounds__(WAVE) void k_traverse(WalkArgs a, ListArgs L, FrontArgs F)
 {
     const int lane = threadIdx.x;
-    const int64_t g = blockIdx.x;
-    const int64_t t = g * WAVE + lane;
-    const bool valid = t < a.n_t;
-    const int32_t s_i = valid ? a.tgt_sorted[t] : -1;
-    double x64 = 0, y64 = 0, z64 = 0, aold = 0, atau = 0;
-    uint32_t X = 0, Y = 0, Z = 0;
-    if (valid) {
-        if constexpr (DEC64) {
-            const Rec64 r = a.prec64[s_i];
-            x64 = r.x;
-            y64 = r.y;
-            z64 = r.z;
-        } else {
-            const Rec32 r = a.prec32[s_i];
-            X = r.X;
-            Y = r.Y;
-            Z = r.Z;
-        }
-        if (a.relative) {
-            aold = a.a_old[a.perm[s_i]];
-            atau = (a.alpha * aold) * a.tau2;
-        }
-    }
-    const uint64_t active = __ballot(valid);
+    uint32_t* ids = F.buf + (int64_t)blockIdx.x * F.cap * 6;
+    uint64_t* masks = (uint64_t*)(ids + 2 * F.cap);
     const bool mixed = a.nhmax[0] != a.nhmin[0];
 
-    // ---- pending entries and their emission in chunks ----
-    uint32_t lsrc = 0;
-    uint64_t lmask = 0;
-    uint32_t nl = 0;
-    int32_t prev_chunk = -1, cur_unit = -1, prev_unit = -1;
-    uint32_t nch = 0, unit_nch = 0;
-    bool overflow = false;
-    auto emit = [&]() {
-        int32_t c0 = 0, u0 = 0;
-        const bool new_unit = (nch % UCH) == 0;
-        if (lane == 0) {
-            c0 = atomicAdd(&L.counters[0], 1);
-            if (new_unit) u0 = atomicAdd(&L.counters[1], 1);
-        }
-        const int32_t c = (int32_t)rl((uint32_t)c0, 0);
-        const int32_t u = (int32_t)rl((uint32_t)u0, 0);
-        if (c >= L.cap_chunks || (new_unit && u >= L.cap_units)) {
-            if (lane == 0) atomicOr(&L.counters[2], 1);
-            overflow = true;
-            nl = 0;
-            return;
-        }
-        if ((uint32_t)lane < nl) {
-            L.ent_src[64 * (int64_t)c + lane] = lsrc;
-            L.ent_mask[64 * (int64_t)c + lane] = lmask;
-        }
-        if (lane == 0) {
-            L.chunk_cnt[c] = (int32_t)nl;
-            L.chunk_next[c] = -1;
-            if (new_unit) {
-                if (cur_unit >= 0) L.unit_nch[cur_unit] = (int32_t)unit_nch;
-                L.unit_group[u] = (int32_t)g;
-                L.unit_chunk[u] = c;
-                L.unit_next[u] = -1;
-                if (prev_unit >= 0) L.unit_next[prev_unit] = u;
-                else L.group_head[g] = u;
+    for (;;) {
+        int32_t g0 = 0;
+        if (lane == 0) g0 = atomicAdd(F.next_group, 1);
+        const int64_t g = (int32_t)rl((uint32_t)g0, 0);
+        if (g >= F.groups) break;
+
+        // ---- targets of group g ----
+        const int64_t t = g * WAVE + lane;
+        const bool valid = t < a.n_t;
+        const int32_t s_i = valid ? a.tgt_sorted[t] : -1;
+        double x64 = 0, y64 = 0, z64 = 0, aold = 0, atau = 0;
+        uint32_t X = 0, Y = 0, Z = 0;
+        if (valid) {
+            if constexpr (DEC64) {
+                const Rec64 r = a.prec64[s_i];
+                x64 = r.x;
+                y64 = r.y;
+                z64 = r.z;
             } else {
-                L.chunk_next[prev_chunk] = c;
+                const Rec32 r = a.prec32[s_i];
+                X = r.X;
+                Y = r.Y;
+                Z = r.Z;
+            }
+            if (a.relative) {
+                aold = a.a_old[a.perm[s_i]];
+                atau = (a.alpha * aold) * a.tau2;
             }
         }
-        if (new_unit) {
-            prev_unit = u;
-            cur_unit = u;
-            unit_nch = 0;
-        }
-        ++unit_nch;
-        prev_chunk = c;
-        ++nch;
-        nl = 0;
-    };
+        const uint64_t active = __ballot(valid);
 
-    // ---- the window ----
-    uint32_t wref = 0xffffffffu, wnext = 0u, wdepth = 0xffffffffu;
-    uint64_t wrun = 0;   // bit l: item l is a particle continued by a sibling particle at l + 1
-    typename std::conditional<DEC64, Node64, Node32>::type wn;
-    auto load_window = [&](uint32_t k0) {
-        const uint32_t idx = k0 + (uint32_t)lane;
-        wref = 0xffffffffu;
-        wnext = 0u;
-        wdepth = 0xffffffffu;
-        if (idx < a.n_items) {
-            const Item it = a.items[idx];
-            wref = it.ref;
-            wnext = it.next;
-            wdepth = it.depth;
-            if (!(wref & ITEM_PARTICLE)) {
-                const uint32_t nd = wref;
-                if constexpr (DEC64) {
-                    const Geo64 gg = a.ngeo64[nd];
-                    const Rec64 c = a.nrec64[nd];
-                    wn.cx = gg.cx;
-                    wn.cy = gg.cy;
-                    wn.cz = gg.cz;
-                    wn.l = gg.l;
-                    wn.X = c.x;
-                    wn.Y = c.y;
-                    wn.Z = c.z;
-                    wn.M = c.m;
-                    wn.hx = a.nhmax[nd];
-                    wn.hn = a.nhmin[nd];
+        // ---- list entries of this group, emitted in chunks ----
+        uint32_t lsrc = 0;
+        uint64_t lmask = 0;
+        uint32_t nl = 0;
+        int32_t prev_chunk = -1, cur_unit = -1, prev_unit = -1;
+        uint32_t nch = 0, unit_nch = 0;
+        bool overflow = false;
+        auto emit = [&]() {
+            int32_t c0 = 0, u0 = 0;
+            const bool new_unit = (nch % UCH) == 0;
+            if (lane == 0) {
+                c0 = atomicAdd(&L.counters[0], 1);
+                if (new_unit) u0 = atomicAdd(&L.counters[1], 1);
+            }
+            const int32_t c = (int32_t)rl((uint32_t)c0, 0);
+            const int32_t u = (int32_t)rl((uint32_t)u0, 0);
+            if (c >= L.cap_chunks || (new_unit && u >= L.cap_units)) {
+                if (lane == 0) atomicOr(&L.counters[2], 1);
+                overflow = true;
+                nl = 0;
+                return;
+            }
+            if ((uint32_t)lane < nl) {
+                L.ent_src[64 * (int64_t)c + lane] = lsrc;
+                L.ent_mask[64 * (int64_t)c + lane] = lmask;
+            }
+            if (lane == 0) {
+                L.chunk_cnt[c] = (int32_t)nl;
+                L.chunk_next[c] = -1;
+                if (new_unit) {
+                    if (cur_unit >= 0) L.unit_nch[cur_unit] = (int32_t)unit_nch;
+                    L.unit_group[u] = (int32_t)g;
+                    L.unit_chunk[u] = c;
+                    L.unit_next[u] = -1;
+                    if (prev_unit >= 0) L.unit_next[prev_unit] = u;
+                    else L.group_head[g] = u;
                 } else {
-                    const Rec32 c = a.nrec32[nd];
-                    const int lev = a.n_level[nd];
-                    const uint32_t half = 1u << (31 - lev);
-                    const uint64_t lint = 1ull << (32 - lev);
-                    wn.cX = a.n_corner[3 * nd + 0] + half;
-                    wn.cY = a.n_corner[3 * nd + 1] + half;
-                    wn.cZ = a.n_corner[3 * nd + 2] + half;
-                    wn.tin = (uint32_t)((3ull * lint - 1ull) / 5ull);
-                    wn.X = c.X;
-                    wn.Y = c.Y;
-                    wn.Z = c.Z;
-                    wn.M = c.m;
-                    wn.half = (float)half;
-                    wn.l2 = (float)lint * (float)lint;
-                    wn.hx = a.nhmax32[nd];
-                    wn.mixed = mixed && a.nhmin[nd] != a.nhmax[nd];
+                    L.chunk_next[prev_chunk] = c;
                 }
             }
-        }
-        const uint32_t nref = (uint32_t)__shfl_down((int)wref, 1, 64);
-        const uint32_t ndep = (uint32_t)__shfl_down((int)wdepth, 1, 64);
-        wrun = __ballot(lane < 63 && (wref & ITEM_PARTICLE) && wdepth != 0xffffffffu && (nref & ITEM_PARTICLE) &&
-                        ndep == wdepth);
-    };
-
-    uint64_t openv = 0;   // lane d: open mask of the path node at depth d
-    uint32_t k = 0, w0 = 0xffffffffu, iters = 0;
-    while (k < a.n_items && !overflow) {
-        // the longest traversals set the kernel's duration: raise their issue priority as they age
-        ++iters;
-        if (iters == 1024u) __builtin_amdgcn_s_setprio(1);
-        if (iters == 2048u) __builtin_amdgcn_s_setprio(2);
-        if (iters == 3072u) __builtin_amdgcn_s_setprio(3);
-        if (k < w0 || k - w0 >= (uint32_t)WIN) {
-            load_window(k);
-            w0 = k;
-        }
-        const uint32_t j = k - w0;
-        const uint32_t ref = rl(wref, j);
-        const uint32_t depth = rl(wdepth, j);
-        const uint64_t reach = depth ? rl64(openv, depth - 1) : active;
-        if (ref & ITEM_PARTICLE) {
-            // a run of sibling particles (consecutive sorted positions) shares the reach mask
-            const uint32_t R = (uint32_t)__builtin_ctzll(~(wrun >> j)) + 1u;
-            if (nl + R > (uint32_t)WAVE) emit();
-            const uint32_t p0 = ref & ~ITEM_PARTICLE;
-            if ((uint32_t)lane >= nl && (uint32_t)lane < nl + R) {
-                lsrc = (p0 + ((uint32_t)lane - nl)) | ITEM_PARTICLE;
-                lmask = reach;
+            if (new_unit) {
+                prev_unit = u;
+                cur_unit = u;
+                unit_nch = 0;
             }
-            // targets whose own particle lies in the run leave that entry
-            uint64_t self = __ballot(valid && (uint32_t)s_i - p0 < R) & reach;
-            while (self) {
-                const uint32_t tl = (uint32_t)__builtin_ctzll(self);
-                self &= self - 1;
-                const uint32_t e = nl + (rl((uint32_t)s_i, tl) - p0);
-                if ((uint32_t)lane == e) lmask &= ~(1ull << tl);
-            }
-            nl += R;
-            k += R;
-            continue;
-        }
-        // decisions of every lane, branch-free (lanes outside `reach` are masked by the ballots)
-        bool keep, open, near;
-        if constexpr (DEC64) {
-            const double l = rld(wn.l, j);
-            const double dcx = min_image(rld(wn.cx, j) - x64, a.box);
-            const double dcy = min_image(rld(wn.cy, j) - y64, a.box);
-            const double dcz = min_image(rld(wn.cz, j) - z64, a.box);
-            const double tx = fmax(fabs(dcx) - 0.5 * l, 0.0);
-            const double ty = fmax(fabs(dcy) - 0.5 * l, 0.0);
-            const double tz = fmax(fabs(dcz) - 0.5 * l, 0.0);
-            keep = !((tx * tx + ty * ty) + tz * tz > a.rc2 * (1.0 + 1e-6));
-            const bool inside = fabs(dcx) < 0.6 * l && fabs(dcy) < 0.6 * l && fabs(dcz) < 0.6 * l;
-            const double dx = min_image(rld(wn.X, j) - x64, a.box);
-            const double dy = min_image(rld(wn.Y, j) - y64, a.box);
-            const double dz = min_image(rld(wn.Z, j) - z64, a.box);
-            const double r2 = (dx * dx + dy * dy) + dz * dz;
-            open = inside || l * l > a.theta2 * r2;
-            if (a.relative) open = open || (a.G * rld(wn.M, j)) * (l * l) > (a.alpha * aold) * (r2 * r2);
-            if (mixed) {
-                const double hx = rld(wn.hx, j);
-                open = open || (rld(wn.hn, j) != hx && r2 < hx * hx);
-            }
-            near = r2 < a.rc2;
-        } else {
-            const uint32_t bx = (uint32_t)abs((int32_t)(rl(wn.cX, j) - X));
-            const uint32_t by = (uint32_t)abs((int32_t)(rl(wn.cY, j) - Y));
-            const uint32_t bz = (uint32_t)abs((int32_t)(rl(wn.cZ, j) - Z));
-            const float half = rlf(wn.half, j);
-            const float tx = fmaxf((float)bx - half, 0.0f);
-            const float ty = fmaxf((float)by - half, 0.0f);
-            const float tz = fmaxf((float)bz - half, 0.0f);
-            keep = !(__builtin_fmaf(tx, tx, __builtin_fmaf(ty, ty, tz * tz)) > a.rc2t * 1.0001f);
-            const uint32_t tin = rl(wn.tin, j);
-            const bool inside = bx <= tin && by <= tin && bz <= tin;
-            const float dx = (float)(int32_t)(rl(wn.X, j) - X);
-            const float dy = (float)(int32_t)(rl(wn.Y, j) - Y);
-            const float dz = (float)(int32_t)(rl(wn.Z, j) - Z);
-            const float r2 = r2_ticks(dx, dy, dz);
-            const float l2 = rlf(wn.l2, j);
-            open = inside || l2 > a.theta2f * r2;
-            if (a.relative) {
-                const double r2d = (double)r2;
-                open = open || (a.G * (double)rlf(wn.M, j)) * (double)l2 > atau * (r2d * r2d);
-            }
-            if (mixed) {
-                const float hx = rlf(wn.hx, j);
-                open = open || (rl(wn.mixed, j) && r2 < hx * hx);
-            }
-            near = r2 < a.rc2t;
-        }
-        const bool live = ((reach >> lane) & 1ull) && keep;
-        const int dec = !live ? D_PRUNE : (open ? D_OPEN : (near ? D_ACCEPT : D_ACCEPT_FAR));
-        const uint64_t om = __ballot(dec == D_OPEN);
-        const uint64_t am = __ballot(dec == D_ACCEPT);
-        if (am) {
+            ++unit_nch;
+            prev_chunk = c;
+            ++nch;
+            nl = 0;
+        };
+        auto append = [&](uint32_t src, uint64_t m) {
             if (nl == (uint32_t)WAVE) emit();
-            lsrc = wl(ref, nl, lsrc);
-            lmask = wl(am, nl, lmask);
+            lsrc = wl(src, nl, lsrc);
+            lmask = wl(m, nl, lmask);
             ++nl;
+        };
+        // a particle entry leaves out the target whose own particle it is
+        auto append_particle = [&](uint32_t s, uint64_t m) {
+            m &= ~__ballot(s_i == (int32_t)s);
+            if (m) append(s | ITEM_PARTICLE, m);
+        };
+
+        // ---- breadth-first levels ----
+        int cur = 0;
+        int64_t na = 1;
+        if (lane == 0) {
+            ids[0] = 0u;
+            masks[0] = active;
         }
-        if (om) {
-            openv = wl(om, depth, openv);
-            ++k;
-        } else {
-            k = rl(wnext, j);
+        while (na > 0 && !overflow) {
+            __syncthreads();
+            uint32_t* nid = ids + (cur ^ 1) * F.cap;
+            uint64_t* nmask = masks + (cur ^ 1) * F.cap;
+            int64_t nb = 0;          // entries of the next level written so far
+            uint32_t qid = 0;        // pending next-level entries (lane q = entry q)
+            uint64_t qmask = 0;
+            uint32_t nq = 0;
+            auto push = [&](uint32_t nd, uint64_t m) {
+                if (nq == (uint32_t)WAVE) {
+                    if (nb + WAVE <= F.cap) {
+                        nid[nb + lane] = qid;
+                        nmask[nb + lane] = qmask;
+                    } else {
+                        if (lane == 0) atomicOr(F.overflow, 1);
+                        overflow = true;
+                    }
+                    nb += WAVE;
+                    nq = 0;
+                }
+                qid = wl(nd, nq, qid);
+                qmask = wl(m, nq, qmask);
+                ++nq;
+            };
+            for (int64_t b0 = 0; b0 < na && !overflow; b0 += WAVE) {
+                const uint32_t cnt = (uint32_t)(na - b0 < WAVE ? na - b0 : WAVE);
+                uint32_t fid = 0, fmeta = 0;
+                uint64_t fmask = 0;
+                uint32_t kid[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+                FNode<DEC64> fn;
+                if ((uint32_t)lane < cnt) {
+                    fid = ids[cur * F.cap + b0 + lane];
+                    fmask = masks[cur * F.cap + b0 + lane];
+                    const uint32_t nd = fid;
+                    fmeta = F.meta[nd];
+                    const uint4* kp = (const uint4*)(F.kids + 8 * (int64_t)nd);
+                    const uint4 k0 = kp[0], k1 = kp[1];
+                    kid[0] = k0.x;
+                    kid[1] = k0.y;
+                    kid[2] = k0.z;
+                    kid[3] = k0.w;
+                    kid[4] = k1.x;
+                    kid[5] = k1.y;
+                    kid[6] = k1.z;
+                    kid[7] = k1.w;
+                    if constexpr (DEC64) {
+                        const Geo64 gg = a.ngeo64[nd];
+                        const Rec64 c = a.nrec64[nd];
+                        fn.cx = gg.cx;
+                        fn.cy = gg.cy;
+                        fn.cz = gg.cz;
+                        fn.l = gg.l;
+                        fn.X = c.x;
+                        fn.Y = c.y;
+                        fn.Z = c.z;
+                        fn.M = c.m;
+                        fn.hx = a.nhmax[nd];
+                        fn.hn = a.nhmin[nd];
+                    } else {
+                        const Rec32 c = a.nrec32[nd];
+                        const int lev = a.n_level[nd];
+                        const uint32_t half = 1u << (31 - lev);
+                        const uint64_t lint = 1ull << (32 - lev);
+                        fn.cX = a.n_corner[3 * nd + 0] + half;
+                        fn.cY = a.n_corner[3 * nd + 1] + half;
+                        fn.cZ = a.n_corner[3 * nd + 2] + half;
+                        fn.tin = (uint32_t)((3ull * lint - 1ull) / 5ull);
+                        fn.X = c.X;
+                        fn.Y = c.Y;
+                        fn.Z = c.Z;
+                        fn.M = c.m;
+                        fn.half = (float)half;
+                        fn.l2 = (float)lint * (float)lint;
+                        fn.hx = a.nhmax32[nd];
+                        fn.mixed = mixed && a.nhmin[nd] != a.nhmax[nd];
+                    }
+                }
+                for (uint32_t j = 0; j < cnt; ++j) {
+                    const uint32_t nd = rl(fid, j);
+                    const uint64_t reach = rl64(fmask, j);
+                    bool keep, open, near;
+                    if constexpr (DEC64) {
+                        const double l = rld(fn.l, j);
+                        const double dcx = min_image(rld(fn.cx, j) - x64, a.box);
+                        const double dcy = min_image(rld(fn.cy, j) - y64, a.box);
+                        const double dcz = min_image(rld(fn.cz, j) - z64, a.box);
+                        const double tx = fmax(fabs(dcx) - 0.5 * l, 0.0);
+                        const double ty = fmax(fabs(dcy) - 0.5 * l, 0.0);
+                        const double tz = fmax(fabs(dcz) - 0.5 * l, 0.0);
+                        keep = !((tx * tx + ty * ty) + tz * tz > a.rc2 * (1.0 + 1e-6));
+                        const bool inside = fabs(dcx) < 0.6 * l && fabs(dcy) < 0.6 * l && fabs(dcz) < 0.6 * l;
+                        const double dx = min_image(rld(fn.X, j) - x64, a.box);
+                        const double dy = min_image(rld(fn.Y, j) - y64, a.box);
+                        const double dz = min_image(rld(fn.Z, j) - z64, a.box);
+                        const double r2 = (dx * dx + dy * dy) + dz * dz;
+                        open = inside || l * l > a.theta2 * r2;
+                        if (a.relative) open = open || (a.G * rld(fn.M, j)) * (l * l) > (a.alpha * aold) * (r2 * r2);
+                        if (mixed) {
+                            const double hx = rld(fn.hx, j);
+                            open = open || (rld(fn.hn, j) != hx && r2 < hx * hx);
+                        }
+                        near = r2 < a.rc2;
+                    } else {
+                        const uint32_t bx = (uint32_t)abs((int32_t)(rl(fn.cX, j) - X));
+                        const uint32_t by = (uint32_t)abs((int32_t)(rl(fn.cY, j) - Y));
+                        const uint32_t bz = (uint32_t)abs((int32_t)(rl(fn.cZ, j) - Z));
+                        const float half = rlf(fn.half, j);
+                        const float tx = fmaxf((float)bx - half, 0.0f);
+                        const float ty = fmaxf((float)by - half, 0.0f);
+                        const float tz = fmaxf((float)bz - half, 0.0f);
+                        keep = !(__builtin_fmaf(tx, tx, __builtin_fmaf(ty, ty, tz * tz)) > a.rc2t * 1.0001f);
+                        const uint32_t tin = rl(fn.tin, j);
+                        const bool inside = bx <= tin && by <= tin && bz <= tin;
+                        const float dx = (float)(int32_t)(rl(fn.X, j) - X);
+                        const float dy = (float)(int32_t)(rl(fn.Y, j) - Y);
+                        const float dz = (float)(int32_t)(rl(fn.Z, j) - Z);
+                        const float r2 = r2_ticks(dx, dy, dz);
+                        const float l2 = rlf(fn.l2, j);
+                        open = inside || l2 > a.theta2f * r2;
+                        if (a.relative) {
+                            const double r2d = (double)r2;
+                            open = open || (a.G * (double)rlf(fn.M, j)) * (double)l2 > atau * (r2d * r2d);
+                        }
+                        if (mixed) {
+                            const float hx = rlf(fn.hx, j);
+                            open = open || (rl(fn.mixed, j) && r2 < hx * hx);
+                        }
+                        near = r2 < a.rc2t;
+                    }
+                    const bool live = ((reach >> lane) & 1ull) && keep;
+                    const uint64_t om = __ballot(live && open);
+                    const uint64_t am = __ballot(live && !open && near);
+                    if (am) append(nd, am);
+                    if (!om) continue;
+                    const uint32_t meta = rl(fmeta, j);
+                    if (meta == META_BUCKET) {
+                        const uint32_t s0 = rl(kid[0], j), sc = rl(kid[1], j);
+                        for (uint32_t s = s0; s < s0 + sc; ++s) append_particle(s, om);
+                        continue;
+                    }
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) {
+                        if ((uint32_t)i < meta) {
+                            const uint32_t c = rl(kid[i], j);
+                            if (c & ITEM_PARTICLE) append_particle(c & ~ITEM_PARTICLE, om);
+                            else push(c, om);
+                        }
+                    }
+                }
+            }
+            // last partial block of the next level
+            if (nq && !overflow) {
+                if (nb + WAVE <= F.cap) {
+                    if ((uint32_t)lane < nq) {
+                        nid[nb + lane] = qid;
+                        nmask[nb + lane] = qmask;
+                    }
+                } else {
+                    if (lane == 0) atomicOr(F.overflow, 1);
+                    overflow = true;
+                }
+            }
+            na = nb + nq;
+            cur ^= 1;
         }
+        if (nl && !overflow) emit();
+        if (lane == 0 && cur_unit >= 0 && !overflow) L.unit_nch[cur_unit] = (int32_t)unit_nch;
+        if (overflow) break;
     }
-    if (nl && !overflow) emit();
-    if (lane == 0 && cur_unit >= 0 && !overflow) L.unit_nch[cur_unit] = (int32_t)unit_nch;
 }
 
 // ----------------------------------------------------------------------------------
@@ -941,7 +1003,7 @@ bool same_lists(const sr_tree* t, const sr_params* p, int64_t n_t, const int32_t
            k.n_t == n_t && k.active == (const void*)active && k.a_old == (const void*)a_old;
 }
 
-// Phase 1, growing the list buffers until every group's entries fit.
+// Phase 1, growing the list buffers (and the per-wave frontier) until everything fits.
 int traverse(sr_tree* t, const sr_params* p, int64_t n_t, const int32_t* active, const double* a_old,
              hipStream_t st)
 {
@@ -949,15 +1011,32 @@ int traverse(sr_tree* t, const sr_params* p, int64_t n_t, const int32_t* active,
     const int64_t groups = (n_t + WAVE - 1) / WAVE;
     int64_t want = 32 * n_t;
     if (want < (int64_t)1 << 16) want = (int64_t)1 << 16;
+    int64_t fcap = t->cap_front > 4096 ? t->cap_front : 4096;
+    // persistent traversal waves: 16 per CU, at most one per group
+    int dev = 0, cus = 0;
+    SR_HIP(hipGetDevice(&dev));
+    SR_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const int64_t waves = groups < 16 * (int64_t)cus ? groups : 16 * (int64_t)cus;
     for (int attempt = 0; attempt < 8; ++attempt) {
         int rc = sr_list_reserve(t, groups, (want + 63) / 64, (int64_t)UCH);
         if (rc) return rc;
+        if ((rc = sr_front_reserve(t, waves, fcap))) return rc;
         hipLaunchKernelGGL(k_fill_i32w, g256(groups), dim3(256), 0, st, t->group_head, groups, -1);
         hipLaunchKernelGGL(k_fill_i32w, g256(4), dim3(256), 0, st, t->list_counters, (int64_t)4, 0);
         const WalkArgs a = make_args(t, p, n_t, a_old);
         const ListArgs L = list_args(t);
-        if (p->precision == SR_FP64) hipLaunchKernelGGL(k_traverse<true>, dim3((unsigned)groups), dim3(WAVE), 0, st, a, L);
-        else hipLaunchKernelGGL(k_traverse<false>, dim3((unsigned)groups), dim3(WAVE), 0, st, a, L);
+        FrontArgs F{};
+        F.buf = t->frontier;
+        F.cap = t->cap_front;
+        F.next_group = t->list_counters + 3;
+        F.overflow = t->list_counters + 2;
+        F.kids = t->n_kids;
+        F.meta = t->n_meta;
+        F.groups = groups;
+        sr_timing_mark(SR_T_TRAVERSE, true, st);
+        if (p->precision == SR_FP64) hipLaunchKernelGGL(k_traverse<true>, dim3((unsigned)waves), dim3(WAVE), 0, st, a, L, F);
+        else hipLaunchKernelGGL(k_traverse<false>, dim3((unsigned)waves), dim3(WAVE), 0, st, a, L, F);
+        sr_timing_mark(SR_T_TRAVERSE, false, st);
         SR_HIP(hipGetLastError());
         int32_t cnt[4];
         SR_HIP(hipMemcpyAsync(cnt, t->list_counters, sizeof(cnt), hipMemcpyDeviceToHost, st));
@@ -980,7 +1059,9 @@ int traverse(sr_tree* t, const sr_params* p, int64_t n_t, const int32_t* active,
             k.a_old = a_old;
             return SR_OK;
         }
+        // something did not fit: grow both (a chunk overflow and a frontier overflow share the flag)
         want = 2 * t->cap_chunks * 64;
+        fcap = 2 * t->cap_front;
     }
     return sr_fail(SR_ENOMEM, "interaction lists did not fit after repeated growth");
 }
@@ -991,18 +1072,23 @@ int eval_and_reduce(sr_tree* t, const sr_params* p, const WalkArgs& a, hipStream
     const int64_t groups = (a.n_t + WAVE - 1) / WAVE;
     const ListArgs L = list_args(t);
     const dim3 gu((unsigned)(t->n_units > 0 ? t->n_units : 1)), gg((unsigned)groups);
+    const int ph_eval = ADJ ? SR_T_ADJ_EVAL : SR_T_EVAL, ph_red = ADJ ? SR_T_ADJ_REDUCE : SR_T_REDUCE;
     if (t->n_units > 0) {
+        sr_timing_mark(ph_eval, true, st);
         switch (p->precision) {
         case SR_FP64: hipLaunchKernelGGL((k_eval<PR64, ADJ>), gu, dim3(WAVE), 0, st, a, L, t->partials); break;
         case SR_FP32: hipLaunchKernelGGL((k_eval<PR32, ADJ>), gu, dim3(WAVE), 0, st, a, L, t->partials); break;
         default: hipLaunchKernelGGL((k_eval<PR32A, ADJ>), gu, dim3(WAVE), 0, st, a, L, t->partials); break;
         }
+        sr_timing_mark(ph_eval, false, st);
     }
+    sr_timing_mark(ph_red, true, st);
     switch (p->precision) {
     case SR_FP64: hipLaunchKernelGGL((k_reduce<PR64, ADJ>), gg, dim3(WAVE), 0, st, a, L, t->partials); break;
     case SR_FP32: hipLaunchKernelGGL((k_reduce<PR32, ADJ>), gg, dim3(WAVE), 0, st, a, L, t->partials); break;
     default: hipLaunchKernelGGL((k_reduce<PR32A, ADJ>), gg, dim3(WAVE), 0, st, a, L, t->partials); break;
     }
+    sr_timing_mark(ph_red, false, st);
     SR_HIP(hipGetLastError());
     return SR_OK;
 }
@@ -1095,8 +1181,10 @@ int sr_walk_adjoint(sr_tree* t, const sr_params* p, int64_t n_t, const int32_t* 
         sx = p->G * TWO32 / (L * L * L);
         sm = p->G * TWO32 * TWO32 / (L * L);
     }
+    sr_timing_mark(SR_T_PUSHDOWN, true, st);
     hipLaunchKernelGGL(k_pushdown, g256(n), dim3(256), 0, st, n, t->perm, t->pparent, t->n_parent, t->prec64,
                        t->nrec64, t->pbar, t->tbar, t->nbar, sx, sm, dLdx, dLdm);
+    sr_timing_mark(SR_T_PUSHDOWN, false, st);
     SR_HIP(hipGetLastError());
     return SR_OK;
 }
