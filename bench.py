@@ -26,8 +26,35 @@ sys.path.insert(0, ROOT)
 
 METRIC = "short-range interactions/s, FP32 vs FP64 at stated force error; fwd+adjoint"
 FP32_PEAK_TFLOPS = 157.3           # MI355X FP32 vector peak
-FLOP_PER_INTERACTION = 24          # algorithmic count per pair force (see DESIGN.md)
+FLOP_PER_INTERACTION = 24          # algorithmic count per pair force
+FLOP_PER_ADJOINT_INTERACTION = 48  # forward pair force plus its vector-Jacobian product
+FLOP_PER_NODE_TEST = 13            # r^2 (5), opening angle (2), enlarged-cube guard (6)
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_clustered_262k.md")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("walk.hip", "internal.h", "gpoly.h"):
+        h.update(open(os.path.join(ROOT, "paper_2606_17145_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic(phase):
+    """HBM bytes per launch of `phase` from the committed counter summary, if it was
+    taken on the current kernel source; else None."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and line.strip().startswith("- "):
+            k, v = line.strip()[2:].split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    v = vals.get(f"{phase}_bytes_per_launch")
+    return float(v) if v else None
 
 
 def log(msg):
@@ -41,6 +68,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-error-check", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="copy a buffer of this size once before the run (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the library has no multi-GPU path); got --gpus {args.gpus}",
@@ -81,16 +110,26 @@ def main():
             ev[3].record()
         return acc, cnt
 
+    if args.copy_probe_mib:
+        src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
     torch.cuda.synchronize()
+    _lib.timing(True)      # HIP events around every phase, on the launch stream
     t0 = time.perf_counter()
     for k in range(args.steps):
         acc, cnt = step(evs[k])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    phases = _lib.timing_read()
+    _lib.timing(False)
+    stats = tree.walk_stats()
     build_ms = np.mean([e[0].elapsed_time(e[1]) for e in evs])
     fwd_ms = np.mean([e[1].elapsed_time(e[2]) for e in evs])
     adj_ms = np.mean([e[2].elapsed_time(e[3]) for e in evs])
@@ -141,12 +180,18 @@ def main():
         "fp32_over_fp64_walk_speedup": fwd64_ms / fwd_ms,
         "particles_per_s": w.n / (ms_step * 1e-3),
     }
-    # dominant kernel: the larger of the two walks (each is a single launch)
-    dom_ms, dom_name = max((fwd_ms, "walk_fp32"), (adj_ms, "adjoint_fp32"))
-    flops = FLOP_PER_INTERACTION * inter * (1 if dom_name == "walk_fp32" else 2)
-    achieved = flops / (dom_ms * 1e-3) / 1e12
-    out["roofline"] = {"kernel": dom_name, "bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
-                       "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None}
+    # per-kernel average launch durations from the library's events
+    avg = {k: (ms / n if n else 0.0) for k, (ms, n) in phases.items()}
+    out["kernel_ms_per_launch"] = avg
+    out["walk_stats"] = stats
+    work = {"eval": FLOP_PER_INTERACTION * inter,
+            "adjoint_eval": FLOP_PER_ADJOINT_INTERACTION * inter,
+            "traverse": FLOP_PER_NODE_TEST * stats["node_tests"]}
+    dom = max(work, key=lambda k: avg[k])
+    achieved = work[dom] / (avg[dom] * 1e-3) / 1e12
+    out["roofline"] = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
+                       "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
+                       "traffic": committed_traffic(dom)}
 
     if not args.no_error_check:
         from oracle import oracle as O

@@ -193,6 +193,10 @@ typedef struct {
 } sr_tree_export;
 
 int tree_node_count(const sr_tree* tree, int64_t* n_nodes);
+
+/* Work statistics of the handle's last walk (HOST int64[4]): node-target
+ * opening tests, 64-entry list chunks, evaluation units, targets. */
+int tree_walk_stats(const sr_tree* tree, int64_t* stats);
 int tree_export(const sr_tree* tree, const sr_tree_export* out, void* stream);
 
 /* Frees the handle and its device workspace (NULL is allowed). */

@@ -76,6 +76,12 @@ class Tree:
         _lib.check(_lib.lib().tree_node_count(self._h, C.byref(m)))
         return int(m.value)
 
+    def walk_stats(self) -> dict:
+        """Work statistics of the last walk on this handle."""
+        s = (C.c_int64 * 4)()
+        _lib.check(_lib.lib().tree_walk_stats(self._h, s))
+        return dict(node_tests=int(s[0]), chunks=int(s[1]), units=int(s[2]), targets=int(s[3]))
+
     def export(self) -> dict:
         """Copies of the sorted keys, permutation and node arrays (device tensors)."""
         n, m = self.n, self.node_count()

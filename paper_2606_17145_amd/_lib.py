@@ -21,7 +21,7 @@ PRECISIONS = {"fp64": SR_FP64, "fp32": SR_FP32, "fp32_acc64": SR_FP32_ACC64}
 CRITERIA = {"bh": SR_OPEN_BH, "relative": SR_OPEN_RELATIVE}
 EXPORTED = ("tree_build", "shortrange_accel", "shortrange_accel_adjoint", "tree_node_count",
             "tree_export", "tree_free", "srgrav_last_error", "sr_axpy", "srgrav_timing",
-            "srgrav_timing_read")
+            "srgrav_timing_read", "tree_walk_stats")
 PHASES = ("tree_build", "traverse", "eval", "reduce", "adjoint_eval", "adjoint_reduce", "pushdown")
 
 
@@ -66,6 +66,8 @@ def lib():
         L.srgrav_timing.restype = C.c_int
         L.srgrav_timing_read.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.srgrav_timing_read.restype = C.c_int
+        L.tree_walk_stats.argtypes = [vp, C.POINTER(C.c_int64)]
+        L.tree_walk_stats.restype = C.c_int
         L.tree_free.argtypes = [vp]
         L.tree_free.restype = None
         L.srgrav_last_error.restype = C.c_char_p

@@ -24,6 +24,7 @@ std::mutex g_tmu;
 bool g_timing = false;
 std::vector<TimedLaunch> g_pending;
 std::vector<hipEvent_t> g_open(SR_T_COUNT, nullptr);
+std::vector<hipEvent_t> g_free;   // recorded-and-read events, reused
 double g_ms[SR_T_COUNT] = {};
 int64_t g_calls[SR_T_COUNT] = {};
 
@@ -263,7 +264,7 @@ int sr_list_reserve(sr_tree* t, int64_t groups, int64_t chunks, int64_t chunks_p
     A(t->unit_nch, units);
     A(t->unit_next, units);
     A(t->group_head, groups);
-    A(t->list_counters, 4);
+    A(t->list_counters, 8);
     A(t->partials, 64 * (3 * 8 + 2 * 4) * units);
 #undef A
     t->cap_groups = groups;
@@ -279,7 +280,12 @@ void sr_timing_mark(int phase, bool start, hipStream_t st)
     std::lock_guard<std::mutex> lk(g_tmu);
     if (!g_timing) return;
     hipEvent_t e;
-    if (hipEventCreate(&e) != hipSuccess) return;
+    if (!g_free.empty()) {
+        e = g_free.back();
+        g_free.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+        return;
+    }
     (void)hipEventRecord(e, st);
     if (start) {
         g_open[phase] = e;
@@ -287,7 +293,7 @@ void sr_timing_mark(int phase, bool start, hipStream_t st)
         g_pending.push_back(TimedLaunch{phase, g_open[phase], e});
         g_open[phase] = nullptr;
     } else {
-        (void)hipEventDestroy(e);
+        g_free.push_back(e);
     }
 }
 
@@ -376,6 +382,17 @@ int shortrange_accel_adjoint(sr_tree* t, const sr_params* p, const int32_t* acti
     return sr_walk_adjoint(t, p, n_active, active, a_old, w, dLdx, dLdm, st);
 }
 
+int tree_walk_stats(const sr_tree* t, int64_t* stats)
+{
+    if (!t || t->n <= 0) return sr_fail(SR_ESTATE, "tree handle is NULL or was never built");
+    if (!stats) return sr_fail(SR_EINVAL, "stats is NULL");
+    stats[0] = t->n_tests;
+    stats[1] = t->n_chunks;
+    stats[2] = t->n_units;
+    stats[3] = t->lkey.valid ? t->lkey.n_t : 0;
+    return SR_OK;
+}
+
 int tree_node_count(const sr_tree* t, int64_t* n_nodes)
 {
     if (!t || t->n <= 0) return sr_fail(SR_ESTATE, "tree handle is NULL or was never built");
@@ -426,12 +443,12 @@ int srgrav_timing(int32_t enable)
 {
     std::lock_guard<std::mutex> lk(g_tmu);
     for (auto& p : g_pending) {
-        (void)hipEventDestroy(p.start);
-        (void)hipEventDestroy(p.stop);
+        g_free.push_back(p.start);
+        g_free.push_back(p.stop);
     }
     g_pending.clear();
     for (auto& e : g_open)
-        if (e) (void)hipEventDestroy(e), e = nullptr;
+        if (e) g_free.push_back(e), e = nullptr;
     if (enable)
         for (int k = 0; k < SR_T_COUNT; ++k) g_ms[k] = 0.0, g_calls[k] = 0;
     g_timing = enable != 0;
@@ -448,8 +465,8 @@ int srgrav_timing_read(double* ms, int64_t* calls)
         SR_HIP(hipEventElapsedTime(&x, p.start, p.stop));
         g_ms[p.phase] += x;
         g_calls[p.phase] += 1;
-        (void)hipEventDestroy(p.start);
-        (void)hipEventDestroy(p.stop);
+        g_free.push_back(p.start);
+        g_free.push_back(p.stop);
     }
     g_pending.clear();
     for (int k = 0; k < SR_T_COUNT; ++k) {

@@ -615,6 +615,7 @@ int sr_build_device(sr_tree* t, const double* pos, const double* mass, const dou
     SR_HIP(hipStreamSynchronize(st));
     if (m == 0) {
         t->max_depth = 0;
+        t->mixed_soft = false;
         return SR_OK;
     }
     t->max_depth = hstat[ST_MAXDEPTH];
@@ -640,7 +641,12 @@ int sr_build_device(sr_tree* t, const double* pos, const double* mass, const dou
                            t->nhmax, t->nhmin, t->nrec32, t->nhmax32, t->n_kids, t->n_meta, t->n_count);
     }
     SR_HIP(hipGetLastError());
-    // the host copy of the offsets must outlive the copy above
+    // the root's softening range tells whether any two particles differ
+    double hr[2];
+    SR_HIP(hipMemcpyAsync(&hr[0], t->nhmax, sizeof(double), hipMemcpyDeviceToHost, st));
+    SR_HIP(hipMemcpyAsync(&hr[1], t->nhmin, sizeof(double), hipMemcpyDeviceToHost, st));
+    // (this also keeps the host copy of the offsets alive until the copies above are done)
     SR_HIP(hipStreamSynchronize(st));
+    t->mixed_soft = hr[0] != hr[1];
     return SR_OK;
 }

@@ -123,16 +123,17 @@ struct sr_tree {
     int32_t *chunk_next = nullptr, *chunk_cnt = nullptr;
     int32_t *unit_group = nullptr, *unit_chunk = nullptr, *unit_nch = nullptr, *unit_next = nullptr;
     int32_t* group_head = nullptr;
-    int32_t* list_counters = nullptr;  // chunks, units, overflow
+    int32_t* list_counters = nullptr;  // chunks, units, overflow, -, node tests (u64 at [4])
     char* partials = nullptr;          // per unit
     uint32_t* frontier = nullptr;      // per traversal wave: 2 x cap_front node ids + 2 x cap_front masks
     int64_t cap_front = 0, n_front_waves = 0;
-    int64_t n_units = 0, n_chunks = 0;
+    int64_t n_units = 0, n_chunks = 0, n_tests = 0;
     ListKey lkey;
     int64_t build_gen = 0;
 
     // host mirrors
     int64_t n_nodes = 0;
+    bool mixed_soft = false;      // softening lengths differ between particles
     int max_depth = 0;
     int depth_hist[SR_MAX_DEPTH] = {};
 };

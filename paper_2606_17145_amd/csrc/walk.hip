@@ -10,6 +10,7 @@
 // The adjoint reuses the forward's lists (the frozen decisions) and scatters
 // source terms with wave sums and FP64 atomics.
 #include <stdio.h>
+#include <string.h>
 
 #include <type_traits>
 
@@ -54,7 +55,7 @@ struct WalkArgs {
     double G, box, rc2, theta2, alpha, inv2rs;
     int relative;
     // parameters (FP32 path; integer-coordinate units)
-    float rc2t, theta2f, inv2rs_t;
+    float rc2t, theta2f, inv2rs_t, rct;
     double tau2;          // (L / 2^32)^2
     double out_scale;     // G / L^2
     // outputs / adjoint
@@ -142,6 +143,26 @@ __device__ inline float spline_h4dS_32(float q)
     return __builtin_fmaf(t, __builtin_fmaf(t, -32.0f, -12.8f), -3.2f) + 1.0f / (5.0f * q2 * q2);
 }
 
+// The same two functions without branches or IEEE division (both pieces are
+// computed and selected; 1/x by v_rcp_f32, 1 ulp).
+__device__ inline float spline_h3S_32f(float q)
+{
+    const float inner = __builtin_fmaf(q * q, __builtin_fmaf(32.0f, q, -38.4f), 10.6666666667f);
+    const float t = 1.0f - q;
+    const float poly = __builtin_fmaf(t, __builtin_fmaf(t, __builtin_fmaf(t, 10.6666666667f, 6.4f), 3.2f), 1.06666666667f);
+    const float outer = poly - __builtin_amdgcn_rcpf(15.0f * q * q * q);
+    return q < 0.5f ? inner : outer;
+}
+
+__device__ inline float spline_h4dS_32f(float q)
+{
+    const float inner = q * __builtin_fmaf(96.0f, q, -76.8f);
+    const float t = 1.0f - q;
+    const float q2 = q * q;
+    const float outer = __builtin_fmaf(t, __builtin_fmaf(t, -32.0f, -12.8f), -3.2f) + __builtin_amdgcn_rcpf(5.0f * q2 * q2);
+    return q < 0.5f ? inner : outer;
+}
+
 // ---- wave reductions (DPP row shifts and row broadcasts; the total lands in lane 63) ----
 
 template <int CTRL, int ROWMASK, int BANKMASK>
@@ -205,16 +226,8 @@ __device__ inline double rld(double v, uint32_t l)
 template <class T>
 __device__ inline T wl(T v, uint32_t l, T old)
 {
-    return (uint32_t)threadIdx.x == l ? v : old;
+    return (threadIdx.x & (WAVE - 1)) == l ? v : old;
 }
-
-struct Node64 {
-    double cx = 0, cy = 0, cz = 0, l = 0, X = 0, Y = 0, Z = 0, M = 0, hx = 0, hn = 0;
-};
-struct Node32 {
-    uint32_t cX = 0, cY = 0, cZ = 0, tin = 0, X = 0, Y = 0, Z = 0, mixed = 0;
-    float M = 0, half = 0, l2 = 0, hx = 0;
-};
 
 // ----------------------------------------------------------------------------------
 // phase 1: traversal -> interaction lists
@@ -244,13 +257,18 @@ struct ListArgs {
     int32_t* unit_nch;
     int32_t* unit_next;
     int32_t* group_head;
-    int32_t* counters;      // [0] chunks, [1] units, [2] overflow
+    int32_t* counters;      // [0] chunks, [1] units, [2] overflow, [4..5] node tests (u64)
     int64_t cap_chunks;
     int64_t cap_units;
 };
 
+// open and accept masks of one decision
+struct Dec {
+    uint64_t om, am;
+};
+
 struct FrontArgs {
-    uint32_t* buf;          // per wave: ids[2][cap], then masks[2][cap]
+    uint32_t* buf;          // per workgroup: ids[2][TW][cap], then masks[2][TW][cap]
     int64_t cap;
     int32_t* next_group;    // work counter of the persistent waves
     int32_t* overflow;      // set when a level does not fit
@@ -272,22 +290,43 @@ struct FNode<false> {
     float M = 0, half = 0, l2 = 0, hx = 0;
 };
 
-// Breadth-first per group: a level's frontier entries (node, reach mask) are
-// loaded 64 at a time (one per lane) and their decisions, all independent, are
-// taken one after the other; opened nodes put their child nodes on the next
-// level and their child particles on the list.
-template <bool DEC64>
-__global__ __launch_bounds__(WAVE) void k_traverse(WalkArgs a, ListArgs L, FrontArgs F)
+// Breadth-first per group, TW waves per group: every wave holds the same 64
+// targets (lane l = target l).  A level's frontier entries (node, reach mask)
+// are split into TW contiguous ranges, one per wave; a wave loads its range 64
+// entries at a time (one per lane) and takes their decisions, all independent,
+// one after the other.  Opened nodes put their child nodes into the wave's own
+// region of the next level and their child particles on the wave's own list.
+// The next level is the concatenation of the waves' regions in wave order, and
+// the group's units are the waves' unit chains linked in wave order, so the
+// lists and their order do not depend on timing.
+#ifndef SR_TRAV_WAVES
+#define SR_TRAV_WAVES 4
+#endif
+#ifndef SR_TRAV_WG_PER_CU
+#define SR_TRAV_WG_PER_CU 6
+#endif
+constexpr int TW = SR_TRAV_WAVES;
+
+template <bool DEC64, bool REL, bool MIXED>
+__global__ __launch_bounds__(TW * WAVE) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_traverse(WalkArgs a, ListArgs L, FrontArgs F)
 {
-    const int lane = threadIdx.x;
-    uint32_t* ids = F.buf + (int64_t)blockIdx.x * F.cap * 6;
-    uint64_t* masks = (uint64_t*)(ids + 2 * F.cap);
-    const bool mixed = a.nhmax[0] != a.nhmin[0];
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    // frontier regions of this workgroup: [parity][wave] x cap ids, then the same for masks
+    uint32_t* fids = F.buf + (int64_t)blockIdx.x * F.cap * (6 * TW);
+    uint64_t* fmasks = (uint64_t*)(fids + 2 * TW * F.cap);
+    auto rid = [&](int par, int w) -> uint32_t* { return fids + (int64_t)(par * TW + w) * F.cap; };
+    auto rmask = [&](int par, int w) -> uint64_t* { return fmasks + (int64_t)(par * TW + w) * F.cap; };
+    constexpr bool mixed = MIXED;
+    __shared__ int32_t sh_g;
+    __shared__ int32_t sh_cnt[2][TW];     // entries of each wave's region, by level parity
+    __shared__ int32_t sh_ovf[2][TW];     // overflow of each wave, by level parity
+    __shared__ int32_t sh_first[TW], sh_last[TW], sh_wovf[TW];
 
     for (;;) {
-        int32_t g0 = 0;
-        if (lane == 0) g0 = atomicAdd(F.next_group, 1);
-        const int64_t g = (int32_t)rl((uint32_t)g0, 0);
+        if (threadIdx.x == 0) sh_g = atomicAdd(F.next_group, 1);
+        __syncthreads();
+        const int64_t g = __builtin_amdgcn_readfirstlane(sh_g);
         if (g >= F.groups) break;
 
         // ---- targets of group g ----
@@ -319,10 +358,10 @@ __global__ __launch_bounds__(WAVE) void k_traverse(WalkArgs a, ListArgs L, Front
         uint32_t lsrc = 0;
         uint64_t lmask = 0;
         uint32_t nl = 0;
-        int32_t prev_chunk = -1, cur_unit = -1, prev_unit = -1;
+        int32_t prev_chunk = -1, cur_unit = -1, prev_unit = -1, first_unit = -1;
         uint32_t nch = 0, unit_nch = 0;
         bool overflow = false;
-        auto emit = [&]() {
+        auto emit = [&]() __attribute__((always_inline)) {
             int32_t c0 = 0, u0 = 0;
             const bool new_unit = (nch % UCH) == 0;
             if (lane == 0) {
@@ -350,12 +389,12 @@ __global__ __launch_bounds__(WAVE) void k_traverse(WalkArgs a, ListArgs L, Front
                     L.unit_chunk[u] = c;
                     L.unit_next[u] = -1;
                     if (prev_unit >= 0) L.unit_next[prev_unit] = u;
-                    else L.group_head[g] = u;
                 } else {
                     L.chunk_next[prev_chunk] = c;
                 }
             }
             if (new_unit) {
+                if (prev_unit < 0) first_unit = u;
                 prev_unit = u;
                 cur_unit = u;
                 unit_nch = 0;
@@ -365,70 +404,100 @@ __global__ __launch_bounds__(WAVE) void k_traverse(WalkArgs a, ListArgs L, Front
             ++nch;
             nl = 0;
         };
-        auto append = [&](uint32_t src, uint64_t m) {
-            if (nl == (uint32_t)WAVE) emit();
+        // room for `need` more entries; one call site per emission path keeps the code small
+        auto reserve_list = [&](uint32_t need) __attribute__((always_inline)) {
+            if (nl + need > (uint32_t)WAVE) emit();
+        };
+        auto append = [&](uint32_t src, uint64_t m) __attribute__((always_inline)) {
             lsrc = wl(src, nl, lsrc);
             lmask = wl(m, nl, lmask);
             ++nl;
         };
         // a particle entry leaves out the target whose own particle it is
-        auto append_particle = [&](uint32_t s, uint64_t m) {
+        auto append_particle = [&](uint32_t s, uint64_t m) __attribute__((always_inline)) {
             m &= ~__ballot(s_i == (int32_t)s);
             if (m) append(s | ITEM_PARTICLE, m);
         };
 
         // ---- breadth-first levels ----
+        uint64_t tests = 0;    // node-target opening tests of this group (work statistics)
         int cur = 0;
-        int64_t na = 1;
-        if (lane == 0) {
-            ids[0] = 0u;
-            masks[0] = active;
+        if (threadIdx.x == 0) {
+            rid(0, 0)[0] = 0u;
+            rmask(0, 0)[0] = active;
+            for (int w = 0; w < TW; ++w) {
+                sh_cnt[0][w] = w == 0 ? 1 : 0;
+                sh_ovf[0][w] = 0;
+            }
         }
-        while (na > 0 && !overflow) {
-            __syncthreads();
-            uint32_t* nid = ids + (cur ^ 1) * F.cap;
-            uint64_t* nmask = masks + (cur ^ 1) * F.cap;
+        __syncthreads();
+        for (;;) {
+            // the level's size and overflow state, the same for every wave of the group
+            int32_t c[TW];
+            int64_t na = 0;
+            bool lvl_ovf = false;
+#pragma unroll
+            for (int w = 0; w < TW; ++w) {
+                c[w] = __builtin_amdgcn_readfirstlane(sh_cnt[cur][w]);
+                na += c[w];
+                lvl_ovf = lvl_ovf || __builtin_amdgcn_readfirstlane(sh_ovf[cur][w]) != 0;
+            }
+            if (na == 0 || lvl_ovf) break;
+            // this wave's range of the level
+            const int64_t per = (na + TW - 1) / TW;
+            const int64_t e0 = wv * per < na ? wv * per : na;
+            const int64_t e1 = e0 + per < na ? e0 + per : na;
+            uint32_t* nid = rid(cur ^ 1, wv);
+            uint64_t* nmask = rmask(cur ^ 1, wv);
             int64_t nb = 0;          // entries of the next level written so far
             uint32_t qid = 0;        // pending next-level entries (lane q = entry q)
             uint64_t qmask = 0;
             uint32_t nq = 0;
-            auto push = [&](uint32_t nd, uint64_t m) {
-                if (nq == (uint32_t)WAVE) {
-                    if (nb + WAVE <= F.cap) {
-                        nid[nb + lane] = qid;
-                        nmask[nb + lane] = qmask;
+            // write the pending next-level entries out once `need` more would not fit
+            auto reserve_front = [&](uint32_t need) __attribute__((always_inline)) {
+                if (nq + need > (uint32_t)WAVE) {
+                    if (nb + nq <= F.cap) {
+                        if ((uint32_t)lane < nq) {
+                            nid[nb + lane] = qid;
+                            nmask[nb + lane] = qmask;
+                        }
                     } else {
                         if (lane == 0) atomicOr(F.overflow, 1);
                         overflow = true;
                     }
-                    nb += WAVE;
+                    nb += nq;
                     nq = 0;
                 }
+            };
+            auto push = [&](uint32_t nd, uint64_t m) __attribute__((always_inline)) {
                 qid = wl(nd, nq, qid);
                 qmask = wl(m, nq, qmask);
                 ++nq;
             };
-            for (int64_t b0 = 0; b0 < na && !overflow; b0 += WAVE) {
-                const uint32_t cnt = (uint32_t)(na - b0 < WAVE ? na - b0 : WAVE);
+            for (int64_t b0 = e0; b0 < e1 && !overflow; b0 += WAVE) {
+                const uint32_t cnt = (uint32_t)(e1 - b0 < WAVE ? e1 - b0 : WAVE);
                 uint32_t fid = 0, fmeta = 0;
                 uint64_t fmask = 0;
-                uint32_t kid[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+                uint4 kA = make_uint4(0, 0, 0, 0), kB = make_uint4(0, 0, 0, 0);   // child table
                 FNode<DEC64> fn;
                 if ((uint32_t)lane < cnt) {
-                    fid = ids[cur * F.cap + b0 + lane];
-                    fmask = masks[cur * F.cap + b0 + lane];
+                    // entry e of the level lies in the region of the first wave whose
+                    // cumulative count exceeds it
+                    int64_t off = b0 + lane;
+                    int r = 0;
+#pragma unroll
+                    for (int w = 0; w < TW - 1; ++w) {
+                        const bool past = r == w && off >= c[w];
+                        off -= past ? c[w] : 0;
+                        r += past ? 1 : 0;
+                    }
+                    fid = rid(cur, r)[off];
+                    fmask = rmask(cur, r)[off];
                     const uint32_t nd = fid;
                     fmeta = F.meta[nd];
                     const uint4* kp = (const uint4*)(F.kids + 8 * (int64_t)nd);
-                    const uint4 k0 = kp[0], k1 = kp[1];
-                    kid[0] = k0.x;
-                    kid[1] = k0.y;
-                    kid[2] = k0.z;
-                    kid[3] = k0.w;
-                    kid[4] = k1.x;
-                    kid[5] = k1.y;
-                    kid[6] = k1.z;
-                    kid[7] = k1.w;
+                    kA = kp[0];
+                    kB = kp[1];
                     if constexpr (DEC64) {
                         const Geo64 gg = a.ngeo64[nd];
                         const Rec64 c = a.nrec64[nd];
@@ -461,9 +530,11 @@ __global__ __launch_bounds__(WAVE) void k_traverse(WalkArgs a, ListArgs L, Front
                         fn.mixed = mixed && a.nhmin[nd] != a.nhmax[nd];
                     }
                 }
-                for (uint32_t j = 0; j < cnt; ++j) {
-                    const uint32_t nd = rl(fid, j);
+                // decisions of all lanes for frontier entry j, straight-line; two entries are
+                // decided together so that their dependency chains interleave
+                auto decide = [&](uint32_t j) __attribute__((always_inline)) -> Dec {
                     const uint64_t reach = rl64(fmask, j);
+                    tests += (uint64_t)__popcll(reach);
                     bool keep, open, near;
                     if constexpr (DEC64) {
                         const double l = rld(fn.l, j);
@@ -480,8 +551,8 @@ __global__ __launch_bounds__(WAVE) void k_traverse(WalkArgs a, ListArgs L, Front
                         const double dz = min_image(rld(fn.Z, j) - z64, a.box);
                         const double r2 = (dx * dx + dy * dy) + dz * dz;
                         open = inside || l * l > a.theta2 * r2;
-                        if (a.relative) open = open || (a.G * rld(fn.M, j)) * (l * l) > (a.alpha * aold) * (r2 * r2);
-                        if (mixed) {
+                        if constexpr (REL) open = open || (a.G * rld(fn.M, j)) * (l * l) > (a.alpha * aold) * (r2 * r2);
+                        if constexpr (MIXED) {
                             const double hx = rld(fn.hx, j);
                             open = open || (rld(fn.hn, j) != hx && r2 < hx * hx);
                         }
@@ -490,68 +561,113 @@ __global__ __launch_bounds__(WAVE) void k_traverse(WalkArgs a, ListArgs L, Front
                         const uint32_t bx = (uint32_t)abs((int32_t)(rl(fn.cX, j) - X));
                         const uint32_t by = (uint32_t)abs((int32_t)(rl(fn.cY, j) - Y));
                         const uint32_t bz = (uint32_t)abs((int32_t)(rl(fn.cZ, j) - Z));
-                        const float half = rlf(fn.half, j);
-                        const float tx = fmaxf((float)bx - half, 0.0f);
-                        const float ty = fmaxf((float)by - half, 0.0f);
-                        const float tz = fmaxf((float)bz - half, 0.0f);
-                        keep = !(__builtin_fmaf(tx, tx, __builtin_fmaf(ty, ty, tz * tz)) > a.rc2t * 1.0001f);
-                        const uint32_t tin = rl(fn.tin, j);
-                        const bool inside = bx <= tin && by <= tin && bz <= tin;
+                        const uint32_t bm = max(bx, max(by, bz));
+                        // prune (work only): the cube lies beyond r_cut along some axis
+                        keep = !((float)bm - rlf(fn.half, j) > a.rct);
+                        const bool inside = bm <= rl(fn.tin, j);
                         const float dx = (float)(int32_t)(rl(fn.X, j) - X);
                         const float dy = (float)(int32_t)(rl(fn.Y, j) - Y);
                         const float dz = (float)(int32_t)(rl(fn.Z, j) - Z);
                         const float r2 = r2_ticks(dx, dy, dz);
                         const float l2 = rlf(fn.l2, j);
                         open = inside || l2 > a.theta2f * r2;
-                        if (a.relative) {
+                        if constexpr (REL) {
                             const double r2d = (double)r2;
                             open = open || (a.G * (double)rlf(fn.M, j)) * (double)l2 > atau * (r2d * r2d);
                         }
-                        if (mixed) {
+                        if constexpr (MIXED) {
                             const float hx = rlf(fn.hx, j);
                             open = open || (rl(fn.mixed, j) && r2 < hx * hx);
                         }
                         near = r2 < a.rc2t;
                     }
                     const bool live = ((reach >> lane) & 1ull) && keep;
-                    const uint64_t om = __ballot(live && open);
-                    const uint64_t am = __ballot(live && !open && near);
-                    if (am) append(nd, am);
-                    if (!om) continue;
+                    return Dec{__ballot(live && open), __ballot(live && !open && near)};
+                };
+                auto expand = [&](uint32_t j, uint64_t om, uint64_t am) __attribute__((always_inline)) {
+                    if (am) append(rl(fid, j), am);
+                    if (!om) return;
                     const uint32_t meta = rl(fmeta, j);
                     if (meta == META_BUCKET) {
-                        const uint32_t s0 = rl(kid[0], j), sc = rl(kid[1], j);
-                        for (uint32_t s = s0; s < s0 + sc; ++s) append_particle(s, om);
-                        continue;
-                    }
-#pragma unroll
-                    for (int i = 0; i < 8; ++i) {
-                        if ((uint32_t)i < meta) {
-                            const uint32_t c = rl(kid[i], j);
-                            if (c & ITEM_PARTICLE) append_particle(c & ~ITEM_PARTICLE, om);
-                            else push(c, om);
+                        const uint32_t s0 = rl(kA.x, j), sc = rl(kA.y, j);
+                        // keep room for the other expansion of the pair (up to 9 entries)
+                        for (uint32_t s = s0; s < s0 + sc; ++s) {
+                            reserve_list(10);
+                            append_particle(s, om);
                         }
+                        return;
                     }
+                    // branch-free: a particle child goes to the list (minus its own target),
+                    // a node child to the next level
+                    auto child = [&](uint32_t c) __attribute__((always_inline)) {
+                        const bool isp = (c & ITEM_PARTICLE) != 0;
+                        const uint64_t pm = isp ? om & ~__ballot(s_i == (int32_t)(c & ~ITEM_PARTICLE)) : 0ull;
+                        const bool to_list = pm != 0;
+                        lsrc = (to_list && (uint32_t)lane == nl) ? c : lsrc;
+                        lmask = (to_list && (uint32_t)lane == nl) ? pm : lmask;
+                        nl += to_list ? 1u : 0u;
+                        qid = (!isp && (uint32_t)lane == nq) ? c : qid;
+                        qmask = (!isp && (uint32_t)lane == nq) ? om : qmask;
+                        nq += isp ? 0u : 1u;
+                    };
+                    // a node has 2..8 children
+                    child(rl(kA.x, j));
+                    child(rl(kA.y, j));
+                    if (meta > 2) child(rl(kA.z, j));
+                    if (meta > 3) child(rl(kA.w, j));
+                    if (meta > 4) child(rl(kB.x, j));
+                    if (meta > 5) child(rl(kB.y, j));
+                    if (meta > 6) child(rl(kB.z, j));
+                    if (meta > 7) child(rl(kB.w, j));
+                };
+                uint32_t j = 0;
+                for (; j < cnt; j += 2) {
+                    // the second of a pair past the end decides with an empty reach mask
+                    const uint32_t j1 = j + 1 < cnt ? j + 1 : j;
+                    const Dec d0 = decide(j);
+                    Dec d1 = decide(j1);
+                    if (j1 == j) d1 = Dec{0, 0};
+                    // each expansion adds at most 9 list entries (accept + 8 children) and 8 nodes
+                    reserve_list(18);
+                    reserve_front(16);
+                    expand(j, d0.om, d0.am);
+                    expand(j1, d1.om, d1.am);
                 }
             }
             // last partial block of the next level
-            if (nq && !overflow) {
-                if (nb + WAVE <= F.cap) {
-                    if ((uint32_t)lane < nq) {
-                        nid[nb + lane] = qid;
-                        nmask[nb + lane] = qmask;
-                    }
-                } else {
-                    if (lane == 0) atomicOr(F.overflow, 1);
-                    overflow = true;
-                }
+            if (!overflow) reserve_front((uint32_t)WAVE + 1);
+            if (lane == 0) {
+                sh_cnt[cur ^ 1][wv] = overflow ? 0 : (int32_t)nb;
+                sh_ovf[cur ^ 1][wv] = overflow ? 1 : 0;
             }
-            na = nb + nq;
+            __syncthreads();
             cur ^= 1;
         }
         if (nl && !overflow) emit();
         if (lane == 0 && cur_unit >= 0 && !overflow) L.unit_nch[cur_unit] = (int32_t)unit_nch;
-        if (overflow) break;
+        if (lane == 0) {
+            atomicAdd((unsigned long long*)(L.counters + 4), (unsigned long long)tests);
+            sh_first[wv] = first_unit;
+            sh_last[wv] = cur_unit;
+            sh_wovf[wv] = overflow ? 1 : 0;
+        }
+        __syncthreads();
+        bool any_ovf = false;
+#pragma unroll
+        for (int w = 0; w < TW; ++w) any_ovf = any_ovf || __builtin_amdgcn_readfirstlane(sh_wovf[w]) != 0;
+        if (threadIdx.x == 0 && !any_ovf) {
+            // link the waves' unit chains in wave order
+            int32_t head = -1, tail = -1;
+            for (int w = 0; w < TW; ++w) {
+                if (sh_first[w] < 0) continue;
+                if (tail >= 0) L.unit_next[tail] = sh_first[w];
+                else head = sh_first[w];
+                tail = sh_last[w];
+            }
+            L.group_head[g] = head;
+        }
+        if (any_ovf) break;
+        __syncthreads();
     }
 }
 
@@ -783,6 +899,179 @@ __global__ __launch_bounds__(WAVE) void k_eval(WalkArgs a, ListArgs L, char* __r
     }
 }
 
+// Sum over each row of 16 lanes (DPP row shifts); lane 16k + 15 holds row k's total.
+__device__ inline float row_sum15(float x)
+{
+    float v = x + dpp_f32<0x111, 0xf, 0xf>(x);
+    v = v + dpp_f32<0x112, 0xf, 0xf>(x);
+    v = v + dpp_f32<0x113, 0xf, 0xf>(x);
+    v = v + dpp_f32<0x114, 0xf, 0xe>(v);
+    v = v + dpp_f32<0x118, 0xf, 0xc>(v);
+    return v;
+}
+
+// FP32 evaluation of one unit, packed by quarters.  A quarter is a row of 16
+// lanes (16 Morton-consecutive targets).  For each chunk the entries whose mask
+// touches quarter k form quarter k's stream; step s evaluates entry
+// stream_k[s] on the lanes of quarter k, for all four quarters at once, so a
+// chunk takes max_k |stream_k| steps instead of one step per entry.  Source
+// records are staged in LDS, 32 bytes per entry; each quarter reads its own
+// entry (a broadcast within the row).  Slots past the end of a stream name
+// entry 64, whose mask is empty.  The adjoint's source terms are summed per row
+// with DPP and added with one atomic per (row, component).
+struct SrcLds {
+    uint32_t X, Y, Z, m;        // integer position, mass bits (mass scaled by 2^64)
+    uint32_t h, inc, mlo, mhi;  // support h bits, count increment, mask of lanes 0-31 / 32-63
+};
+
+template <int PREC, bool ADJ>
+__global__ __launch_bounds__(WAVE) void k_eval32(WalkArgs a, ListArgs L, char* __restrict__ partials)
+{
+    using acc_t = typename std::conditional<PREC == PR32, float, double>::type;
+    static_assert(PREC != PR64, "FP32 kernel");
+    __shared__ SrcLds s_ent[WAVE + 1];
+    __shared__ uint32_t s_src[WAVE];
+    __shared__ uint8_t s_stream[4][WAVE];
+    const int lane = threadIdx.x;
+    const int quarter = lane >> 4;
+    const uint32_t bit = 1u << (lane & 31);
+    const bool hi_half = lane >= 32;
+    const int32_t u = blockIdx.x;
+    const int64_t g = L.unit_group[u];
+    const int64_t t = g * WAVE + lane;
+    const bool valid = t < a.n_t;
+    const int32_t s_i = valid ? a.tgt_sorted[t] : 0;
+    const Rec32 tr = a.prec32[s_i];
+    const uint32_t X = tr.X, Y = tr.Y, Z = tr.Z;
+    const uint32_t h32b = __float_as_uint(a.ph32[s_i]);   // supports are >= 0: integer order is float order
+    acc_t ax = 0, ay = 0, az = 0;
+    uint32_t cnt2 = 0;       // interactions: particles in the low half, nodes in the high half
+    float wx = 0, wy = 0, wz = 0;
+    acc_t tbx = 0, tby = 0, tbz = 0;
+    if constexpr (ADJ) {
+        if (valid) {
+            const int32_t slot = a.tgt_slot[t];
+            const acc_t* w = (const acc_t*)a.w;
+            wx = (float)w[3 * (int64_t)slot];
+            wy = (float)w[3 * (int64_t)slot + 1];
+            wz = (float)w[3 * (int64_t)slot + 2];
+        }
+    }
+    if (lane == 0) s_ent[WAVE] = SrcLds{0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+
+    int32_t c = L.unit_chunk[u];
+    const int32_t nch = L.unit_nch[u];
+    for (int32_t q = 0; q < nch; ++q) {
+        const uint32_t cnt = (uint32_t)L.chunk_cnt[c];
+        const bool has = (uint32_t)lane < cnt;
+        uint64_t lmask = 0;
+        if (has) {
+            const uint32_t lsrc = L.ent_src[64 * (int64_t)c + lane];
+            lmask = L.ent_mask[64 * (int64_t)c + lane];
+            const bool isp = lsrc & ITEM_PARTICLE;
+            const uint32_t idx = lsrc & ~ITEM_PARTICLE;
+            const Rec32 r = isp ? a.prec32[idx] : a.nrec32[idx];
+            const float hs = isp ? a.ph32[idx] : a.nhmax32[idx];
+            s_ent[lane] = SrcLds{r.X, r.Y, r.Z, __float_as_uint(r.m * TWO64_F), __float_as_uint(hs),
+                                 isp ? 1u : 0x10000u, (uint32_t)lmask, (uint32_t)(lmask >> 32)};
+            s_src[lane] = lsrc;
+        }
+        // the four quarter streams, each in entry order, padded with entry 64
+        const uint64_t below = (1ull << lane) - 1ull;
+        uint32_t nk[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint64_t b = __ballot(has && ((lmask >> (16 * k)) & 0xffffull) != 0);
+            nk[k] = __popcll(b);
+            if ((b >> lane) & 1) s_stream[k][__popcll(b & below)] = (uint8_t)lane;
+            if ((uint32_t)lane >= nk[k]) s_stream[k][lane] = (uint8_t)WAVE;   // slots past the stream
+        }
+        const uint32_t steps = max(max(nk[0], nk[1]), max(nk[2], nk[3]));
+        const int32_t cnext = L.chunk_next[c];
+        __syncthreads();
+        for (uint32_t st = 0; st < steps; ++st) {
+            const uint32_t e = s_stream[quarter][st];
+            const SrcLds src = s_ent[e];
+            const uint32_t mw = hi_half ? src.mhi : src.mlo;
+            const bool on = (mw & bit) != 0;
+            const float hp = __uint_as_float(max(h32b, src.h));
+            const float qm = __uint_as_float(src.m);
+            const float dx = (float)(int32_t)(src.X - X);
+            const float dy = (float)(int32_t)(src.Y - Y);
+            const float dz = (float)(int32_t)(src.Z - Z);
+            const float r2 = r2_ticks(dx, dy, dz);
+            const bool in = on && r2 < a.rc2t;
+            // r2 = 0 (coincident particles) gives r = 0 and a finite rinv; such a pair is
+            // always inside the softening support
+            const float rinv = __builtin_amdgcn_rsqf(__uint_as_float(max(__float_as_uint(r2), 0x0da24260u)));   // max(r2, 1e-30)
+            const float r = r2 * rinv;
+            const float uu = r * a.inv2rs_t;
+            float ex;
+            const float gg = gshort32(uu, ex);
+            float S = rinv * rinv * rinv;
+            float Srd = -3.0f * S;
+            if (in && r < hp) {
+                const float ih = __builtin_amdgcn_rcpf(hp);
+                const float qq = r * ih;
+                const float ih3 = ih * ih * ih;
+                S = spline_h3S_32f(qq) * ih3;
+                if constexpr (ADJ) Srd = spline_h4dS_32f(qq) * qq * ih3;
+            }
+            cnt2 += in ? src.inc : 0u;
+            const float K = in ? S * gg : 0.0f;
+            if constexpr (!ADJ) {
+                const float f = qm * K;
+                ax += (acc_t)(f * dx);
+                ay += (acc_t)(f * dy);
+                az += (acc_t)(f * dz);
+            } else {
+                // J w = K w + (K' r)(w . n) n,  K' r = r S' g + S g'(u) u
+                const float dg = -2.0f * TWO_OVER_SQRTPI_F * uu * uu * ex;
+                const float Kr = in ? Srd * gg + S * dg * uu : 0.0f;
+                const float nx = dx * rinv, ny = dy * rinv, nz = dz * rinv;
+                const float wn = __builtin_fmaf(wx, nx, __builtin_fmaf(wy, ny, wz * nz));
+                const float wd = __builtin_fmaf(wx, dx, __builtin_fmaf(wy, dy, wz * dz));
+                const float cc = Kr * wn;
+                const float px = qm * __builtin_fmaf(K, wx, cc * nx);
+                const float py = qm * __builtin_fmaf(K, wy, cc * ny);
+                const float pz = qm * __builtin_fmaf(K, wz, cc * nz);
+                tbx -= (acc_t)px;
+                tby -= (acc_t)py;
+                tbz -= (acc_t)pz;
+                // source terms: per-row sums, one atomic per (row, component)
+                const float sx = row_sum15(px);
+                const float sy = row_sum15(py);
+                const float sz = row_sum15(pz);
+                const float sm = row_sum15(K * wd);
+                if ((lane & 15) == 15 && e < (uint32_t)WAVE) {
+                    const uint32_t sid = s_src[e];
+                    double* dst = (sid & ITEM_PARTICLE) ? a.pbar + 4 * (int64_t)(sid & ~ITEM_PARTICLE)
+                                                        : a.nbar + 4 * (int64_t)sid;
+                    unsafeAtomicAdd(dst + 0, (double)sx);
+                    unsafeAtomicAdd(dst + 1, (double)sy);
+                    unsafeAtomicAdd(dst + 2, (double)sz);
+                    unsafeAtomicAdd(dst + 3, (double)sm);
+                }
+            }
+        }
+        __syncthreads();
+        c = cnext;
+    }
+    acc_t* pa = (acc_t*)(partials + (int64_t)u * PARTIAL_BYTES);
+    if constexpr (!ADJ) {
+        pa[lane] = ax;
+        pa[64 + lane] = ay;
+        pa[128 + lane] = az;
+        int32_t* pc = (int32_t*)(pa + 192);
+        pc[lane] = (int32_t)(cnt2 & 0xffffu);
+        pc[64 + lane] = (int32_t)(cnt2 >> 16);
+    } else {
+        pa[lane] = tbx;
+        pa[64 + lane] = tby;
+        pa[128 + lane] = tbz;
+    }
+}
+
 // ----------------------------------------------------------------------------------
 // phase 3: per group, sum the units' partials in their order and write the outputs
 // ----------------------------------------------------------------------------------
@@ -969,6 +1258,7 @@ WalkArgs make_args(const sr_tree* t, const sr_params* p, int64_t n_t, const doub
     a.relative = p->criterion == SR_OPEN_RELATIVE;
     const double tick = t->box / TWO32;
     a.rc2t = (float)((p->r_cut / tick) * (p->r_cut / tick));
+    a.rct = (float)(p->r_cut / tick * 1.0001);
     a.theta2f = (float)(p->theta * p->theta);
     a.inv2rs_t = (float)(tick / (2.0 * p->r_s));
     a.tau2 = tick * tick;
@@ -1012,17 +1302,17 @@ int traverse(sr_tree* t, const sr_params* p, int64_t n_t, const int32_t* active,
     int64_t want = 32 * n_t;
     if (want < (int64_t)1 << 16) want = (int64_t)1 << 16;
     int64_t fcap = t->cap_front > 4096 ? t->cap_front : 4096;
-    // persistent traversal waves: 16 per CU, at most one per group
+    // persistent traversal workgroups of TW waves, at most one per group
     int dev = 0, cus = 0;
     SR_HIP(hipGetDevice(&dev));
     SR_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    const int64_t waves = groups < 16 * (int64_t)cus ? groups : 16 * (int64_t)cus;
+    const int64_t wgs = groups < SR_TRAV_WG_PER_CU * (int64_t)cus ? groups : SR_TRAV_WG_PER_CU * (int64_t)cus;
     for (int attempt = 0; attempt < 8; ++attempt) {
         int rc = sr_list_reserve(t, groups, (want + 63) / 64, (int64_t)UCH);
         if (rc) return rc;
-        if ((rc = sr_front_reserve(t, waves, fcap))) return rc;
+        if ((rc = sr_front_reserve(t, wgs * TW, fcap))) return rc;
         hipLaunchKernelGGL(k_fill_i32w, g256(groups), dim3(256), 0, st, t->group_head, groups, -1);
-        hipLaunchKernelGGL(k_fill_i32w, g256(4), dim3(256), 0, st, t->list_counters, (int64_t)4, 0);
+        hipLaunchKernelGGL(k_fill_i32w, g256(8), dim3(256), 0, st, t->list_counters, (int64_t)8, 0);
         const WalkArgs a = make_args(t, p, n_t, a_old);
         const ListArgs L = list_args(t);
         FrontArgs F{};
@@ -1034,16 +1324,30 @@ int traverse(sr_tree* t, const sr_params* p, int64_t n_t, const int32_t* active,
         F.meta = t->n_meta;
         F.groups = groups;
         sr_timing_mark(SR_T_TRAVERSE, true, st);
-        if (p->precision == SR_FP64) hipLaunchKernelGGL(k_traverse<true>, dim3((unsigned)waves), dim3(WAVE), 0, st, a, L, F);
-        else hipLaunchKernelGGL(k_traverse<false>, dim3((unsigned)waves), dim3(WAVE), 0, st, a, L, F);
+        const dim3 gw((unsigned)wgs), bw(TW * WAVE);
+        const bool rel = p->criterion == SR_OPEN_RELATIVE, mix = t->mixed_soft;
+        const int variant = (p->precision == SR_FP64 ? 4 : 0) + (rel ? 2 : 0) + (mix ? 1 : 0);
+        switch (variant) {
+        case 0: hipLaunchKernelGGL((k_traverse<false, false, false>), gw, bw, 0, st, a, L, F); break;
+        case 1: hipLaunchKernelGGL((k_traverse<false, false, true>), gw, bw, 0, st, a, L, F); break;
+        case 2: hipLaunchKernelGGL((k_traverse<false, true, false>), gw, bw, 0, st, a, L, F); break;
+        case 3: hipLaunchKernelGGL((k_traverse<false, true, true>), gw, bw, 0, st, a, L, F); break;
+        case 4: hipLaunchKernelGGL((k_traverse<true, false, false>), gw, bw, 0, st, a, L, F); break;
+        case 5: hipLaunchKernelGGL((k_traverse<true, false, true>), gw, bw, 0, st, a, L, F); break;
+        case 6: hipLaunchKernelGGL((k_traverse<true, true, false>), gw, bw, 0, st, a, L, F); break;
+        default: hipLaunchKernelGGL((k_traverse<true, true, true>), gw, bw, 0, st, a, L, F); break;
+        }
         sr_timing_mark(SR_T_TRAVERSE, false, st);
         SR_HIP(hipGetLastError());
-        int32_t cnt[4];
+        int32_t cnt[8];
         SR_HIP(hipMemcpyAsync(cnt, t->list_counters, sizeof(cnt), hipMemcpyDeviceToHost, st));
         SR_HIP(hipStreamSynchronize(st));
         if (!cnt[2]) {
             t->n_units = cnt[1];
             t->n_chunks = cnt[0];
+            int64_t tests;
+            memcpy(&tests, cnt + 4, sizeof(tests));
+            t->n_tests = tests;
             ListKey& k = t->lkey;
             k.valid = true;
             k.gen = t->build_gen;
@@ -1077,8 +1381,8 @@ int eval_and_reduce(sr_tree* t, const sr_params* p, const WalkArgs& a, hipStream
         sr_timing_mark(ph_eval, true, st);
         switch (p->precision) {
         case SR_FP64: hipLaunchKernelGGL((k_eval<PR64, ADJ>), gu, dim3(WAVE), 0, st, a, L, t->partials); break;
-        case SR_FP32: hipLaunchKernelGGL((k_eval<PR32, ADJ>), gu, dim3(WAVE), 0, st, a, L, t->partials); break;
-        default: hipLaunchKernelGGL((k_eval<PR32A, ADJ>), gu, dim3(WAVE), 0, st, a, L, t->partials); break;
+        case SR_FP32: hipLaunchKernelGGL((k_eval32<PR32, ADJ>), gu, dim3(WAVE), 0, st, a, L, t->partials); break;
+        default: hipLaunchKernelGGL((k_eval32<PR32A, ADJ>), gu, dim3(WAVE), 0, st, a, L, t->partials); break;
         }
         sr_timing_mark(ph_eval, false, st);
     }
