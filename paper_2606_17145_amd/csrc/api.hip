@@ -112,6 +112,8 @@ void free_workspace(sr_tree* t)
     release(t->items);
     release(t->n_kids);
     release(t->n_meta);
+    release(t->wrec32);
+    release(t->wrec64);
     release(t->tgt_sorted);
     release(t->tgt_slot);
     release(t->mark);
@@ -181,6 +183,8 @@ int allocate_workspace(sr_tree* t, int64_t cap)
     A(t->items, 2 * cap);
     A(t->n_kids, 8 * nodes);
     A(t->n_meta, nodes);
+    A(t->wrec32, nodes);
+    A(t->wrec64, nodes);
     A(t->tgt_sorted, cap);
     A(t->tgt_slot, cap);
     A(t->mark, cap);
@@ -242,9 +246,8 @@ int sr_front_reserve(sr_tree* t, int64_t waves, int64_t cap)
     return SR_OK;
 }
 
-int sr_list_reserve(sr_tree* t, int64_t groups, int64_t chunks, int64_t chunks_per_unit)
+int sr_list_reserve(sr_tree* t, int64_t groups, int64_t chunks, int64_t units)
 {
-    const int64_t units = groups + chunks / chunks_per_unit + 1;
     if (groups <= t->cap_groups && chunks <= t->cap_chunks && units <= t->cap_units) return SR_OK;
     // the old lists may still be read by queued work
     SR_HIP(hipDeviceSynchronize());

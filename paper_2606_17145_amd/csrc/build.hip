@@ -531,6 +531,60 @@ __global__ void k_moments(const int32_t* __restrict__ order, int64_t count, doub
     meta[nd] = bucket ? META_BUCKET : nk;
 }
 
+// The walk's per-node records (one 128-byte line each), from the node arrays.
+__global__ void k_walk_records(int64_t m, const int32_t* __restrict__ n_level,
+                               const uint32_t* __restrict__ n_corner, const Rec32* __restrict__ nrec32,
+                               const float* __restrict__ nhmax32, const Rec64* __restrict__ nrec64,
+                               const Geo64* __restrict__ geo, const double* __restrict__ nhmax,
+                               const double* __restrict__ nhmin, const uint32_t* __restrict__ kids,
+                               const uint32_t* __restrict__ meta, WalkRec32* __restrict__ w32,
+                               WalkRec64* __restrict__ w64)
+{
+    const int64_t nd = blockIdx.x * (int64_t)TPB + threadIdx.x;
+    if (nd >= m) return;
+    const int lev = n_level[nd];
+    const uint32_t half = 1u << (31 - lev);
+    const uint64_t lint = 1ull << (32 - lev);
+    const Rec32 c32 = nrec32[nd];
+    const Rec64 c64 = nrec64[nd];
+    const Geo64 g = geo[nd];
+    const double hx = nhmax[nd], hn = nhmin[nd];
+    const uint32_t mt = meta[nd];
+    WalkRec32 a{};
+    a.cX = n_corner[3 * nd + 0] + half;
+    a.cY = n_corner[3 * nd + 1] + half;
+    a.cZ = n_corner[3 * nd + 2] + half;
+    a.tin = (uint32_t)((3ull * lint - 1ull) / 5ull);   // largest integer below 0.6 l
+    a.X = c32.X;
+    a.Y = c32.Y;
+    a.Z = c32.Z;
+    a.l2 = __float_as_uint((float)lint * (float)lint);
+    a.half = __float_as_uint((float)half);
+    a.M = __float_as_uint(c32.m);
+    a.hx = __float_as_uint(nhmax32[nd]);
+    a.mixed = hn != hx ? 1u : 0u;
+    a.meta = mt;
+    WalkRec64 b{};
+    b.cx = g.cx;
+    b.cy = g.cy;
+    b.cz = g.cz;
+    b.l = g.l;
+    b.X = c64.x;
+    b.Y = c64.y;
+    b.Z = c64.z;
+    b.M = c64.m;
+    b.hx = hx;
+    b.hn = hn;
+    b.meta = mt;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        a.kids[k] = kids[8 * nd + k];
+        b.kids[k] = a.kids[k];
+    }
+    w32[nd] = a;
+    w64[nd] = b;
+}
+
 __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v)
 {
     int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x;
@@ -640,6 +694,10 @@ int sr_build_device(sr_tree* t, const double* pos, const double* mass, const dou
                            t->n_first, t->n_level, t->n_corner, t->prec64, t->ph64, t->nrec64, t->nS, t->ngeo64,
                            t->nhmax, t->nhmin, t->nrec32, t->nhmax32, t->n_kids, t->n_meta, t->n_count);
     }
+    if (m > 0)
+        hipLaunchKernelGGL(k_walk_records, grid_for(m), dim3(TPB), 0, st, m, t->n_level, t->n_corner, t->nrec32,
+                           t->nhmax32, t->nrec64, t->ngeo64, t->nhmax, t->nhmin, t->n_kids, t->n_meta,
+                           t->wrec32, t->wrec64);
     SR_HIP(hipGetLastError());
     // the root's softening range tells whether any two particles differ
     double hr[2];

@@ -28,6 +28,25 @@ struct Geo64 {
     double cx, cy, cz, l;
 };
 
+// Everything the walk reads about one node, packed into one 128-byte line
+// (written by the build after the moments): decision data and child table.
+struct alignas(16) WalkRec32 {
+    uint32_t cX, cY, cZ, tin;     // cube centre (ticks), 0.6 side rounded down (ticks)
+    uint32_t X, Y, Z, l2;         // centre of mass (ticks), side^2 (float bits, ticks^2)
+    uint32_t half, M, hx, mixed;  // half side, mass, h_max (float bits), mixed softening flag
+    uint32_t meta, r0, r1, r2;    // child count or META_BUCKET
+    uint32_t kids[8];
+    uint32_t pad[8];
+};
+struct alignas(16) WalkRec64 {
+    double cx, cy, cz, l;         // cube centre and side
+    double X, Y, Z, M;            // centre of mass and mass
+    double hx, hn;                // largest and smallest support h below the node
+    uint32_t meta, r0, r1, r2;    // child count or META_BUCKET
+    uint32_t kids[8];
+};
+static_assert(sizeof(WalkRec32) == 128 && sizeof(WalkRec64) == 128, "one line per node");
+
 // One entry of the combined pre-order sequence.
 //   ref:   node index, or (sorted particle position | ITEM_PARTICLE)
 //   next:  item index after this entry's subtree
@@ -106,6 +125,8 @@ struct sr_tree {
     Item* items = nullptr;
     uint32_t* n_kids = nullptr;       // 8 per node: children (node index or particle | ITEM_PARTICLE)
     uint32_t* n_meta = nullptr;
+    WalkRec32* wrec32 = nullptr;      // per node, for the walk
+    WalkRec64* wrec64 = nullptr;
 
     // walk workspace (cap)
     int32_t *tgt_sorted = nullptr, *tgt_slot = nullptr, *mark = nullptr;
@@ -166,7 +187,7 @@ int sr_axpy_device(void* y, int y_type, const void* x, int x_type, double a, int
 bool sr_timing_on();
 void sr_timing_mark(int phase, bool start, hipStream_t st);
 
-// api.hip: make room for the lists of `groups` target groups and `chunks` chunks
-int sr_list_reserve(sr_tree* t, int64_t groups, int64_t chunks, int64_t chunks_per_unit);
+// api.hip: make room for the lists of `groups` target groups, `chunks` chunks and `units` units
+int sr_list_reserve(sr_tree* t, int64_t groups, int64_t chunks, int64_t units);
 // api.hip: frontier scratch of `waves` persistent traversal waves, `cap` entries per level
 int sr_front_reserve(sr_tree* t, int64_t waves, int64_t cap);

@@ -272,56 +272,131 @@ struct FrontArgs {
     int64_t cap;
     int32_t* next_group;    // work counter of the persistent waves
     int32_t* overflow;      // set when a level does not fit
-    const uint32_t* kids;
-    const uint32_t* meta;
+    const WalkRec32* w32;   // per-node walk records
+    const WalkRec64* w64;
     int64_t groups;
+    int contig;             // the targets are all particles in sorted order (target t = particle t)
 };
 
-// Node decision data of the frontier entry a lane holds.
+// Orders the LDS accesses of one wavefront among its lanes: LDS operations of
+// a wavefront complete in order, so this is a compiler barrier and waits for no
+// memory operation (in particular not for pending atomics).
+__device__ inline void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Node data of one frontier entry, staged in LDS for the decisions of a block
+// (read back as a broadcast: every lane reads the same record).
 template <bool DEC64>
-struct FNode;
+struct NodeRec;
 template <>
-struct FNode<true> {
-    double cx = 0, cy = 0, cz = 0, l = 0, X = 0, Y = 0, Z = 0, M = 0, hx = 0, hn = 0;
+struct NodeRec<false> {
+    uint32_t cX, cY, cZ, tin;      // cube centre (ticks), 0.6 side rounded down (ticks)
+    uint32_t X, Y, Z, l2;          // centre of mass (ticks), side^2 (float bits, ticks^2)
+    uint32_t half, M, hx, mixed;   // half side, mass, h_max (float bits), mixed softening
+    uint32_t rlo, rhi, id, meta;   // reach mask, node id, child count or META_BUCKET
 };
 template <>
-struct FNode<false> {
-    uint32_t cX = 0, cY = 0, cZ = 0, tin = 0, X = 0, Y = 0, Z = 0, mixed = 0;
-    float M = 0, half = 0, l2 = 0, hx = 0;
+struct NodeRec<true> {
+    double cx, cy, cz, l, X, Y, Z, M, hx, hn;
+    uint32_t rlo, rhi, id, meta;
 };
+
+// Sum of a uint32 over the 64 lanes (DPP, total in lane 63).
+__device__ inline uint32_t wave_sum63_u32(uint32_t x)
+{
+    uint32_t v = x + (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false);
+    v = v + (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false);
+    v = v + (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x113, 0xf, 0xf, false);
+    v = v + (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xe, false);
+    v = v + (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xc, false);
+    v = v + (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);
+    v = v + (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);
+    return v;
+}
 
 // Breadth-first per group, TW waves per group: every wave holds the same 64
 // targets (lane l = target l).  A level's frontier entries (node, reach mask)
-// are split into TW contiguous ranges, one per wave; a wave loads its range 64
-// entries at a time (one per lane) and takes their decisions, all independent,
-// one after the other.  Opened nodes put their child nodes into the wave's own
-// region of the next level and their child particles on the wave's own list.
-// The next level is the concatenation of the waves' regions in wave order, and
-// the group's units are the waves' unit chains linked in wave order, so the
-// lists and their order do not depend on timing.
+// are split into TW contiguous ranges, one per wave.  A wave takes its range 64
+// entries at a time: it stages the entries' node data in LDS, takes their
+// decisions one after the other (each a 64-lane test of every reached target
+// against one node, the records read as LDS broadcasts), and then expands the
+// block lane-parallel: accepted nodes become list entries, and the children of
+// opened nodes -- eight nodes by eight children per step -- go to the list
+// (particles, without the target that is the particle itself) or to the wave's
+// region of the next level (nodes).  The next level is the concatenation of
+// the waves' regions in wave order, and the group's units are the waves' unit
+// chains linked in wave order, so the lists and their order do not depend on
+// timing.
 #ifndef SR_TRAV_WAVES
-#define SR_TRAV_WAVES 4
+#define SR_TRAV_WAVES 2
 #endif
 #ifndef SR_TRAV_WG_PER_CU
-#define SR_TRAV_WG_PER_CU 6
+#define SR_TRAV_WG_PER_CU 8
 #endif
+
 constexpr int TW = SR_TRAV_WAVES;
+#ifndef SR_CHUNK_BATCH
+#define SR_CHUNK_BATCH 16
+#endif
+#ifndef SR_UNIT_BATCH
+#define SR_UNIT_BATCH 1
+#endif
+constexpr int TRAV_CHUNK_BATCH = SR_CHUNK_BATCH;   // chunk indices reserved per atomic
+constexpr int TRAV_UNIT_BATCH = SR_UNIT_BATCH;     // unit indices reserved per atomic
 
 template <bool DEC64, bool REL, bool MIXED>
-__global__ __launch_bounds__(TW * WAVE) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_traverse(WalkArgs a, ListArgs L, FrontArgs F)
+__global__ __launch_bounds__(TW * WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_traverse(WalkArgs a, ListArgs L, FrontArgs F)
 {
     const int lane = threadIdx.x & (WAVE - 1);
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const uint64_t below = (1ull << lane) - 1ull;
     // frontier regions of this workgroup: [parity][wave] x cap ids, then the same for masks
     uint32_t* fids = F.buf + (int64_t)blockIdx.x * F.cap * (6 * TW);
     uint64_t* fmasks = (uint64_t*)(fids + 2 * TW * F.cap);
     auto rid = [&](int par, int w) -> uint32_t* { return fids + (int64_t)(par * TW + w) * F.cap; };
     auto rmask = [&](int par, int w) -> uint64_t* { return fmasks + (int64_t)(par * TW + w) * F.cap; };
-    constexpr bool mixed = MIXED;
+    __shared__ NodeRec<DEC64> s_rec[TW][WAVE];
+    __shared__ uint32_t s_kids[TW][WAVE][8];
+    __shared__ uint64_t s_om[TW][WAVE];
+    __shared__ uint32_t s_open[TW][WAVE];     // block positions of the opened nodes
+    __shared__ uint32_t s_tgt[WAVE + 1];      // sorted particle index of each target (ascending)
     __shared__ int32_t sh_g;
     __shared__ int32_t sh_cnt[2][TW];     // entries of each wave's region, by level parity
     __shared__ int32_t sh_ovf[2][TW];     // overflow of each wave, by level parity
     __shared__ int32_t sh_first[TW], sh_last[TW], sh_wovf[TW];
+    NodeRec<DEC64>* rec = s_rec[wv];
+
+    // Chunk and unit indices: each wave reserves them in batches (one atomic per
+    // TRAV_CHUNK_BATCH chunks / TRAV_UNIT_BATCH units on the shared counters) and
+    // hands them out in order.  `cc` is the chunk being filled and `cn` the one
+    // after it; both carry over to the next group.  Reserved units a wave never
+    // uses are written as empty when it exits; unused chunks are never read.
+    uint32_t c_next = 0, c_end = 0, u_next = 0, u_end = 0;
+    uint64_t tests_all = 0;
+    auto take_chunk = [&]() __attribute__((always_inline)) -> int64_t {
+        if (c_next == c_end) {
+            uint32_t b = 0;
+            if (lane == 0) b = atomicAdd((uint32_t*)&L.counters[0], (uint32_t)TRAV_CHUNK_BATCH);
+            c_next = rl(b, 0);
+            c_end = c_next + TRAV_CHUNK_BATCH;
+        }
+        return c_next++;
+    };
+    auto take_unit = [&]() __attribute__((always_inline)) -> int32_t {
+        if (u_next == u_end) {
+            uint32_t b = 0;
+            if (lane == 0) b = atomicAdd((uint32_t*)&L.counters[1], (uint32_t)TRAV_UNIT_BATCH);
+            u_next = rl(b, 0);
+            u_end = u_next + TRAV_UNIT_BATCH;
+        }
+        return (int32_t)u_next++;
+    };
+    int64_t cc = take_chunk();
+    int64_t cn = take_chunk();
 
     for (;;) {
         if (threadIdx.x == 0) sh_g = atomicAdd(F.next_group, 1);
@@ -353,35 +428,28 @@ __global__ __launch_bounds__(TW * WAVE) __attribute__((amdgpu_waves_per_eu(5, 8)
             }
         }
         const uint64_t active = __ballot(valid);
+        if (wv == 0) {
+            s_tgt[lane] = valid ? (uint32_t)s_i : 0xffffffffu;
+            if (lane == 0) s_tgt[WAVE] = 0xffffffffu;
+        }
 
-        // ---- list entries of this group, emitted in chunks ----
-        uint32_t lsrc = 0;
-        uint64_t lmask = 0;
-        uint32_t nl = 0;
+        // ---- list entries of this group, written straight into chunks ----
+        uint32_t nl = 0;                       // entries in chunk cc
         int32_t prev_chunk = -1, cur_unit = -1, prev_unit = -1, first_unit = -1;
         uint32_t nch = 0, unit_nch = 0;
         bool overflow = false;
-        auto emit = [&]() __attribute__((always_inline)) {
-            int32_t c0 = 0, u0 = 0;
+        // close chunk cc with `count` entries, link it into the unit chain, move on to cn
+        auto finish_chunk = [&](uint32_t count) __attribute__((always_inline)) {
             const bool new_unit = (nch % UCH) == 0;
-            if (lane == 0) {
-                c0 = atomicAdd(&L.counters[0], 1);
-                if (new_unit) u0 = atomicAdd(&L.counters[1], 1);
-            }
-            const int32_t c = (int32_t)rl((uint32_t)c0, 0);
-            const int32_t u = (int32_t)rl((uint32_t)u0, 0);
-            if (c >= L.cap_chunks || (new_unit && u >= L.cap_units)) {
+            const int32_t c = (int32_t)cc;
+            const int32_t u = new_unit ? take_unit() : -1;
+            if (new_unit && u >= L.cap_units) {
                 if (lane == 0) atomicOr(&L.counters[2], 1);
                 overflow = true;
-                nl = 0;
                 return;
             }
-            if ((uint32_t)lane < nl) {
-                L.ent_src[64 * (int64_t)c + lane] = lsrc;
-                L.ent_mask[64 * (int64_t)c + lane] = lmask;
-            }
             if (lane == 0) {
-                L.chunk_cnt[c] = (int32_t)nl;
+                L.chunk_cnt[c] = (int32_t)count;
                 L.chunk_next[c] = -1;
                 if (new_unit) {
                     if (cur_unit >= 0) L.unit_nch[cur_unit] = (int32_t)unit_nch;
@@ -402,26 +470,49 @@ __global__ __launch_bounds__(TW * WAVE) __attribute__((amdgpu_waves_per_eu(5, 8)
             ++unit_nch;
             prev_chunk = c;
             ++nch;
-            nl = 0;
+            cc = cn;
+            cn = take_chunk();
         };
-        // room for `need` more entries; one call site per emission path keeps the code small
-        auto reserve_list = [&](uint32_t need) __attribute__((always_inline)) {
-            if (nl + need > (uint32_t)WAVE) emit();
+        // append one entry per lane set in `b` (in lane order): source `src`, mask `m`
+        auto append = [&](uint64_t b, uint32_t src, uint64_t m) __attribute__((always_inline)) {
+            if (!b || overflow) return;
+            if (cc >= L.cap_chunks || cn >= L.cap_chunks) {
+                if (lane == 0) atomicOr(&L.counters[2], 1);
+                overflow = true;
+                return;
+            }
+            if ((b >> lane) & 1) {
+                const uint32_t slot = nl + (uint32_t)__popcll(b & below);
+                const int64_t ch = slot < (uint32_t)WAVE ? cc : cn;
+                const int64_t at = 64 * ch + (slot & (WAVE - 1));
+                L.ent_src[at] = src;
+                L.ent_mask[at] = m;
+            }
+            nl += (uint32_t)__popcll(b);
+            if (nl >= (uint32_t)WAVE) {
+                finish_chunk((uint32_t)WAVE);
+                nl -= (uint32_t)WAVE;
+            }
         };
-        auto append = [&](uint32_t src, uint64_t m) __attribute__((always_inline)) {
-            lsrc = wl(src, nl, lsrc);
-            lmask = wl(m, nl, lmask);
-            ++nl;
-        };
-        // a particle entry leaves out the target whose own particle it is
-        auto append_particle = [&](uint32_t s, uint64_t m) __attribute__((always_inline)) {
-            m &= ~__ballot(s_i == (int32_t)s);
-            if (m) append(s | ITEM_PARTICLE, m);
+        // the lane of the target whose own particle is sorted particle s, or none:
+        // with all particles as targets it is s - 64 g, else a search of the group's
+        // (ascending) target particles
+        auto own_bit = [&](uint32_t s) __attribute__((always_inline)) -> uint64_t {
+            if (F.contig) {
+                const uint32_t o = s - (uint32_t)(g * WAVE);
+                return o < (uint32_t)WAVE ? (1ull << o) : 0ull;
+            }
+            uint32_t pos = 0;
+#pragma unroll
+            for (uint32_t st = 32; st; st >>= 1)
+                if (s_tgt[pos + st - 1] < s) pos += st;
+            return s_tgt[pos] == s ? (1ull << pos) : 0ull;
         };
 
         // ---- breadth-first levels ----
-        uint64_t tests = 0;    // node-target opening tests of this group (work statistics)
+        uint32_t tests = 0;    // this lane's share of the node-target tests (work statistics)
         int cur = 0;
+
         if (threadIdx.x == 0) {
             rid(0, 0)[0] = 0u;
             rmask(0, 0)[0] = active;
@@ -450,36 +541,25 @@ __global__ __launch_bounds__(TW * WAVE) __attribute__((amdgpu_waves_per_eu(5, 8)
             uint32_t* nid = rid(cur ^ 1, wv);
             uint64_t* nmask = rmask(cur ^ 1, wv);
             int64_t nb = 0;          // entries of the next level written so far
-            uint32_t qid = 0;        // pending next-level entries (lane q = entry q)
-            uint64_t qmask = 0;
-            uint32_t nq = 0;
-            // write the pending next-level entries out once `need` more would not fit
-            auto reserve_front = [&](uint32_t need) __attribute__((always_inline)) {
-                if (nq + need > (uint32_t)WAVE) {
-                    if (nb + nq <= F.cap) {
-                        if ((uint32_t)lane < nq) {
-                            nid[nb + lane] = qid;
-                            nmask[nb + lane] = qmask;
-                        }
-                    } else {
-                        if (lane == 0) atomicOr(F.overflow, 1);
-                        overflow = true;
-                    }
-                    nb += nq;
-                    nq = 0;
+            auto push = [&](uint64_t b, uint32_t id, uint64_t m) __attribute__((always_inline)) {
+                if (!b || overflow) return;
+                const uint32_t k = (uint32_t)__popcll(b);
+                if (nb + k > F.cap) {
+                    if (lane == 0) atomicOr(F.overflow, 1);
+                    overflow = true;
+                    return;
                 }
-            };
-            auto push = [&](uint32_t nd, uint64_t m) __attribute__((always_inline)) {
-                qid = wl(nd, nq, qid);
-                qmask = wl(m, nq, qmask);
-                ++nq;
+                if ((b >> lane) & 1) {
+                    const int64_t at = nb + __popcll(b & below);
+                    nid[at] = id;
+                    nmask[at] = m;
+                }
+                nb += k;
             };
             for (int64_t b0 = e0; b0 < e1 && !overflow; b0 += WAVE) {
                 const uint32_t cnt = (uint32_t)(e1 - b0 < WAVE ? e1 - b0 : WAVE);
+                // ---- stage the block's nodes ----
                 uint32_t fid = 0, fmeta = 0;
-                uint64_t fmask = 0;
-                uint4 kA = make_uint4(0, 0, 0, 0), kB = make_uint4(0, 0, 0, 0);   // child table
-                FNode<DEC64> fn;
                 if ((uint32_t)lane < cnt) {
                     // entry e of the level lies in the region of the first wave whose
                     // cumulative count exceeds it
@@ -492,150 +572,159 @@ __global__ __launch_bounds__(TW * WAVE) __attribute__((amdgpu_waves_per_eu(5, 8)
                         r += past ? 1 : 0;
                     }
                     fid = rid(cur, r)[off];
-                    fmask = rmask(cur, r)[off];
+                    const uint64_t fmask = rmask(cur, r)[off];
+                    tests += (uint32_t)__popcll(fmask);
                     const uint32_t nd = fid;
-                    fmeta = F.meta[nd];
-                    const uint4* kp = (const uint4*)(F.kids + 8 * (int64_t)nd);
-                    kA = kp[0];
-                    kB = kp[1];
+                    NodeRec<DEC64> nr;
+                    uint4* kd = (uint4*)s_kids[wv][lane];
                     if constexpr (DEC64) {
-                        const Geo64 gg = a.ngeo64[nd];
-                        const Rec64 c = a.nrec64[nd];
-                        fn.cx = gg.cx;
-                        fn.cy = gg.cy;
-                        fn.cz = gg.cz;
-                        fn.l = gg.l;
-                        fn.X = c.x;
-                        fn.Y = c.y;
-                        fn.Z = c.z;
-                        fn.M = c.m;
-                        fn.hx = a.nhmax[nd];
-                        fn.hn = a.nhmin[nd];
+                        const WalkRec64* wr = F.w64 + nd;
+                        nr.cx = wr->cx;
+                        nr.cy = wr->cy;
+                        nr.cz = wr->cz;
+                        nr.l = wr->l;
+                        nr.X = wr->X;
+                        nr.Y = wr->Y;
+                        nr.Z = wr->Z;
+                        nr.M = wr->M;
+                        nr.hx = wr->hx;
+                        nr.hn = wr->hn;
+                        fmeta = wr->meta;
+                        kd[0] = ((const uint4*)wr->kids)[0];
+                        kd[1] = ((const uint4*)wr->kids)[1];
                     } else {
-                        const Rec32 c = a.nrec32[nd];
-                        const int lev = a.n_level[nd];
-                        const uint32_t half = 1u << (31 - lev);
-                        const uint64_t lint = 1ull << (32 - lev);
-                        fn.cX = a.n_corner[3 * nd + 0] + half;
-                        fn.cY = a.n_corner[3 * nd + 1] + half;
-                        fn.cZ = a.n_corner[3 * nd + 2] + half;
-                        fn.tin = (uint32_t)((3ull * lint - 1ull) / 5ull);
-                        fn.X = c.X;
-                        fn.Y = c.Y;
-                        fn.Z = c.Z;
-                        fn.M = c.m;
-                        fn.half = (float)half;
-                        fn.l2 = (float)lint * (float)lint;
-                        fn.hx = a.nhmax32[nd];
-                        fn.mixed = mixed && a.nhmin[nd] != a.nhmax[nd];
+                        const WalkRec32* wr = F.w32 + nd;
+                        const uint4 q0 = ((const uint4*)wr)[0], q1 = ((const uint4*)wr)[1], q2 = ((const uint4*)wr)[2];
+                        nr.cX = q0.x;
+                        nr.cY = q0.y;
+                        nr.cZ = q0.z;
+                        nr.tin = q0.w;
+                        nr.X = q1.x;
+                        nr.Y = q1.y;
+                        nr.Z = q1.z;
+                        nr.l2 = q1.w;
+                        nr.half = q2.x;
+                        nr.M = q2.y;
+                        nr.hx = q2.z;
+                        nr.mixed = MIXED ? q2.w : 0u;
+                        fmeta = wr->meta;
+                        kd[0] = ((const uint4*)wr->kids)[0];
+                        kd[1] = ((const uint4*)wr->kids)[1];
                     }
+                    nr.rlo = (uint32_t)fmask;
+                    nr.rhi = (uint32_t)(fmask >> 32);
+                    nr.id = nd;
+                    nr.meta = fmeta;
+                    rec[lane] = nr;
                 }
-                // decisions of all lanes for frontier entry j, straight-line; two entries are
-                // decided together so that their dependency chains interleave
+                wave_sync();
+
+                // ---- decisions: all lanes against node j ----
                 auto decide = [&](uint32_t j) __attribute__((always_inline)) -> Dec {
-                    const uint64_t reach = rl64(fmask, j);
-                    tests += (uint64_t)__popcll(reach);
+                    const NodeRec<DEC64> nr = rec[j];
+                    const uint64_t reach = ((uint64_t)nr.rhi << 32) | nr.rlo;
                     bool keep, open, near;
                     if constexpr (DEC64) {
-                        const double l = rld(fn.l, j);
-                        const double dcx = min_image(rld(fn.cx, j) - x64, a.box);
-                        const double dcy = min_image(rld(fn.cy, j) - y64, a.box);
-                        const double dcz = min_image(rld(fn.cz, j) - z64, a.box);
+                        const double l = nr.l;
+                        const double dcx = min_image(nr.cx - x64, a.box);
+                        const double dcy = min_image(nr.cy - y64, a.box);
+                        const double dcz = min_image(nr.cz - z64, a.box);
                         const double tx = fmax(fabs(dcx) - 0.5 * l, 0.0);
                         const double ty = fmax(fabs(dcy) - 0.5 * l, 0.0);
                         const double tz = fmax(fabs(dcz) - 0.5 * l, 0.0);
                         keep = !((tx * tx + ty * ty) + tz * tz > a.rc2 * (1.0 + 1e-6));
                         const bool inside = fabs(dcx) < 0.6 * l && fabs(dcy) < 0.6 * l && fabs(dcz) < 0.6 * l;
-                        const double dx = min_image(rld(fn.X, j) - x64, a.box);
-                        const double dy = min_image(rld(fn.Y, j) - y64, a.box);
-                        const double dz = min_image(rld(fn.Z, j) - z64, a.box);
+                        const double dx = min_image(nr.X - x64, a.box);
+                        const double dy = min_image(nr.Y - y64, a.box);
+                        const double dz = min_image(nr.Z - z64, a.box);
                         const double r2 = (dx * dx + dy * dy) + dz * dz;
-                        open = inside || l * l > a.theta2 * r2;
-                        if constexpr (REL) open = open || (a.G * rld(fn.M, j)) * (l * l) > (a.alpha * aold) * (r2 * r2);
-                        if constexpr (MIXED) {
-                            const double hx = rld(fn.hx, j);
-                            open = open || (rld(fn.hn, j) != hx && r2 < hx * hx);
-                        }
+                        open = inside | (l * l > a.theta2 * r2);
+                        if constexpr (REL) open = open || (a.G * nr.M) * (l * l) > (a.alpha * aold) * (r2 * r2);
+                        if constexpr (MIXED) open = open || (nr.hn != nr.hx && r2 < nr.hx * nr.hx);
                         near = r2 < a.rc2;
                     } else {
-                        const uint32_t bx = (uint32_t)abs((int32_t)(rl(fn.cX, j) - X));
-                        const uint32_t by = (uint32_t)abs((int32_t)(rl(fn.cY, j) - Y));
-                        const uint32_t bz = (uint32_t)abs((int32_t)(rl(fn.cZ, j) - Z));
+                        const uint32_t bx = (uint32_t)abs((int32_t)(nr.cX - X));
+                        const uint32_t by = (uint32_t)abs((int32_t)(nr.cY - Y));
+                        const uint32_t bz = (uint32_t)abs((int32_t)(nr.cZ - Z));
                         const uint32_t bm = max(bx, max(by, bz));
                         // prune (work only): the cube lies beyond r_cut along some axis
-                        keep = !((float)bm - rlf(fn.half, j) > a.rct);
-                        const bool inside = bm <= rl(fn.tin, j);
-                        const float dx = (float)(int32_t)(rl(fn.X, j) - X);
-                        const float dy = (float)(int32_t)(rl(fn.Y, j) - Y);
-                        const float dz = (float)(int32_t)(rl(fn.Z, j) - Z);
+                        keep = !((float)bm - __uint_as_float(nr.half) > a.rct);
+                        const bool inside = bm <= nr.tin;
+                        const float dx = (float)(int32_t)(nr.X - X);
+                        const float dy = (float)(int32_t)(nr.Y - Y);
+                        const float dz = (float)(int32_t)(nr.Z - Z);
                         const float r2 = r2_ticks(dx, dy, dz);
-                        const float l2 = rlf(fn.l2, j);
-                        open = inside || l2 > a.theta2f * r2;
+                        const float l2 = __uint_as_float(nr.l2);
+                        open = inside | (l2 > a.theta2f * r2);
                         if constexpr (REL) {
                             const double r2d = (double)r2;
-                            open = open || (a.G * (double)rlf(fn.M, j)) * (double)l2 > atau * (r2d * r2d);
+                            open = open || (a.G * (double)__uint_as_float(nr.M)) * (double)l2 > atau * (r2d * r2d);
                         }
                         if constexpr (MIXED) {
-                            const float hx = rlf(fn.hx, j);
-                            open = open || (rl(fn.mixed, j) && r2 < hx * hx);
+                            const float hx = __uint_as_float(nr.hx);
+                            open = open || (nr.mixed && r2 < hx * hx);
                         }
                         near = r2 < a.rc2t;
                     }
                     const bool live = ((reach >> lane) & 1ull) && keep;
                     return Dec{__ballot(live && open), __ballot(live && !open && near)};
                 };
-                auto expand = [&](uint32_t j, uint64_t om, uint64_t am) __attribute__((always_inline)) {
-                    if (am) append(rl(fid, j), am);
-                    if (!om) return;
-                    const uint32_t meta = rl(fmeta, j);
-                    if (meta == META_BUCKET) {
-                        const uint32_t s0 = rl(kA.x, j), sc = rl(kA.y, j);
-                        // keep room for the other expansion of the pair (up to 9 entries)
-                        for (uint32_t s = s0; s < s0 + sc; ++s) {
-                            reserve_list(10);
-                            append_particle(s, om);
-                        }
-                        return;
-                    }
-                    // branch-free: a particle child goes to the list (minus its own target),
-                    // a node child to the next level
-                    auto child = [&](uint32_t c) __attribute__((always_inline)) {
-                        const bool isp = (c & ITEM_PARTICLE) != 0;
-                        const uint64_t pm = isp ? om & ~__ballot(s_i == (int32_t)(c & ~ITEM_PARTICLE)) : 0ull;
-                        const bool to_list = pm != 0;
-                        lsrc = (to_list && (uint32_t)lane == nl) ? c : lsrc;
-                        lmask = (to_list && (uint32_t)lane == nl) ? pm : lmask;
-                        nl += to_list ? 1u : 0u;
-                        qid = (!isp && (uint32_t)lane == nq) ? c : qid;
-                        qmask = (!isp && (uint32_t)lane == nq) ? om : qmask;
-                        nq += isp ? 0u : 1u;
-                    };
-                    // a node has 2..8 children
-                    child(rl(kA.x, j));
-                    child(rl(kA.y, j));
-                    if (meta > 2) child(rl(kA.z, j));
-                    if (meta > 3) child(rl(kA.w, j));
-                    if (meta > 4) child(rl(kB.x, j));
-                    if (meta > 5) child(rl(kB.y, j));
-                    if (meta > 6) child(rl(kB.z, j));
-                    if (meta > 7) child(rl(kB.w, j));
-                };
-                uint32_t j = 0;
-                for (; j < cnt; j += 2) {
-                    // the second of a pair past the end decides with an empty reach mask
+                // lane j keeps the masks of node j; two decisions interleave
+                uint64_t my_om = 0, my_am = 0;
+                for (uint32_t j = 0; j < cnt; j += 2) {
                     const uint32_t j1 = j + 1 < cnt ? j + 1 : j;
                     const Dec d0 = decide(j);
-                    Dec d1 = decide(j1);
-                    if (j1 == j) d1 = Dec{0, 0};
-                    // each expansion adds at most 9 list entries (accept + 8 children) and 8 nodes
-                    reserve_list(18);
-                    reserve_front(16);
-                    expand(j, d0.om, d0.am);
-                    expand(j1, d1.om, d1.am);
+                    const Dec d1 = decide(j1);
+                    my_om = (uint32_t)lane == j ? d0.om : my_om;
+                    my_am = (uint32_t)lane == j ? d0.am : my_am;
+                    my_om = (uint32_t)lane == j1 && j1 != j ? d1.om : my_om;
+                    my_am = (uint32_t)lane == j1 && j1 != j ? d1.am : my_am;
                 }
+
+                // ---- accepted nodes: one list entry each, in block order ----
+                append(__ballot(my_am != 0), fid, my_am);
+
+                // ---- opened nodes: children, eight nodes by eight children per step ----
+                const bool opened = my_om != 0 && fmeta != META_BUCKET;
+                const uint64_t bo = __ballot(opened);
+                s_om[wv][lane] = my_om;
+                if (opened) s_open[wv][__popcll(bo & below)] = (uint32_t)lane;
+                wave_sync();
+                const uint32_t n_open = (uint32_t)__popcll(bo);
+                for (uint32_t q0 = 0; q0 < n_open && !overflow; q0 += 8) {
+                    const uint32_t q = q0 + ((uint32_t)lane >> 3);
+                    const uint32_t k = (uint32_t)lane & 7u;
+                    uint32_t ch = 0;
+                    uint64_t om = 0;
+                    bool has = false;
+                    if (q < n_open) {
+                        const uint32_t jn = s_open[wv][q];
+                        om = s_om[wv][jn];
+                        has = k < rec[jn].meta;
+                        ch = s_kids[wv][jn][k];
+                    }
+                    const bool isp = (ch & ITEM_PARTICLE) != 0;
+                    const uint64_t pm = has && isp ? om & ~own_bit(ch & ~ITEM_PARTICLE) : 0ull;
+                    append(__ballot(pm != 0), ch, pm);
+                    push(__ballot(has && !isp), ch, om);
+                }
+                // ---- opened buckets (identical keys): their particles, 64 at a time ----
+                uint64_t bb = __ballot(my_om != 0 && fmeta == META_BUCKET);
+                while (bb && !overflow) {
+                    const uint32_t jn = (uint32_t)__builtin_ctzll(bb);
+                    bb &= bb - 1;
+                    const uint64_t om = rl64(my_om, jn);
+                    const uint32_t s0 = __builtin_amdgcn_readfirstlane(s_kids[wv][jn][0]);
+                    const uint32_t sc = __builtin_amdgcn_readfirstlane(s_kids[wv][jn][1]);
+                    for (uint32_t p0 = 0; p0 < sc && !overflow; p0 += WAVE) {
+                        const uint32_t sidx = s0 + p0 + (uint32_t)lane;
+                        const bool in = p0 + (uint32_t)lane < sc;
+                        const uint64_t pm = in ? om & ~own_bit(sidx) : 0ull;
+                        append(__ballot(pm != 0), sidx | ITEM_PARTICLE, pm);
+                    }
+                }
+                wave_sync();
             }
-            // last partial block of the next level
-            if (!overflow) reserve_front((uint32_t)WAVE + 1);
             if (lane == 0) {
                 sh_cnt[cur ^ 1][wv] = overflow ? 0 : (int32_t)nb;
                 sh_ovf[cur ^ 1][wv] = overflow ? 1 : 0;
@@ -643,10 +732,13 @@ __global__ __launch_bounds__(TW * WAVE) __attribute__((amdgpu_waves_per_eu(5, 8)
             __syncthreads();
             cur ^= 1;
         }
-        if (nl && !overflow) emit();
+        if (nl && !overflow) {
+            finish_chunk(nl);
+            nl = 0;
+        }
         if (lane == 0 && cur_unit >= 0 && !overflow) L.unit_nch[cur_unit] = (int32_t)unit_nch;
+        tests_all += rl(wave_sum63_u32(tests), 63);
         if (lane == 0) {
-            atomicAdd((unsigned long long*)(L.counters + 4), (unsigned long long)tests);
             sh_first[wv] = first_unit;
             sh_last[wv] = cur_unit;
             sh_wovf[wv] = overflow ? 1 : 0;
@@ -668,6 +760,17 @@ __global__ __launch_bounds__(TW * WAVE) __attribute__((amdgpu_waves_per_eu(5, 8)
         }
         if (any_ovf) break;
         __syncthreads();
+    }
+    if (lane == 0) atomicAdd((unsigned long long*)(L.counters + 4), (unsigned long long)tests_all);
+    // units reserved and never used: empty units
+    if ((uint32_t)lane < u_end - u_next) {
+        const int64_t u = (int64_t)u_next + lane;
+        if (u < L.cap_units) {
+            L.unit_nch[u] = 0;
+            L.unit_group[u] = 0;
+            L.unit_chunk[u] = -1;
+            L.unit_next[u] = -1;
+        }
     }
 }
 
@@ -694,6 +797,7 @@ __global__ __launch_bounds__(WAVE) void k_eval(WalkArgs a, ListArgs L, char* __r
     using SrcT = typename std::conditional<F64, Src64, Src32>::type;
     const int lane = threadIdx.x;
     const int32_t u = blockIdx.x;
+    if (L.unit_nch[u] == 0) return;   // a unit reserved but not used (its partials are never read)
     const int64_t g = L.unit_group[u];
     const int64_t t = g * WAVE + lane;
     const bool valid = t < a.n_t;
@@ -918,7 +1022,8 @@ __device__ inline float row_sum15(float x)
 // records are staged in LDS, 32 bytes per entry; each quarter reads its own
 // entry (a broadcast within the row).  Slots past the end of a stream name
 // entry 64, whose mask is empty.  The adjoint's source terms are summed per row
-// with DPP and added with one atomic per (row, component).
+// with DPP, collected per entry in LDS, and added to the source with one FP64
+// atomic per (entry, component) after the chunk.
 struct SrcLds {
     uint32_t X, Y, Z, m;        // integer position, mass bits (mass scaled by 2^64)
     uint32_t h, inc, mlo, mhi;  // support h bits, count increment, mask of lanes 0-31 / 32-63
@@ -932,11 +1037,13 @@ __global__ __launch_bounds__(WAVE) void k_eval32(WalkArgs a, ListArgs L, char* _
     __shared__ SrcLds s_ent[WAVE + 1];
     __shared__ uint32_t s_src[WAVE];
     __shared__ uint8_t s_stream[4][WAVE];
+    __shared__ float s_acc[ADJ ? 4 : 1][WAVE];   // adjoint: source terms of each entry
     const int lane = threadIdx.x;
     const int quarter = lane >> 4;
     const uint32_t bit = 1u << (lane & 31);
     const bool hi_half = lane >= 32;
     const int32_t u = blockIdx.x;
+    if (L.unit_nch[u] == 0) return;   // a unit reserved but not used (its partials are never read)
     const int64_t g = L.unit_group[u];
     const int64_t t = g * WAVE + lane;
     const bool valid = t < a.n_t;
@@ -976,6 +1083,10 @@ __global__ __launch_bounds__(WAVE) void k_eval32(WalkArgs a, ListArgs L, char* _
                                  isp ? 1u : 0x10000u, (uint32_t)lmask, (uint32_t)(lmask >> 32)};
             s_src[lane] = lsrc;
         }
+        if constexpr (ADJ) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) s_acc[k][lane] = 0.0f;
+        }
         // the four quarter streams, each in entry order, padded with entry 64
         const uint64_t below = (1ull << lane) - 1ull;
         uint32_t nk[4];
@@ -988,7 +1099,7 @@ __global__ __launch_bounds__(WAVE) void k_eval32(WalkArgs a, ListArgs L, char* _
         }
         const uint32_t steps = max(max(nk[0], nk[1]), max(nk[2], nk[3]));
         const int32_t cnext = L.chunk_next[c];
-        __syncthreads();
+        wave_sync();
         for (uint32_t st = 0; st < steps; ++st) {
             const uint32_t e = s_stream[quarter][st];
             const SrcLds src = s_ent[e];
@@ -1038,23 +1149,33 @@ __global__ __launch_bounds__(WAVE) void k_eval32(WalkArgs a, ListArgs L, char* _
                 tbx -= (acc_t)px;
                 tby -= (acc_t)py;
                 tbz -= (acc_t)pz;
-                // source terms: per-row sums, one atomic per (row, component)
+                // source terms: per-row sums, collected per entry
                 const float sx = row_sum15(px);
                 const float sy = row_sum15(py);
                 const float sz = row_sum15(pz);
                 const float sm = row_sum15(K * wd);
                 if ((lane & 15) == 15 && e < (uint32_t)WAVE) {
-                    const uint32_t sid = s_src[e];
-                    double* dst = (sid & ITEM_PARTICLE) ? a.pbar + 4 * (int64_t)(sid & ~ITEM_PARTICLE)
-                                                        : a.nbar + 4 * (int64_t)sid;
-                    unsafeAtomicAdd(dst + 0, (double)sx);
-                    unsafeAtomicAdd(dst + 1, (double)sy);
-                    unsafeAtomicAdd(dst + 2, (double)sz);
-                    unsafeAtomicAdd(dst + 3, (double)sm);
+                    atomicAdd(&s_acc[0][e], sx);
+                    atomicAdd(&s_acc[1][e], sy);
+                    atomicAdd(&s_acc[2][e], sz);
+                    atomicAdd(&s_acc[3][e], sm);
                 }
             }
         }
-        __syncthreads();
+        wave_sync();
+        if constexpr (ADJ) {
+            if (has) {
+                const uint32_t sid = s_src[lane];
+                double* dst = (sid & ITEM_PARTICLE) ? a.pbar + 4 * (int64_t)(sid & ~ITEM_PARTICLE)
+                                                    : a.nbar + 4 * (int64_t)sid;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const float v = s_acc[k][lane];
+                    if (v != 0.0f) unsafeAtomicAdd(dst + k, (double)v);
+                }
+            }
+            wave_sync();
+        }
         c = cnext;
     }
     acc_t* pa = (acc_t*)(partials + (int64_t)u * PARTIAL_BYTES);
@@ -1308,7 +1429,10 @@ int traverse(sr_tree* t, const sr_params* p, int64_t n_t, const int32_t* active,
     SR_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     const int64_t wgs = groups < SR_TRAV_WG_PER_CU * (int64_t)cus ? groups : SR_TRAV_WG_PER_CU * (int64_t)cus;
     for (int attempt = 0; attempt < 8; ++attempt) {
-        int rc = sr_list_reserve(t, groups, (want + 63) / 64, (int64_t)UCH);
+        // every wave of a group may start a unit chain; each wave may leave a
+        // reserved batch of chunks and units unused
+        const int64_t chunks = (want + 63) / 64 + TW * wgs * (TRAV_CHUNK_BATCH + 2);
+        int rc = sr_list_reserve(t, groups, chunks, TW * groups + chunks / UCH + TW * wgs * TRAV_UNIT_BATCH + 1);
         if (rc) return rc;
         if ((rc = sr_front_reserve(t, wgs * TW, fcap))) return rc;
         hipLaunchKernelGGL(k_fill_i32w, g256(groups), dim3(256), 0, st, t->group_head, groups, -1);
@@ -1320,8 +1444,9 @@ int traverse(sr_tree* t, const sr_params* p, int64_t n_t, const int32_t* active,
         F.cap = t->cap_front;
         F.next_group = t->list_counters + 3;
         F.overflow = t->list_counters + 2;
-        F.kids = t->n_kids;
-        F.meta = t->n_meta;
+        F.w32 = t->wrec32;
+        F.w64 = t->wrec64;
+        F.contig = active == nullptr;
         F.groups = groups;
         sr_timing_mark(SR_T_TRAVERSE, true, st);
         const dim3 gw((unsigned)wgs), bw(TW * WAVE);
@@ -1445,7 +1570,7 @@ int sr_walk_forward(sr_tree* t, const sr_params* p, int64_t n_t, const int32_t* 
     if (t->n_nodes == 0) {
         // a single particle: no sources, every group list is empty
         const int64_t groups = (n_t + WAVE - 1) / WAVE;
-        int rc = sr_list_reserve(t, groups, 1, (int64_t)UCH);
+        int rc = sr_list_reserve(t, groups, 1, 1);
         if (rc) return rc;
         t->n_units = 0;
         t->lkey.valid = false;
