@@ -116,6 +116,65 @@ __global__ void k_scan_sums(const uint32_t* __restrict__ in, int64_t n, uint32_t
     if (threadIdx.x == 0) sums[blockIdx.x] = tot;
 }
 
+// Exclusive scan of n <= 64 * 1024 values by one workgroup of 1024 threads, total
+// at out[n]; in place is allowed.  Thread t takes a contiguous run of `per`
+// values (a multiple of 4), loaded as 16-byte vectors in one unrolled burst.
+constexpr int SCAN1_TPB = 1024;
+constexpr int SCAN1_MAXPER = 64;
+__global__ __launch_bounds__(SCAN1_TPB) void k_scan_one(const uint32_t* in, uint32_t* out, int64_t n)
+{
+    __shared__ uint32_t s_w[SCAN1_TPB / 64];
+    const int64_t per = ((n + SCAN1_TPB - 1) / SCAN1_TPB + 3) & ~(int64_t)3;
+    const int64_t b = threadIdx.x * per;
+    uint32_t v[SCAN1_MAXPER];
+    uint32_t acc = 0;
+#pragma unroll
+    for (int q = 0; q < SCAN1_MAXPER / 4; ++q) {
+        const int64_t i = b + 4 * q;
+        uint4 x = make_uint4(0, 0, 0, 0);
+        if (4 * q < per) {
+            if (i + 3 < n) {
+                x = *(const uint4*)(in + i);
+            } else {
+                x.x = i < n ? in[i] : 0u;
+                x.y = i + 1 < n ? in[i + 1] : 0u;
+                x.z = i + 2 < n ? in[i + 2] : 0u;
+            }
+        }
+        v[4 * q] = x.x;
+        v[4 * q + 1] = x.y;
+        v[4 * q + 2] = x.z;
+        v[4 * q + 3] = x.w;
+        acc += (x.x + x.y) + (x.z + x.w);
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint32_t inc = wave_inclusive_scan(acc);
+    if (lane == 63) s_w[w] = inc;
+    __syncthreads();
+    uint32_t off = inc - acc;
+    for (int k = 0; k < w; ++k) off += s_w[k];
+#pragma unroll
+    for (int q = 0; q < SCAN1_MAXPER / 4; ++q) {
+        const int64_t i = b + 4 * q;
+        uint4 y;
+        y.x = off;
+        y.y = y.x + v[4 * q];
+        y.z = y.y + v[4 * q + 1];
+        y.w = y.z + v[4 * q + 2];
+        off = y.w + v[4 * q + 3];
+        if (4 * q < per) {
+            if (i + 3 < n) {
+                *(uint4*)(out + i) = y;
+            } else {
+                if (i < n) out[i] = y.x;
+                if (i + 1 < n) out[i + 1] = y.y;
+                if (i + 2 < n) out[i + 2] = y.z;
+            }
+        }
+    }
+    if (threadIdx.x == SCAN1_TPB - 1) out[n] = off;
+}
+
 // One block scans all tile sums in place (exclusive).
 __global__ void k_scan_top(uint32_t* __restrict__ sums, int64_t nb)
 {
@@ -449,51 +508,52 @@ __global__ void k_depth_scatter(int64_t m, const int32_t* __restrict__ n_depth,
 // Fold the children of every node of one depth, left to right in digit order:
 // M <- c1, M <- M + c2, ...; S likewise with a particle contributing m x;
 // COM = S / M.  Also the FP32-path node record and the FP64 decision geometry.
+// Child table of every node: its children in digit order, at most 8 (node
+// index, or sorted particle index | ITEM_PARTICLE); a level-30 bucket keeps its
+// particle range (first, count) with META_BUCKET.
+__global__ void k_child_table(int64_t m, const Item* __restrict__ items, const int32_t* __restrict__ n_first,
+                              const int32_t* __restrict__ n_level, const int32_t* __restrict__ n_count,
+                              uint32_t* __restrict__ kids, uint32_t* __restrict__ meta)
+{
+    const int64_t nd = blockIdx.x * (int64_t)TPB + threadIdx.x;
+    if (nd >= m) return;
+    if (n_level[nd] == 30) {
+        kids[8 * nd + 0] = (uint32_t)n_first[nd];
+        kids[8 * nd + 1] = (uint32_t)n_count[nd];
+        meta[nd] = META_BUCKET;
+        return;
+    }
+    const uint32_t it = (uint32_t)(n_first[nd] + nd);
+    const uint32_t end = items[it].next;
+    uint32_t nk = 0;
+    for (uint32_t j = it + 1; j < end;) {
+        const Item c = items[j];
+        kids[8 * nd + nk] = c.ref;
+        ++nk;
+        j = (c.ref & ITEM_PARTICLE) ? j + 1 : c.next;
+    }
+    meta[nd] = nk;
+}
+
+// Moments of the nodes of one depth (children done): M, S = sum m x, COM = S / M,
+// folded left to right over the children in digit order without FMA, the
+// support range, the cube geometry and the FP32 record.  All children's data
+// are loaded before the fold.
 __global__ void k_moments(const int32_t* __restrict__ order, int64_t count, double box,
-                          const Item* __restrict__ items, const int32_t* __restrict__ n_first,
-                          const int32_t* __restrict__ n_level, const uint32_t* __restrict__ n_corner,
-                          const Rec64* __restrict__ r64, const double* __restrict__ h64,
-                          Rec64* __restrict__ nrec64, double* __restrict__ nS, Geo64* __restrict__ geo,
-                          double* __restrict__ nhmax, double* __restrict__ nhmin,
-                          Rec32* __restrict__ nrec32, float* __restrict__ nhmax32, uint32_t* __restrict__ kids,
-                          uint32_t* __restrict__ meta, const int32_t* __restrict__ n_count)
+                          const int32_t* __restrict__ n_first, const int32_t* __restrict__ n_level,
+                          const uint32_t* __restrict__ n_corner, const Rec64* __restrict__ r64,
+                          const double* __restrict__ h64, Rec64* __restrict__ nrec64, double* __restrict__ nS,
+                          Geo64* __restrict__ geo, double* __restrict__ nhmax, double* __restrict__ nhmin,
+                          Rec32* __restrict__ nrec32, float* __restrict__ nhmax32,
+                          const uint32_t* __restrict__ kids, const uint32_t* __restrict__ meta,
+                          const int32_t* __restrict__ n_count)
 {
     int64_t t = blockIdx.x * (int64_t)TPB + threadIdx.x;
     if (t >= count) return;
-    int32_t nd = order[t];
-    uint32_t it = (uint32_t)(n_first[nd] + nd);
-    uint32_t end = items[it].next;
+    const int32_t nd = order[t];
+    const uint32_t mt = meta[nd];
     double M = 0.0, S0 = 0.0, S1 = 0.0, S2 = 0.0, hx = 0.0, hn = 0.0;
-    bool first = true;
-    // child table: up to 8 children in digit order; a bucket (level 30) keeps its particle range
-    const bool bucket = n_level[nd] == 30;
-    uint32_t nk = 0;
-    if (bucket) {
-        kids[8 * (int64_t)nd + 0] = (uint32_t)n_first[nd];
-        kids[8 * (int64_t)nd + 1] = (uint32_t)n_count[nd];
-    }
-    for (uint32_t j = it + 1; j < end;) {
-        Item c = items[j];
-        if (!bucket) kids[8 * (int64_t)nd + nk] = c.ref;
-        ++nk;
-        double cm, c0, c1, c2, cx, cn;
-        if (c.ref & ITEM_PARTICLE) {
-            Rec64 p = r64[c.ref & ~ITEM_PARTICLE];
-            cm = p.m;
-            c0 = p.m * p.x;
-            c1 = p.m * p.y;
-            c2 = p.m * p.z;
-            cx = cn = h64[c.ref & ~ITEM_PARTICLE];
-            j += 1;
-        } else {
-            cm = nrec64[c.ref].m;
-            c0 = nS[3 * c.ref + 0];
-            c1 = nS[3 * c.ref + 1];
-            c2 = nS[3 * c.ref + 2];
-            cx = nhmax[c.ref];
-            cn = nhmin[c.ref];
-            j = c.next;
-        }
+    auto fold = [&](bool first, double cm, double c0, double c1, double c2, double cx, double cn) {
         if (first) {
             M = cm;
             S0 = c0;
@@ -501,7 +561,6 @@ __global__ void k_moments(const int32_t* __restrict__ order, int64_t count, doub
             S2 = c2;
             hx = cx;
             hn = cn;
-            first = false;
         } else {
             M = M + cm;
             S0 = S0 + c0;
@@ -510,6 +569,45 @@ __global__ void k_moments(const int32_t* __restrict__ order, int64_t count, doub
             hx = cx > hx ? cx : hx;
             hn = cn < hn ? cn : hn;
         }
+    };
+    if (mt == META_BUCKET) {
+        // identical keys: the particles first .. first + count - 1
+        const uint32_t f = (uint32_t)n_first[nd], c = (uint32_t)n_count[nd];
+        for (uint32_t k = 0; k < c; ++k) {
+            const Rec64 p = r64[f + k];
+            const double h = h64[f + k];
+            fold(k == 0, p.m, p.m * p.x, p.m * p.y, p.m * p.z, h, h);
+        }
+    } else {
+        const uint4 ka = ((const uint4*)(kids + 8 * (int64_t)nd))[0];
+        const uint4 kb = ((const uint4*)(kids + 8 * (int64_t)nd))[1];
+        const uint32_t kr[8] = {ka.x, ka.y, ka.z, ka.w, kb.x, kb.y, kb.z, kb.w};
+        double cm[8], c0[8], c1[8], c2[8], cx[8], cn[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            cm[k] = c0[k] = c1[k] = c2[k] = cx[k] = cn[k] = 0.0;
+            if ((uint32_t)k < mt) {
+                const uint32_t r = kr[k];
+                if (r & ITEM_PARTICLE) {
+                    const Rec64 p = r64[r & ~ITEM_PARTICLE];
+                    cm[k] = p.m;
+                    c0[k] = p.m * p.x;
+                    c1[k] = p.m * p.y;
+                    c2[k] = p.m * p.z;
+                    cx[k] = cn[k] = h64[r & ~ITEM_PARTICLE];
+                } else {
+                    cm[k] = nrec64[r].m;
+                    c0[k] = nS[3 * r + 0];
+                    c1[k] = nS[3 * r + 1];
+                    c2[k] = nS[3 * r + 2];
+                    cx[k] = nhmax[r];
+                    cn[k] = nhmin[r];
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if ((uint32_t)k < mt) fold(k == 0, cm[k], c0[k], c1[k], c2[k], cx[k], cn[k]);
     }
     double com[3] = {S0 / M, S1 / M, S2 / M};
     nrec64[nd] = Rec64{com[0], com[1], com[2], M};
@@ -528,7 +626,6 @@ __global__ void k_moments(const int32_t* __restrict__ order, int64_t count, doub
     for (int k = 0; k < 3; ++k) q[k] = (uint32_t)(uint64_t)rint(com[k] / box * TWO32);
     nrec32[nd] = Rec32{q[0], q[1], q[2], (float)M};
     nhmax32[nd] = (float)(hx / box * TWO32);
-    meta[nd] = bucket ? META_BUCKET : nk;
 }
 
 // The walk's per-node records (one 128-byte line each), from the node arrays.
@@ -603,6 +700,11 @@ inline dim3 grid_for(int64_t n) { return dim3((unsigned)cdiv(n > 0 ? n : 1, TPB)
 
 int sr_scan_exclusive(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* tmp, hipStream_t st)
 {
+    if (n <= (int64_t)8 * SCAN1_TPB) {
+        hipLaunchKernelGGL(k_scan_one, dim3(1), dim3(SCAN1_TPB), 0, st, in, out, n);
+        SR_HIP(hipGetLastError());
+        return SR_OK;
+    }
     int64_t nb = cdiv(n > 0 ? n : 1, SCAN_TILE);
     hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)nb), dim3(TPB), 0, st, in, n, tmp);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(TPB), 0, st, tmp, nb);
@@ -687,10 +789,12 @@ int sr_build_device(sr_tree* t, const double* pos, const double* mass, const dou
                        (int64_t)SR_MAX_DEPTH, 0);
     hipLaunchKernelGGL(k_depth_scatter, grid_for(m), dim3(TPB), 0, st, m, t->n_depth, t->status, t->depth_cursor,
                        t->depth_order);
+    hipLaunchKernelGGL(k_child_table, grid_for(m), dim3(TPB), 0, st, m, t->items, t->n_first, t->n_level,
+                       t->n_count, t->n_kids, t->n_meta);
     for (int d = t->max_depth; d >= 0; --d) {
         int64_t cnt = t->depth_hist[d];
         if (!cnt) continue;
-        hipLaunchKernelGGL(k_moments, grid_for(cnt), dim3(TPB), 0, st, t->depth_order + offs[d], cnt, box, t->items,
+        hipLaunchKernelGGL(k_moments, grid_for(cnt), dim3(TPB), 0, st, t->depth_order + offs[d], cnt, box,
                            t->n_first, t->n_level, t->n_corner, t->prec64, t->ph64, t->nrec64, t->nS, t->ngeo64,
                            t->nhmax, t->nhmin, t->nrec32, t->nhmax32, t->n_kids, t->n_meta, t->n_count);
     }

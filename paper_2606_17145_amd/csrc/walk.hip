@@ -20,7 +20,6 @@
 namespace {
 
 constexpr int WAVE = 64;
-constexpr int WIN = 64;                 // items held by the register window (one per lane)
 constexpr double TWO32 = 4294967296.0;
 constexpr double TWO_OVER_SQRTPI = 1.12837916709551257390;
 constexpr float LOG2E_F = 1.44269504088896340736f;
@@ -28,7 +27,6 @@ constexpr float TWO_OVER_SQRTPI_F = 1.12837916709551257390f;
 constexpr float TWO64_F = 18446744073709551616.0f;
 
 enum { PR64 = 0, PR32 = 1, PR32A = 2 };
-enum { D_PRUNE = 0, D_ACCEPT = 1, D_ACCEPT_FAR = 2, D_OPEN = 3 };
 
 struct WalkArgs {
     int64_t n_t;
@@ -67,14 +65,6 @@ struct WalkArgs {
     double* nbar;
 };
 
-__device__ inline uint64_t uniform64(uint64_t v)
-{
-    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-    uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-    return ((uint64_t)hi << 32) | lo;
-}
-
-__device__ inline uint32_t uniform32(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
 __device__ inline double min_image(double d, double L)
 {
@@ -204,14 +194,11 @@ __device__ inline T wave_sum63(T x)
 }
 
 // ----------------------------------------------------------------------------------
-// register-resident wave state
+// cross-lane helpers
 // ----------------------------------------------------------------------------------
 //
-// Everything a wave keeps lives in VGPRs, one slot per lane, and is read back
-// as a scalar with v_readlane at a uniform index (or written with a lane
-// select): the window of the item sequence (lane l = item w0 + l, with its
-// node's decision data), the open masks of the current path (lane d = depth
-// d), and the pending list entries (lane e = entry e).
+// v_readlane at a uniform lane index (a VGPR value as a scalar), and a lane
+// select that writes one lane of a VGPR.
 
 __device__ inline uint32_t rl(uint32_t v, uint32_t l) { return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)l); }
 __device__ inline float rlf(float v, uint32_t l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), (int)l)); }
@@ -1003,14 +990,14 @@ __global__ __launch_bounds__(WAVE) void k_eval(WalkArgs a, ListArgs L, char* __r
     }
 }
 
-// Sum over each row of 16 lanes (DPP row shifts); lane 16k + 15 holds row k's total.
+// Sum over each row of 16 lanes by a rotation butterfly (DPP row_ror 1, 2, 4,
+// 8): every lane of row k ends with row k's total.
 __device__ inline float row_sum15(float x)
 {
-    float v = x + dpp_f32<0x111, 0xf, 0xf>(x);
-    v = v + dpp_f32<0x112, 0xf, 0xf>(x);
-    v = v + dpp_f32<0x113, 0xf, 0xf>(x);
-    v = v + dpp_f32<0x114, 0xf, 0xe>(v);
-    v = v + dpp_f32<0x118, 0xf, 0xc>(v);
+    float v = x + dpp_f32<0x121, 0xf, 0xf>(x);
+    v = v + dpp_f32<0x122, 0xf, 0xf>(v);
+    v = v + dpp_f32<0x124, 0xf, 0xf>(v);
+    v = v + dpp_f32<0x128, 0xf, 0xf>(v);
     return v;
 }
 
