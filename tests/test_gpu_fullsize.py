@@ -5,6 +5,8 @@ computes one by one.
   active subset walked with the relative criterion (alpha = 0.005, geometric
   guard 0.7); |a_old| is the oracle's FP64 Barnes-Hut (theta = 0.5) walk of the
   active particles.
+* zoom_6m: tree, sampled FP64/FP32 forces and the full 8-step FP32 rollout
+  gradient (consistency with the FP64 rollout gradient).
 * adjoint on clustered_262k: the FP64 adjoint against the oracle's per-particle
   gradient on 4,096 random particles, the oracle's central differences of the
   frozen-decision loss against its analytic gradient on the same particles,
@@ -114,3 +116,55 @@ def test_direct_sum_gradient_4096(sg, oracle):
     assert np.allclose(acc.cpu().numpy(), acc_ref, rtol=1e-11, atol=1e-11 * np.abs(acc_ref).max())
     assert np.allclose(dx.cpu().numpy(), gx, rtol=1e-9, atol=1e-10 * np.abs(gx).max())
     assert np.allclose(dm.cpu().numpy(), gm, rtol=1e-9, atol=1e-10 * np.abs(gm).max())
+
+
+def test_zoom_6m_step_and_rollout(sg, oracle):
+    """zoom_6m (4,194,304 + 128^3 particles, two masses, two softenings): the tree
+    against the oracle's (node count, permutation, per-node particle counts), the
+    FP64 and FP32 forces of 2,048 sampled targets against the oracle's walk, and
+    the full 8-step FP32 rollout gradient of L = sum w . x_8; its agreement with
+    the FP64 rollout gradient is a consistency property (the oracle's rollout is
+    checked at small N in test_gpu_rollout)."""
+    from paper_2606_17145_amd import rollout as RL
+    w = WL.zoom_6m()
+    print(f"zoom_6m: N={w.n}", flush=True)
+    pos, mass, eps = _t(w.pos), _t(w.mass), _t(w.eps)
+    t = sg.tree_build(pos, mass, eps=eps)
+    ref = oracle.Tree(w.pos, w.mass, w.eps)
+    ex = t.export()
+    assert t.node_count() == ref.n_nodes
+    assert np.array_equal(ex["perm"].cpu().numpy(), ref.perm)
+    nd = ref.nodes()
+    assert np.array_equal(ex["count"].cpu().numpy(), nd["count"])
+    assert np.array_equal(ex["comX"].cpu().numpy().view(np.uint32), nd["comX"])
+    del nd
+    sample = np.sort(np.random.default_rng(61).choice(w.n, 2048, replace=False))
+    p = w.params("fp64")
+    acc_ref, cnt_ref = oracle.walk(ref, p, targets=sample)
+    del ref
+    acc, cnt = sg.shortrange_accel(t, p)
+    assert np.array_equal(cnt.cpu().numpy()[sample], cnt_ref)
+    e = rel_err(acc.cpu().numpy()[sample], acc_ref)
+    print(f"   fp64 max rel err {e.max():.3e}; interactions/target {cnt_ref.sum() / sample.size:.0f}", flush=True)
+    assert e.max() <= 1e-12
+    acc32, _ = sg.shortrange_accel(t, w.params("fp32"))
+    e32 = rel_err(acc32.double().cpu().numpy()[sample], acc_ref)
+    print(f"   fp32 median {np.median(e32):.3e} p99.9 {np.quantile(e32, 0.999):.3e}", flush=True)
+    assert np.median(e32) <= 1e-5 and np.quantile(e32, 0.999) <= 1e-4
+    del t
+    vel = _t(w.extra["vel"])
+    wx = _t(w.extra["loss_w"])
+    ns, dt = w.extra["n_steps"], w.extra["dt"]
+    gx32, gv32, x32, _ = RL.kdk_rollout_grad(pos, vel, mass, eps, w.params("fp32"), ns, dt, wx)
+    gx64, gv64, x64, _ = RL.kdk_rollout_grad(pos, vel, mass, eps, w.params("fp64"), ns, dt, wx)
+    for name, a32, a64 in (("dL/dx0", gx32, gx64), ("dL/dv0", gv32, gv64)):
+        a32, a64 = a32.cpu().numpy(), a64.cpu().numpy()
+        assert np.all(np.isfinite(a32))
+        r = np.linalg.norm(a32 - a64, axis=1) / np.maximum(np.linalg.norm(a64, axis=1),
+                                                            1e-6 * np.median(np.linalg.norm(a64, axis=1)))
+        print(f"   rollout {name}: fp32 vs fp64 median {np.median(r):.2e} p99.9 {np.quantile(r, 0.999):.2e}",
+              flush=True)
+        assert np.median(r) <= 1e-4
+    dx = np.abs(x32.cpu().numpy() - x64.cpu().numpy()).max()
+    print(f"   final positions fp32 vs fp64: max |dx| {dx:.2e}", flush=True)
+    assert dx <= 1e-6
