@@ -12,8 +12,8 @@
 namespace {
 
 constexpr int TPB = 256;                 // threads per block for elementwise kernels
-constexpr int RS_ITEMS = 8;              // keys per thread in the radix sort
-constexpr int RS_TILE = TPB * RS_ITEMS;  // keys per block
+// Radix-sort tiles hold TPB * ITEMS keys; ITEMS is chosen by N (2, 4 or 8) so
+// that a pass has several hundred blocks.
 constexpr int SCAN_ITEMS = 8;
 constexpr int SCAN_TILE = TPB * SCAN_ITEMS;
 constexpr double TWO32 = 4294967296.0;
@@ -225,13 +225,14 @@ __device__ inline uint32_t rs_digit(uint64_t hi, uint64_t lo, int pass)
     return pass < 6 ? (uint32_t)(lo >> (8 * pass)) & 0xffu : (uint32_t)(hi >> (8 * (pass - 6))) & 0xffu;
 }
 
+template <int RS_ITEMS>
 __global__ void k_rs_hist(const uint64_t* __restrict__ hi, const uint64_t* __restrict__ lo, int64_t n,
                           int pass, uint32_t* __restrict__ hist, int64_t nb)
 {
     __shared__ uint32_t h[256];
     h[threadIdx.x] = 0;
     __syncthreads();
-    int64_t base = blockIdx.x * (int64_t)RS_TILE;
+    int64_t base = blockIdx.x * (int64_t)(TPB * RS_ITEMS);
     for (int r = 0; r < RS_ITEMS; ++r) {
         int64_t i = base + r * TPB + threadIdx.x;
         if (i < n) atomicAdd(&h[rs_digit(hi[i], lo[i], pass)], 1u);
@@ -242,6 +243,7 @@ __global__ void k_rs_hist(const uint64_t* __restrict__ hi, const uint64_t* __res
 
 // Stable scatter: within a tile, keys keep their order (rounds in order, waves
 // in order, lanes in order); tiles take their offsets from the digit-major scan.
+template <int RS_ITEMS>
 __global__ void k_rs_scatter(const uint64_t* __restrict__ hi, const uint64_t* __restrict__ lo,
                              const uint32_t* __restrict__ idx, uint64_t* __restrict__ ohi,
                              uint64_t* __restrict__ olo, uint32_t* __restrict__ oidx, int64_t n,
@@ -252,7 +254,7 @@ __global__ void k_rs_scatter(const uint64_t* __restrict__ hi, const uint64_t* __
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     s_off[threadIdx.x] = offs[threadIdx.x * nb + blockIdx.x];
     const uint64_t lt = (1ull << lane) - 1ull;
-    int64_t base = blockIdx.x * (int64_t)RS_TILE;
+    int64_t base = blockIdx.x * (int64_t)(TPB * RS_ITEMS);
     for (int r = 0; r < RS_ITEMS; ++r) {
         int64_t i = base + r * TPB + threadIdx.x;
         bool valid = i < n;
@@ -546,12 +548,15 @@ __global__ void k_moments(const int32_t* __restrict__ order, int64_t count, doub
                           Geo64* __restrict__ geo, double* __restrict__ nhmax, double* __restrict__ nhmin,
                           Rec32* __restrict__ nrec32, float* __restrict__ nhmax32,
                           const uint32_t* __restrict__ kids, const uint32_t* __restrict__ meta,
-                          const int32_t* __restrict__ n_count)
+                          const int32_t* __restrict__ n_count, WalkRec32* __restrict__ w32,
+                          WalkRec64* __restrict__ w64)
 {
     int64_t t = blockIdx.x * (int64_t)TPB + threadIdx.x;
     if (t >= count) return;
     const int32_t nd = order[t];
     const uint32_t mt = meta[nd];
+    const uint4 ka = ((const uint4*)(kids + 8 * (int64_t)nd))[0];
+    const uint4 kb = ((const uint4*)(kids + 8 * (int64_t)nd))[1];
     double M = 0.0, S0 = 0.0, S1 = 0.0, S2 = 0.0, hx = 0.0, hn = 0.0;
     auto fold = [&](bool first, double cm, double c0, double c1, double c2, double cx, double cn) {
         if (first) {
@@ -579,8 +584,6 @@ __global__ void k_moments(const int32_t* __restrict__ order, int64_t count, doub
             fold(k == 0, p.m, p.m * p.x, p.m * p.y, p.m * p.z, h, h);
         }
     } else {
-        const uint4 ka = ((const uint4*)(kids + 8 * (int64_t)nd))[0];
-        const uint4 kb = ((const uint4*)(kids + 8 * (int64_t)nd))[1];
         const uint32_t kr[8] = {ka.x, ka.y, ka.z, ka.w, kb.x, kb.y, kb.z, kb.w};
         double cm[8], c0[8], c1[8], c2[8], cx[8], cn[8];
 #pragma unroll
@@ -619,66 +622,54 @@ __global__ void k_moments(const int32_t* __restrict__ order, int64_t count, doub
     int lev = n_level[nd];
     double l = ldexp(box, -lev);
     double half = ldexp(1.0, -lev - 1);
-    geo[nd] = Geo64{box * (ldexp((double)n_corner[3 * nd + 0], -32) + half),
-                    box * (ldexp((double)n_corner[3 * nd + 1], -32) + half),
-                    box * (ldexp((double)n_corner[3 * nd + 2], -32) + half), l};
+    const Geo64 gg{box * (ldexp((double)n_corner[3 * nd + 0], -32) + half),
+                   box * (ldexp((double)n_corner[3 * nd + 1], -32) + half),
+                   box * (ldexp((double)n_corner[3 * nd + 2], -32) + half), l};
+    geo[nd] = gg;
     uint32_t q[3];
     for (int k = 0; k < 3; ++k) q[k] = (uint32_t)(uint64_t)rint(com[k] / box * TWO32);
-    nrec32[nd] = Rec32{q[0], q[1], q[2], (float)M};
-    nhmax32[nd] = (float)(hx / box * TWO32);
-}
-
-// The walk's per-node records (one 128-byte line each), from the node arrays.
-__global__ void k_walk_records(int64_t m, const int32_t* __restrict__ n_level,
-                               const uint32_t* __restrict__ n_corner, const Rec32* __restrict__ nrec32,
-                               const float* __restrict__ nhmax32, const Rec64* __restrict__ nrec64,
-                               const Geo64* __restrict__ geo, const double* __restrict__ nhmax,
-                               const double* __restrict__ nhmin, const uint32_t* __restrict__ kids,
-                               const uint32_t* __restrict__ meta, WalkRec32* __restrict__ w32,
-                               WalkRec64* __restrict__ w64)
-{
-    const int64_t nd = blockIdx.x * (int64_t)TPB + threadIdx.x;
-    if (nd >= m) return;
-    const int lev = n_level[nd];
-    const uint32_t half = 1u << (31 - lev);
+    const float M32 = (float)M, hx32 = (float)(hx / box * TWO32);
+    nrec32[nd] = Rec32{q[0], q[1], q[2], M32};
+    nhmax32[nd] = hx32;
+    // the walk's record of this node (one 128-byte line per precision)
+    const uint32_t halfi = 1u << (31 - lev);
     const uint64_t lint = 1ull << (32 - lev);
-    const Rec32 c32 = nrec32[nd];
-    const Rec64 c64 = nrec64[nd];
-    const Geo64 g = geo[nd];
-    const double hx = nhmax[nd], hn = nhmin[nd];
-    const uint32_t mt = meta[nd];
     WalkRec32 a{};
-    a.cX = n_corner[3 * nd + 0] + half;
-    a.cY = n_corner[3 * nd + 1] + half;
-    a.cZ = n_corner[3 * nd + 2] + half;
+    a.cX = n_corner[3 * nd + 0] + halfi;
+    a.cY = n_corner[3 * nd + 1] + halfi;
+    a.cZ = n_corner[3 * nd + 2] + halfi;
     a.tin = (uint32_t)((3ull * lint - 1ull) / 5ull);   // largest integer below 0.6 l
-    a.X = c32.X;
-    a.Y = c32.Y;
-    a.Z = c32.Z;
+    a.X = q[0];
+    a.Y = q[1];
+    a.Z = q[2];
     a.l2 = __float_as_uint((float)lint * (float)lint);
-    a.half = __float_as_uint((float)half);
-    a.M = __float_as_uint(c32.m);
-    a.hx = __float_as_uint(nhmax32[nd]);
+    a.half = __float_as_uint((float)halfi);
+    a.M = __float_as_uint(M32);
+    a.hx = __float_as_uint(hx32);
     a.mixed = hn != hx ? 1u : 0u;
     a.meta = mt;
+    a.kids[0] = ka.x;
+    a.kids[1] = ka.y;
+    a.kids[2] = ka.z;
+    a.kids[3] = ka.w;
+    a.kids[4] = kb.x;
+    a.kids[5] = kb.y;
+    a.kids[6] = kb.z;
+    a.kids[7] = kb.w;
+    w32[nd] = a;
     WalkRec64 b{};
-    b.cx = g.cx;
-    b.cy = g.cy;
-    b.cz = g.cz;
-    b.l = g.l;
-    b.X = c64.x;
-    b.Y = c64.y;
-    b.Z = c64.z;
-    b.M = c64.m;
+    b.cx = gg.cx;
+    b.cy = gg.cy;
+    b.cz = gg.cz;
+    b.l = l;
+    b.X = com[0];
+    b.Y = com[1];
+    b.Z = com[2];
+    b.M = M;
     b.hx = hx;
     b.hn = hn;
     b.meta = mt;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        a.kids[k] = kids[8 * nd + k];
-        b.kids[k] = a.kids[k];
-    }
-    w32[nd] = a;
+    for (int k = 0; k < 8; ++k) b.kids[k] = a.kids[k];
     w64[nd] = b;
 }
 
@@ -722,16 +713,28 @@ int sr_build_device(sr_tree* t, const double* pos, const double* mass, const dou
     hipLaunchKernelGGL(k_keys, grid_for(n), dim3(TPB), 0, st, pos, mass, eps, eps_scalar, n, box,
                        t->khi[0], t->klo[0], t->kidx[0], t->status);
     // 12 passes of 8 bits: lo word bits 0..47, then hi word bits 0..47
-    const int64_t nb = cdiv(n, RS_TILE);
+    const int items = n <= 384 * 1024 ? 2 : n <= 1536 * 1024 ? 4 : 8;
+    const int64_t nb = cdiv(n, (int64_t)TPB * items);
     int cur = 0;
     for (int pass = 0; pass < 12; ++pass) {
-        hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nb), dim3(TPB), 0, st, t->khi[cur], t->klo[cur], n, pass,
-                           t->hist, nb);
+        const dim3 gb((unsigned)nb), tb(TPB);
+        if (items == 2)
+            hipLaunchKernelGGL(k_rs_hist<2>, gb, tb, 0, st, t->khi[cur], t->klo[cur], n, pass, t->hist, nb);
+        else if (items == 4)
+            hipLaunchKernelGGL(k_rs_hist<4>, gb, tb, 0, st, t->khi[cur], t->klo[cur], n, pass, t->hist, nb);
+        else
+            hipLaunchKernelGGL(k_rs_hist<8>, gb, tb, 0, st, t->khi[cur], t->klo[cur], n, pass, t->hist, nb);
         int rc = sr_scan_exclusive(t->hist, t->hist, 256 * nb, t->scan_tmp, st);
         if (rc) return rc;
-        hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nb), dim3(TPB), 0, st, t->khi[cur], t->klo[cur],
-                           t->kidx[cur], t->khi[cur ^ 1], t->klo[cur ^ 1], t->kidx[cur ^ 1], n, pass,
-                           t->hist, nb);
+        if (items == 2)
+            hipLaunchKernelGGL(k_rs_scatter<2>, gb, tb, 0, st, t->khi[cur], t->klo[cur], t->kidx[cur],
+                               t->khi[cur ^ 1], t->klo[cur ^ 1], t->kidx[cur ^ 1], n, pass, t->hist, nb);
+        else if (items == 4)
+            hipLaunchKernelGGL(k_rs_scatter<4>, gb, tb, 0, st, t->khi[cur], t->klo[cur], t->kidx[cur],
+                               t->khi[cur ^ 1], t->klo[cur ^ 1], t->kidx[cur ^ 1], n, pass, t->hist, nb);
+        else
+            hipLaunchKernelGGL(k_rs_scatter<8>, gb, tb, 0, st, t->khi[cur], t->klo[cur], t->kidx[cur],
+                               t->khi[cur ^ 1], t->klo[cur ^ 1], t->kidx[cur ^ 1], n, pass, t->hist, nb);
         cur ^= 1;
     }
     // 12 passes leave the sorted keys in buffer 0
@@ -796,12 +799,9 @@ int sr_build_device(sr_tree* t, const double* pos, const double* mass, const dou
         if (!cnt) continue;
         hipLaunchKernelGGL(k_moments, grid_for(cnt), dim3(TPB), 0, st, t->depth_order + offs[d], cnt, box,
                            t->n_first, t->n_level, t->n_corner, t->prec64, t->ph64, t->nrec64, t->nS, t->ngeo64,
-                           t->nhmax, t->nhmin, t->nrec32, t->nhmax32, t->n_kids, t->n_meta, t->n_count);
-    }
-    if (m > 0)
-        hipLaunchKernelGGL(k_walk_records, grid_for(m), dim3(TPB), 0, st, m, t->n_level, t->n_corner, t->nrec32,
-                           t->nhmax32, t->nrec64, t->ngeo64, t->nhmax, t->nhmin, t->n_kids, t->n_meta,
+                           t->nhmax, t->nhmin, t->nrec32, t->nhmax32, t->n_kids, t->n_meta, t->n_count,
                            t->wrec32, t->wrec64);
+    }
     SR_HIP(hipGetLastError());
     // the root's softening range tells whether any two particles differ
     double hr[2];

@@ -1001,6 +1001,22 @@ __device__ inline float row_sum15(float x)
     return v;
 }
 
+#ifndef SR_EVAL_QL
+#define SR_EVAL_QL 16
+#endif
+constexpr int QL = SR_EVAL_QL;        // lanes (targets) per stream: 16 or 8
+constexpr int NQ = WAVE / QL;         // streams per chunk
+
+// Sum over each group of 8 lanes (DPP half-row mirror, then quad swaps): every
+// lane of the group ends with the group's total.
+__device__ inline float oct_sum(float x)
+{
+    float v = x + dpp_f32<0x141, 0xf, 0xf>(x);
+    v = v + dpp_f32<0x4e, 0xf, 0xf>(v);
+    v = v + dpp_f32<0xb1, 0xf, 0xf>(v);
+    return v;
+}
+
 // FP32 evaluation of one unit, packed by quarters.  A quarter is a row of 16
 // lanes (16 Morton-consecutive targets).  For each chunk the entries whose mask
 // touches quarter k form quarter k's stream; step s evaluates entry
@@ -1023,10 +1039,10 @@ __global__ __launch_bounds__(WAVE) void k_eval32(WalkArgs a, ListArgs L, char* _
     static_assert(PREC != PR64, "FP32 kernel");
     __shared__ SrcLds s_ent[WAVE + 1];
     __shared__ uint32_t s_src[WAVE];
-    __shared__ uint8_t s_stream[4][WAVE];
+    __shared__ uint8_t s_stream[NQ][WAVE];
     __shared__ float s_acc[ADJ ? 4 : 1][WAVE];   // adjoint: source terms of each entry
     const int lane = threadIdx.x;
-    const int quarter = lane >> 4;
+    const int quarter = lane / QL;
     const uint32_t bit = 1u << (lane & 31);
     const bool hi_half = lane >= 32;
     const int32_t u = blockIdx.x;
@@ -1074,17 +1090,18 @@ __global__ __launch_bounds__(WAVE) void k_eval32(WalkArgs a, ListArgs L, char* _
 #pragma unroll
             for (int k = 0; k < 4; ++k) s_acc[k][lane] = 0.0f;
         }
-        // the four quarter streams, each in entry order, padded with entry 64
+        // the streams (one per group of QL lanes), each in entry order, padded with entry 64
         const uint64_t below = (1ull << lane) - 1ull;
-        uint32_t nk[4];
+        constexpr uint64_t QMASK = (1ull << QL) - 1ull;
+        uint32_t steps = 0;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const uint64_t b = __ballot(has && ((lmask >> (16 * k)) & 0xffffull) != 0);
-            nk[k] = __popcll(b);
+        for (int k = 0; k < NQ; ++k) {
+            const uint64_t b = __ballot(has && ((lmask >> (QL * k)) & QMASK) != 0);
+            const uint32_t nk = __popcll(b);
             if ((b >> lane) & 1) s_stream[k][__popcll(b & below)] = (uint8_t)lane;
-            if ((uint32_t)lane >= nk[k]) s_stream[k][lane] = (uint8_t)WAVE;   // slots past the stream
+            if ((uint32_t)lane >= nk) s_stream[k][lane] = (uint8_t)WAVE;   // slots past the stream
+            steps = max(steps, nk);
         }
-        const uint32_t steps = max(max(nk[0], nk[1]), max(nk[2], nk[3]));
         const int32_t cnext = L.chunk_next[c];
         wave_sync();
         for (uint32_t st = 0; st < steps; ++st) {
@@ -1136,12 +1153,20 @@ __global__ __launch_bounds__(WAVE) void k_eval32(WalkArgs a, ListArgs L, char* _
                 tbx -= (acc_t)px;
                 tby -= (acc_t)py;
                 tbz -= (acc_t)pz;
-                // source terms: per-row sums, collected per entry
-                const float sx = row_sum15(px);
-                const float sy = row_sum15(py);
-                const float sz = row_sum15(pz);
-                const float sm = row_sum15(K * wd);
-                if ((lane & 15) == 15 && e < (uint32_t)WAVE) {
+                // source terms: sums over each stream's lanes, collected per entry
+                float sx, sy, sz, sm;
+                if constexpr (QL == 16) {
+                    sx = row_sum15(px);
+                    sy = row_sum15(py);
+                    sz = row_sum15(pz);
+                    sm = row_sum15(K * wd);
+                } else {
+                    sx = oct_sum(px);
+                    sy = oct_sum(py);
+                    sz = oct_sum(pz);
+                    sm = oct_sum(K * wd);
+                }
+                if ((lane % QL) == QL - 1 && e < (uint32_t)WAVE) {
                     atomicAdd(&s_acc[0][e], sx);
                     atomicAdd(&s_acc[1][e], sy);
                     atomicAdd(&s_acc[2][e], sz);
