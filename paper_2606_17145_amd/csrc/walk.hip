@@ -1001,11 +1001,10 @@ __device__ inline float row_sum15(float x)
     return v;
 }
 
-#ifndef SR_EVAL_QL
-#define SR_EVAL_QL 16
-#endif
-constexpr int QL = SR_EVAL_QL;        // lanes (targets) per stream: 16 or 8
-constexpr int NQ = WAVE / QL;         // streams per chunk
+// Lanes (targets) per stream of the FP32 evaluation: 8 for the forward, 16 for
+// the adjoint (whose per-stream source sums are DPP row operations).
+constexpr int QL_FWD = 8;
+constexpr int QL_ADJ = 16;
 
 // Sum over each group of 8 lanes (DPP half-row mirror, then quad swaps): every
 // lane of the group ends with the group's total.
@@ -1037,6 +1036,8 @@ __global__ __launch_bounds__(WAVE) void k_eval32(WalkArgs a, ListArgs L, char* _
 {
     using acc_t = typename std::conditional<PREC == PR32, float, double>::type;
     static_assert(PREC != PR64, "FP32 kernel");
+    constexpr int QL = ADJ ? QL_ADJ : QL_FWD;
+    constexpr int NQ = WAVE / QL;
     __shared__ SrcLds s_ent[WAVE + 1];
     __shared__ uint32_t s_src[WAVE];
     __shared__ uint8_t s_stream[NQ][WAVE];
@@ -1132,7 +1133,7 @@ __global__ __launch_bounds__(WAVE) void k_eval32(WalkArgs a, ListArgs L, char* _
                 S = spline_h3S_32f(qq) * ih3;
                 if constexpr (ADJ) Srd = spline_h4dS_32f(qq) * qq * ih3;
             }
-            cnt2 += in ? src.inc : 0u;
+            if constexpr (!ADJ) cnt2 += in ? src.inc : 0u;
             const float K = in ? S * gg : 0.0f;
             if constexpr (!ADJ) {
                 const float f = qm * K;
@@ -1140,16 +1141,16 @@ __global__ __launch_bounds__(WAVE) void k_eval32(WalkArgs a, ListArgs L, char* _
                 ay += (acc_t)(f * dy);
                 az += (acc_t)(f * dz);
             } else {
-                // J w = K w + (K' r)(w . n) n,  K' r = r S' g + S g'(u) u
+                // J w = K w + (K' r)(w . n) n,  K' r = r S' g + S g'(u) u; with n = d / r:
+                // m J w = (m K) w + (m K' r (w . d) / r^2) d
                 const float dg = -2.0f * TWO_OVER_SQRTPI_F * uu * uu * ex;
                 const float Kr = in ? Srd * gg + S * dg * uu : 0.0f;
-                const float nx = dx * rinv, ny = dy * rinv, nz = dz * rinv;
-                const float wn = __builtin_fmaf(wx, nx, __builtin_fmaf(wy, ny, wz * nz));
                 const float wd = __builtin_fmaf(wx, dx, __builtin_fmaf(wy, dy, wz * dz));
-                const float cc = Kr * wn;
-                const float px = qm * __builtin_fmaf(K, wx, cc * nx);
-                const float py = qm * __builtin_fmaf(K, wy, cc * ny);
-                const float pz = qm * __builtin_fmaf(K, wz, cc * nz);
+                const float cA = qm * K;
+                const float cB = qm * (Kr * wd) * (rinv * rinv);
+                const float px = __builtin_fmaf(cA, wx, cB * dx);
+                const float py = __builtin_fmaf(cA, wy, cB * dy);
+                const float pz = __builtin_fmaf(cA, wz, cB * dz);
                 tbx -= (acc_t)px;
                 tby -= (acc_t)py;
                 tbz -= (acc_t)pz;
