@@ -114,27 +114,9 @@ __device__ inline float gshort32(float u, float& e)
     return e * p;
 }
 
-// Softened branch in FP32: h^3 S as a function of q, written around q = 1 in the
-// outer part so that nothing cancels; also q dS/dq-type term for the adjoint.
-__device__ inline float spline_h3S_32(float q)
-{
-    if (q < 0.5f) return __builtin_fmaf(q * q, __builtin_fmaf(32.0f, q, -38.4f), 10.6666666667f);
-    float t = 1.0f - q;
-    float poly = __builtin_fmaf(t, __builtin_fmaf(t, __builtin_fmaf(t, 10.6666666667f, 6.4f), 3.2f), 1.06666666667f);
-    return poly - 1.0f / (15.0f * q * q * q);
-}
-
-// h^4 dS/dr as a function of q.
-__device__ inline float spline_h4dS_32(float q)
-{
-    if (q < 0.5f) return q * __builtin_fmaf(96.0f, q, -76.8f);
-    float t = 1.0f - q;
-    float q2 = q * q;
-    return __builtin_fmaf(t, __builtin_fmaf(t, -32.0f, -12.8f), -3.2f) + 1.0f / (5.0f * q2 * q2);
-}
-
-// The same two functions without branches or IEEE division (both pieces are
-// computed and selected; 1/x by v_rcp_f32, 1 ulp).
+// Softened branch in FP32: h^3 S and h^4 dS/dr as functions of q = r / h, the
+// outer part written around q = 1 so that nothing cancels; both pieces are
+// computed and selected, 1/x by v_rcp_f32 (1 ulp).
 __device__ inline float spline_h3S_32f(float q)
 {
     const float inner = __builtin_fmaf(q * q, __builtin_fmaf(32.0f, q, -38.4f), 10.6666666667f);
@@ -153,7 +135,7 @@ __device__ inline float spline_h4dS_32f(float q)
     return q < 0.5f ? inner : outer;
 }
 
-// ---- wave reductions (DPP row shifts and row broadcasts; the total lands in lane 63) ----
+// ---- DPP moves (lane permutations within rows of 16, used for row and group sums) ----
 
 template <int CTRL, int ROWMASK, int BANKMASK>
 __device__ inline float dpp_f32(float v)
@@ -171,28 +153,6 @@ __device__ inline double dpp_f64(double v)
 }
 
 
-template <class T, int CTRL, int ROWMASK, int BANKMASK>
-__device__ inline T dppm(T v)
-{
-    if constexpr (sizeof(T) == 4) return dpp_f32<CTRL, ROWMASK, BANKMASK>(v);
-    else return dpp_f64<CTRL, ROWMASK, BANKMASK>(v);
-}
-
-// Sum over the 64 lanes: rows of 16 by shifts of 1, 2, 3, 4, 8, then rows
-// chained by broadcasts of lanes 15 and 31.  Only lane 63 holds the total.
-template <class T>
-__device__ inline T wave_sum63(T x)
-{
-    T v = x + dppm<T, 0x111, 0xf, 0xf>(x);
-    v = v + dppm<T, 0x112, 0xf, 0xf>(x);
-    v = v + dppm<T, 0x113, 0xf, 0xf>(x);
-    v = v + dppm<T, 0x114, 0xf, 0xe>(v);
-    v = v + dppm<T, 0x118, 0xf, 0xc>(v);
-    v = v + dppm<T, 0x142, 0xa, 0xf>(v);
-    v = v + dppm<T, 0x143, 0xc, 0xf>(v);
-    return v;
-}
-
 // ----------------------------------------------------------------------------------
 // cross-lane helpers
 // ----------------------------------------------------------------------------------
@@ -201,14 +161,9 @@ __device__ inline T wave_sum63(T x)
 // select that writes one lane of a VGPR.
 
 __device__ inline uint32_t rl(uint32_t v, uint32_t l) { return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)l); }
-__device__ inline float rlf(float v, uint32_t l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), (int)l)); }
 __device__ inline uint64_t rl64(uint64_t v, uint32_t l)
 {
     return ((uint64_t)rl((uint32_t)(v >> 32), l) << 32) | rl((uint32_t)v, l);
-}
-__device__ inline double rld(double v, uint32_t l)
-{
-    return __longlong_as_double((long long)rl64((uint64_t)__double_as_longlong(v), l));
 }
 template <class T>
 __device__ inline T wl(T v, uint32_t l, T old)
@@ -765,230 +720,8 @@ __global__ __launch_bounds__(TW * WAVE) __attribute__((amdgpu_waves_per_eu(4, 8)
 // phase 2: evaluation of one unit (up to UCH chunks of one group)
 // ----------------------------------------------------------------------------------
 
-struct Src64 {
-    double x = 0, y = 0, z = 0, m = 0, h = 0;
-};
-struct Src32 {
-    uint32_t X = 0, Y = 0, Z = 0;
-    float m = 0, h = 0;
-};
-
 // per-unit partial results: acc_t[3][64] then int32[2][64] (forward) or acc_t[3][64] (adjoint)
 constexpr int PARTIAL_BYTES = 64 * (3 * 8 + 2 * 4);
-
-template <int PREC, bool ADJ>
-__global__ __launch_bounds__(WAVE) void k_eval(WalkArgs a, ListArgs L, char* __restrict__ partials)
-{
-    using acc_t = typename std::conditional<PREC == PR32, float, double>::type;
-    constexpr bool F64 = PREC == PR64;
-    using SrcT = typename std::conditional<F64, Src64, Src32>::type;
-    const int lane = threadIdx.x;
-    const int32_t u = blockIdx.x;
-    if (L.unit_nch[u] == 0) return;   // a unit reserved but not used (its partials are never read)
-    const int64_t g = L.unit_group[u];
-    const int64_t t = g * WAVE + lane;
-    const bool valid = t < a.n_t;
-    const int32_t s_i = valid ? a.tgt_sorted[t] : 0;
-    double x64 = 0, y64 = 0, z64 = 0, h64 = 0;
-    uint32_t X = 0, Y = 0, Z = 0;
-    float h32 = 0, h32sq = 0;
-    if constexpr (F64) {
-        const Rec64 r = a.prec64[s_i];
-        x64 = r.x;
-        y64 = r.y;
-        z64 = r.z;
-        h64 = a.ph64[s_i];
-    } else {
-        const Rec32 r = a.prec32[s_i];
-        X = r.X;
-        Y = r.Y;
-        Z = r.Z;
-        h32 = a.ph32[s_i];
-        h32sq = h32 * h32;
-    }
-    acc_t ax = 0, ay = 0, az = 0;
-    int npp = 0, npn = 0;
-    acc_t wx = 0, wy = 0, wz = 0, tbx = 0, tby = 0, tbz = 0;
-    if constexpr (ADJ) {
-        if (valid) {
-            const int32_t slot = a.tgt_slot[t];
-            const acc_t* w = (const acc_t*)a.w;
-            wx = w[3 * (int64_t)slot];
-            wy = w[3 * (int64_t)slot + 1];
-            wz = w[3 * (int64_t)slot + 2];
-        }
-    }
-
-    int32_t c = L.unit_chunk[u];
-    const int32_t nch = L.unit_nch[u];
-    for (int32_t q = 0; q < nch; ++q) {
-        const uint32_t cnt = (uint32_t)L.chunk_cnt[c];
-        uint32_t lsrc = 0;
-        uint64_t lmask = 0;
-        SrcT mine;
-        if ((uint32_t)lane < cnt) {
-            lsrc = L.ent_src[64 * (int64_t)c + lane];
-            lmask = L.ent_mask[64 * (int64_t)c + lane];
-            const bool isp = lsrc & ITEM_PARTICLE;
-            const uint32_t idx = lsrc & ~ITEM_PARTICLE;
-            if constexpr (F64) {
-                const Rec64 r = isp ? a.prec64[idx] : a.nrec64[idx];
-                mine.x = r.x;
-                mine.y = r.y;
-                mine.z = r.z;
-                mine.m = r.m;
-                mine.h = isp ? a.ph64[idx] : a.nhmax[idx];
-            } else {
-                const Rec32 r = isp ? a.prec32[idx] : a.nrec32[idx];
-                const float hs = isp ? a.ph32[idx] : a.nhmax32[idx];
-                mine.X = r.X;
-                mine.Y = r.Y;
-                mine.Z = r.Z;
-                mine.m = r.m * TWO64_F;
-                mine.h = hs * hs;   // squared support of the source
-            }
-        }
-        const int32_t cnext = L.chunk_next[c];
-        for (uint32_t e = 0; e < cnt; ++e) {
-            const uint32_t src = rl(lsrc, e);
-            const uint64_t m = rl64(lmask, e);
-            const bool isp = (src & ITEM_PARTICLE) != 0;
-            const bool on = (m >> lane) & 1ull;
-            acc_t vx = 0, vy = 0, vz = 0, vm = 0;
-            if constexpr (F64) {
-                const double qx = rld(mine.x, e), qy = rld(mine.y, e), qz = rld(mine.z, e);
-                const double qm = rld(mine.m, e), qh = rld(mine.h, e);
-                if (on) {
-                    const double dx = min_image(qx - x64, a.box);
-                    const double dy = min_image(qy - y64, a.box);
-                    const double dz = min_image(qz - z64, a.box);
-                    const double r2 = (dx * dx + dy * dy) + dz * dz;
-                    if (r2 < a.rc2) {
-                        if (isp) ++npp;
-                        else ++npn;
-                        const double r = sqrt(r2);
-                        const double uu = r * a.inv2rs;
-                        const double ex = exp(-uu * uu);
-                        const double gg = erfc(uu) + TWO_OVER_SQRTPI * uu * ex;
-                        const double hp = h64 > qh ? h64 : qh;
-                        double S, dS;
-                        spline64(r, hp, S, dS);
-                        const double K = a.G * S * gg;
-                        if constexpr (!ADJ) {
-                            const double f = qm * K;
-                            ax += f * dx;
-                            ay += f * dy;
-                            az += f * dz;
-                        } else {
-                            const double dg = -2.0 * TWO_OVER_SQRTPI * uu * uu * ex;
-                            const double dK = a.G * (dS * gg + S * dg * a.inv2rs);
-                            const double c2 = r > 0.0 ? dK / r : 0.0;
-                            const double wd = (wx * dx + wy * dy) + wz * dz;
-                            vx = qm * (K * wx + c2 * wd * dx);
-                            vy = qm * (K * wy + c2 * wd * dy);
-                            vz = qm * (K * wz + c2 * wd * dz);
-                            vm = K * wd;
-                            tbx -= vx;
-                            tby -= vy;
-                            tbz -= vz;
-                        }
-                    }
-                }
-            } else {
-                // branch-free: every lane computes, lanes outside the entry select zero
-                const float qm = rlf(mine.m, e), qh2 = rlf(mine.h, e);
-                const float dx = (float)(int32_t)(rl(mine.X, e) - X);
-                const float dy = (float)(int32_t)(rl(mine.Y, e) - Y);
-                const float dz = (float)(int32_t)(rl(mine.Z, e) - Z);
-                const float r2 = r2_ticks(dx, dy, dz);
-                const bool in = on && r2 < a.rc2t;
-                const float rinv = __builtin_amdgcn_rsqf(r2);
-                const float r = r2 > 0.0f ? r2 * rinv : 0.0f;
-                const float uu = r * a.inv2rs_t;
-                float ex;
-                const float gg = gshort32(uu, ex);
-                float S = rinv * rinv * rinv;
-                float Srd = -3.0f * S;
-                const bool soft = in && r2 < fmaxf(h32sq, qh2);
-                if (__ballot(soft)) {
-                    if (soft) {
-                        const float hp = __builtin_sqrtf(fmaxf(h32sq, qh2));
-                        const float ih = __builtin_amdgcn_rcpf(hp);
-                        const float qq = r * ih;
-                        const float ih3 = ih * ih * ih;
-                        S = spline_h3S_32(qq) * ih3;
-                        if constexpr (ADJ) Srd = spline_h4dS_32(qq) * qq * ih3;
-                    }
-                }
-                if (isp) npp += in ? 1 : 0;
-                else npn += in ? 1 : 0;
-                const float K = in ? S * gg : 0.0f;
-                if constexpr (!ADJ) {
-                    const float f = qm * K;
-                    ax += (acc_t)(f * dx);
-                    ay += (acc_t)(f * dy);
-                    az += (acc_t)(f * dz);
-                } else {
-                    // J w = K w + (K' r)(w . n) n,  K' r = r S' g + S g'(u) u
-                    const float dg = -2.0f * TWO_OVER_SQRTPI_F * uu * uu * ex;
-                    const float Kr = in ? Srd * gg + S * dg * uu : 0.0f;
-                    const float nrm = r2 > 0.0f ? rinv : 0.0f;
-                    const float nx = dx * nrm, ny = dy * nrm, nz = dz * nrm;
-                    const float fx = (float)wx, fy = (float)wy, fz = (float)wz;
-                    const float wn = __builtin_fmaf(fx, nx, __builtin_fmaf(fy, ny, fz * nz));
-                    const float wd = __builtin_fmaf(fx, dx, __builtin_fmaf(fy, dy, fz * dz));
-                    const float cc = Kr * wn;
-                    const float px = qm * __builtin_fmaf(K, fx, cc * nx);
-                    const float py = qm * __builtin_fmaf(K, fy, cc * ny);
-                    const float pz = qm * __builtin_fmaf(K, fz, cc * nz);
-                    vx = px;
-                    vy = py;
-                    vz = pz;
-                    vm = K * wd;
-                    tbx -= (acc_t)px;
-                    tby -= (acc_t)py;
-                    tbz -= (acc_t)pz;
-                }
-            }
-            if constexpr (ADJ) {
-                // source terms: wave sum, then one atomic per (wave, source, component)
-                double sx, sy, sz, smass;
-                if constexpr (F64) {
-                    sx = wave_sum63<double>(vx);
-                    sy = wave_sum63<double>(vy);
-                    sz = wave_sum63<double>(vz);
-                    smass = wave_sum63<double>(vm);
-                } else {
-                    sx = wave_sum63<float>((float)vx);
-                    sy = wave_sum63<float>((float)vy);
-                    sz = wave_sum63<float>((float)vz);
-                    smass = wave_sum63<float>((float)vm);
-                }
-                if (lane == 63) {
-                    double* dst = isp ? a.pbar + 4 * (int64_t)(src & ~ITEM_PARTICLE) : a.nbar + 4 * (int64_t)src;
-                    unsafeAtomicAdd(dst + 0, sx);
-                    unsafeAtomicAdd(dst + 1, sy);
-                    unsafeAtomicAdd(dst + 2, sz);
-                    unsafeAtomicAdd(dst + 3, smass);
-                }
-            }
-        }
-        c = cnext;
-    }
-    acc_t* pa = (acc_t*)(partials + (int64_t)u * PARTIAL_BYTES);
-    if constexpr (!ADJ) {
-        pa[lane] = ax;
-        pa[64 + lane] = ay;
-        pa[128 + lane] = az;
-        int32_t* pc = (int32_t*)(pa + 192);
-        pc[lane] = npp;
-        pc[64 + lane] = npn;
-    } else {
-        pa[lane] = tbx;
-        pa[64 + lane] = tby;
-        pa[128 + lane] = tbz;
-    }
-}
 
 // Sum over each row of 16 lanes by a rotation butterfly (DPP row_ror 1, 2, 4,
 // 8): every lane of row k ends with row k's total.
@@ -1192,6 +925,176 @@ __global__ __launch_bounds__(WAVE) void k_eval32(WalkArgs a, ListArgs L, char* _
         c = cnext;
     }
     acc_t* pa = (acc_t*)(partials + (int64_t)u * PARTIAL_BYTES);
+    if constexpr (!ADJ) {
+        pa[lane] = ax;
+        pa[64 + lane] = ay;
+        pa[128 + lane] = az;
+        int32_t* pc = (int32_t*)(pa + 192);
+        pc[lane] = (int32_t)(cnt2 & 0xffffu);
+        pc[64 + lane] = (int32_t)(cnt2 >> 16);
+    } else {
+        pa[lane] = tbx;
+        pa[64 + lane] = tby;
+        pa[128 + lane] = tbz;
+    }
+}
+
+// FP64 evaluation of one unit, packed into streams like the FP32 kernel (QL
+// lanes per stream); the pair arithmetic is the plain FP64 form (library erfc,
+// exp and square root, division) and each lane sums its entries in entry order.
+struct alignas(16) SrcLds64 {
+    double x, y, z, m, h;          // position, mass, support h
+    uint32_t sid, inc, mlo, mhi;   // source id, count increment, mask of lanes 0-31 / 32-63
+    uint32_t pad[2];
+};
+
+// FP64 sum over each row of 16 lanes (rotation butterfly on both halves).
+__device__ inline double row_sum15_f64(double x)
+{
+    double v = x + dpp_f64<0x121, 0xf, 0xf>(x);
+    v = v + dpp_f64<0x122, 0xf, 0xf>(v);
+    v = v + dpp_f64<0x124, 0xf, 0xf>(v);
+    v = v + dpp_f64<0x128, 0xf, 0xf>(v);
+    return v;
+}
+
+template <bool ADJ>
+__global__ __launch_bounds__(WAVE) void k_eval64(WalkArgs a, ListArgs L, char* __restrict__ partials)
+{
+    constexpr int QL = 16;
+    constexpr int NQ = WAVE / QL;
+    __shared__ SrcLds64 s_ent[WAVE + 1];
+    __shared__ uint8_t s_stream[NQ][WAVE];
+    __shared__ double s_acc[ADJ ? 4 : 1][WAVE];   // adjoint: source terms of each entry
+    const int lane = threadIdx.x;
+    const int quarter = lane / QL;
+    const uint32_t bit = 1u << (lane & 31);
+    const bool hi_half = lane >= 32;
+    const int32_t u = blockIdx.x;
+    if (L.unit_nch[u] == 0) return;   // a unit reserved but not used (its partials are never read)
+    const int64_t g = L.unit_group[u];
+    const int64_t t = g * WAVE + lane;
+    const bool valid = t < a.n_t;
+    const int32_t s_i = valid ? a.tgt_sorted[t] : 0;
+    const Rec64 tr = a.prec64[s_i];
+    const double x64 = tr.x, y64 = tr.y, z64 = tr.z, h64 = a.ph64[s_i];
+    double ax = 0, ay = 0, az = 0;
+    uint32_t cnt2 = 0;       // interactions: particles in the low half, nodes in the high half
+    double wx = 0, wy = 0, wz = 0, tbx = 0, tby = 0, tbz = 0;
+    if constexpr (ADJ) {
+        if (valid) {
+            const int32_t slot = a.tgt_slot[t];
+            const double* w = (const double*)a.w;
+            wx = w[3 * (int64_t)slot];
+            wy = w[3 * (int64_t)slot + 1];
+            wz = w[3 * (int64_t)slot + 2];
+        }
+    }
+    if (lane == 0) s_ent[WAVE] = SrcLds64{0.0, 0.0, 0.0, 0.0, 0.0, 0u, 0u, 0u, 0u, {0u, 0u}};
+
+    int32_t c = L.unit_chunk[u];
+    const int32_t nch = L.unit_nch[u];
+    for (int32_t q = 0; q < nch; ++q) {
+        const uint32_t cnt = (uint32_t)L.chunk_cnt[c];
+        const bool has = (uint32_t)lane < cnt;
+        uint64_t lmask = 0;
+        if (has) {
+            const uint32_t lsrc = L.ent_src[64 * (int64_t)c + lane];
+            lmask = L.ent_mask[64 * (int64_t)c + lane];
+            const bool isp = lsrc & ITEM_PARTICLE;
+            const uint32_t idx = lsrc & ~ITEM_PARTICLE;
+            const Rec64 r = isp ? a.prec64[idx] : a.nrec64[idx];
+            const double hs = isp ? a.ph64[idx] : a.nhmax[idx];
+            s_ent[lane] = SrcLds64{r.x, r.y, r.z, r.m, hs, lsrc, isp ? 1u : 0x10000u, (uint32_t)lmask,
+                                   (uint32_t)(lmask >> 32), {0u, 0u}};
+        }
+        if constexpr (ADJ) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) s_acc[k][lane] = 0.0;
+        }
+        const uint64_t below = (1ull << lane) - 1ull;
+        constexpr uint64_t QMASK = (1ull << QL) - 1ull;
+        uint32_t steps = 0;
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) {
+            const uint64_t b = __ballot(has && ((lmask >> (QL * k)) & QMASK) != 0);
+            const uint32_t nk = __popcll(b);
+            if ((b >> lane) & 1) s_stream[k][__popcll(b & below)] = (uint8_t)lane;
+            if ((uint32_t)lane >= nk) s_stream[k][lane] = (uint8_t)WAVE;   // slots past the stream
+            steps = max(steps, nk);
+        }
+        const int32_t cnext = L.chunk_next[c];
+        wave_sync();
+        for (uint32_t st = 0; st < steps; ++st) {
+            const uint32_t e = s_stream[quarter][st];
+            const SrcLds64 src = s_ent[e];
+            const uint32_t mw = hi_half ? src.mhi : src.mlo;
+            const bool on = (mw & bit) != 0;
+            double vx = 0, vy = 0, vz = 0, vm = 0;
+            const double dx = min_image(src.x - x64, a.box);
+            const double dy = min_image(src.y - y64, a.box);
+            const double dz = min_image(src.z - z64, a.box);
+            const double r2 = (dx * dx + dy * dy) + dz * dz;
+            if (on && r2 < a.rc2) {
+                if constexpr (!ADJ) cnt2 += src.inc;
+                const double r = sqrt(r2);
+                const double uu = r * a.inv2rs;
+                const double ex = exp(-uu * uu);
+                const double gg = erfc(uu) + TWO_OVER_SQRTPI * uu * ex;
+                const double hp = h64 > src.h ? h64 : src.h;
+                double S, dS;
+                spline64(r, hp, S, dS);
+                const double K = a.G * S * gg;
+                if constexpr (!ADJ) {
+                    const double f = src.m * K;
+                    ax += f * dx;
+                    ay += f * dy;
+                    az += f * dz;
+                } else {
+                    const double dg = -2.0 * TWO_OVER_SQRTPI * uu * uu * ex;
+                    const double dK = a.G * (dS * gg + S * dg * a.inv2rs);
+                    const double c2 = r > 0.0 ? dK / r : 0.0;
+                    const double wd = (wx * dx + wy * dy) + wz * dz;
+                    vx = src.m * (K * wx + c2 * wd * dx);
+                    vy = src.m * (K * wy + c2 * wd * dy);
+                    vz = src.m * (K * wz + c2 * wd * dz);
+                    vm = K * wd;
+                    tbx -= vx;
+                    tby -= vy;
+                    tbz -= vz;
+                }
+            }
+            if constexpr (ADJ) {
+                // source terms: sums over each stream's lanes, collected per entry
+                const double sx = row_sum15_f64(vx);
+                const double sy = row_sum15_f64(vy);
+                const double sz = row_sum15_f64(vz);
+                const double sm = row_sum15_f64(vm);
+                if ((lane % QL) == QL - 1 && e < (uint32_t)WAVE) {
+                    atomicAdd(&s_acc[0][e], sx);
+                    atomicAdd(&s_acc[1][e], sy);
+                    atomicAdd(&s_acc[2][e], sz);
+                    atomicAdd(&s_acc[3][e], sm);
+                }
+            }
+        }
+        wave_sync();
+        if constexpr (ADJ) {
+            if (has) {
+                const uint32_t sid = s_ent[lane].sid;
+                double* dst = (sid & ITEM_PARTICLE) ? a.pbar + 4 * (int64_t)(sid & ~ITEM_PARTICLE)
+                                                    : a.nbar + 4 * (int64_t)sid;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const double v = s_acc[k][lane];
+                    if (v != 0.0) unsafeAtomicAdd(dst + k, v);
+                }
+            }
+            wave_sync();
+        }
+        c = cnext;
+    }
+    double* pa = (double*)(partials + (int64_t)u * PARTIAL_BYTES);
     if constexpr (!ADJ) {
         pa[lane] = ax;
         pa[64 + lane] = ay;
@@ -1518,7 +1421,7 @@ int eval_and_reduce(sr_tree* t, const sr_params* p, const WalkArgs& a, hipStream
     if (t->n_units > 0) {
         sr_timing_mark(ph_eval, true, st);
         switch (p->precision) {
-        case SR_FP64: hipLaunchKernelGGL((k_eval<PR64, ADJ>), gu, dim3(WAVE), 0, st, a, L, t->partials); break;
+        case SR_FP64: hipLaunchKernelGGL((k_eval64<ADJ>), gu, dim3(WAVE), 0, st, a, L, t->partials); break;
         case SR_FP32: hipLaunchKernelGGL((k_eval32<PR32, ADJ>), gu, dim3(WAVE), 0, st, a, L, t->partials); break;
         default: hipLaunchKernelGGL((k_eval32<PR32A, ADJ>), gu, dim3(WAVE), 0, st, a, L, t->partials); break;
         }
