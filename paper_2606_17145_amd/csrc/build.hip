@@ -64,6 +64,9 @@ __global__ void k_keys(const double* __restrict__ pos, const double* __restrict_
     double e = eps ? eps[i] : eps_scalar;
     if (!(isfinite(m) && m > 0.0) || !(isfinite(e) && e > 0.0)) bad = true;
     if (bad) atomicOr(&status[ST_FLAGS], 1);
+    // bit 1: some softening differs from particle 0's (one atomic per wave at most)
+    const bool differs = eps && e != eps[0];
+    if (__ballot(differs) && (threadIdx.x & 63) == __builtin_ctzll(__ballot(differs))) atomicOr(&status[ST_FLAGS], 2);
     // digits 1..15 from coordinate bits 29..15, digits 16..30 from bits 14..0; x-major
     khi[i] = (spread3(c[0] >> 15) << 2) | (spread3(c[1] >> 15) << 1) | spread3(c[2] >> 15);
     klo[i] = (spread3(c[0] & 0x7fffu) << 2) | (spread3(c[1] & 0x7fffu) << 1) | spread3(c[2] & 0x7fffu);
@@ -487,12 +490,18 @@ __global__ void k_particle_items(int64_t n, const int32_t* __restrict__ leaf_bpa
 // ------------------------------------------------------------------------------------
 
 __global__ void k_depth_scatter(int64_t m, const int32_t* __restrict__ n_depth,
-                                const int32_t* __restrict__ offsets, int32_t* __restrict__ cursor,
+                                const int32_t* __restrict__ hist, int32_t* __restrict__ cursor,
                                 int32_t* __restrict__ order)
 {
-    // ranks within the block from LDS counters; one global reservation per depth and block
-    __shared__ int32_t cnt[SR_MAX_DEPTH], off[SR_MAX_DEPTH];
-    if (threadIdx.x < SR_MAX_DEPTH) cnt[threadIdx.x] = 0;
+    // ranks within the block from LDS counters; one global reservation per depth and block;
+    // depth d starts at the sum of the node counts of the depths above it
+    __shared__ int32_t cnt[SR_MAX_DEPTH], off[SR_MAX_DEPTH], base[SR_MAX_DEPTH];
+    if (threadIdx.x < SR_MAX_DEPTH) {
+        cnt[threadIdx.x] = 0;
+        int32_t b = 0;
+        for (int k = 0; k < (int)threadIdx.x; ++k) b += hist[k];
+        base[threadIdx.x] = b;
+    }
     __syncthreads();
     int64_t nd = blockIdx.x * (int64_t)TPB + threadIdx.x;
     int d = -1, r = 0;
@@ -504,7 +513,7 @@ __global__ void k_depth_scatter(int64_t m, const int32_t* __restrict__ n_depth,
     if (threadIdx.x < SR_MAX_DEPTH && cnt[threadIdx.x])
         off[threadIdx.x] = atomicAdd(&cursor[threadIdx.x], cnt[threadIdx.x]);
     __syncthreads();
-    if (d >= 0) order[offsets[d] + off[d] + r] = (int32_t)nd;
+    if (d >= 0) order[base[d] + off[d] + r] = (int32_t)nd;
 }
 
 // Fold the children of every node of one depth, left to right in digit order:
@@ -761,6 +770,8 @@ int sr_build_device(sr_tree* t, const double* pos, const double* mass, const dou
     SR_HIP(hipMemcpyAsync(hstat, t->status, sizeof(hstat), hipMemcpyDeviceToHost, st));
     SR_HIP(hipStreamSynchronize(st));
     if (hstat[ST_FLAGS] & 1) return sr_fail(SR_EINVAL, "tree_build: non-finite position or non-positive / non-finite mass or softening");
+    // softenings that are not all equal select the walk's mixed-softening opening rule
+    t->mixed_soft = (hstat[ST_FLAGS] & 2) != 0;
     const int64_t m = n > 1 ? hstat[ST_NODES] : 0;
     t->n_nodes = m;
     if (m > 0) {
@@ -786,12 +797,10 @@ int sr_build_device(sr_tree* t, const double* pos, const double* mass, const dou
         offs[d] = acc;
         acc += hstat[ST_HIST + d];
     }
-    // offsets go through the status words (free again) to the device
-    SR_HIP(hipMemcpyAsync(t->status, offs, sizeof(offs), hipMemcpyHostToDevice, st));
     hipLaunchKernelGGL(k_fill_i32, grid_for(SR_MAX_DEPTH), dim3(TPB), 0, st, t->depth_cursor,
                        (int64_t)SR_MAX_DEPTH, 0);
-    hipLaunchKernelGGL(k_depth_scatter, grid_for(m), dim3(TPB), 0, st, m, t->n_depth, t->status, t->depth_cursor,
-                       t->depth_order);
+    hipLaunchKernelGGL(k_depth_scatter, grid_for(m), dim3(TPB), 0, st, m, t->n_depth, t->status + ST_HIST,
+                       t->depth_cursor, t->depth_order);
     hipLaunchKernelGGL(k_child_table, grid_for(m), dim3(TPB), 0, st, m, t->items, t->n_first, t->n_level,
                        t->n_count, t->n_kids, t->n_meta);
     for (int d = t->max_depth; d >= 0; --d) {
@@ -803,12 +812,5 @@ int sr_build_device(sr_tree* t, const double* pos, const double* mass, const dou
                            t->wrec32, t->wrec64);
     }
     SR_HIP(hipGetLastError());
-    // the root's softening range tells whether any two particles differ
-    double hr[2];
-    SR_HIP(hipMemcpyAsync(&hr[0], t->nhmax, sizeof(double), hipMemcpyDeviceToHost, st));
-    SR_HIP(hipMemcpyAsync(&hr[1], t->nhmin, sizeof(double), hipMemcpyDeviceToHost, st));
-    // (this also keeps the host copy of the offsets alive until the copies above are done)
-    SR_HIP(hipStreamSynchronize(st));
-    t->mixed_soft = hr[0] != hr[1];
     return SR_OK;
 }

@@ -149,6 +149,7 @@ struct sr_tree {
     uint32_t* frontier = nullptr;      // per traversal wave: 2 x cap_front node ids + 2 x cap_front masks
     int64_t cap_front = 0, n_front_waves = 0;
     int64_t n_units = 0, n_chunks = 0, n_tests = 0;
+    int64_t unit_hint = 0;             // unit count expected from the previous traversal
     ListKey lkey;
     int64_t build_gen = 0;
 

@@ -202,6 +202,7 @@ struct ListArgs {
     int32_t* counters;      // [0] chunks, [1] units, [2] overflow, [4..5] node tests (u64)
     int64_t cap_chunks;
     int64_t cap_units;
+    int32_t unit_base;      // evaluation: first unit of this launch
 };
 
 // open and accept masks of one decision
@@ -779,7 +780,10 @@ __global__ __launch_bounds__(WAVE) void k_eval32(WalkArgs a, ListArgs L, char* _
     const int quarter = lane / QL;
     const uint32_t bit = 1u << (lane & 31);
     const bool hi_half = lane >= 32;
-    const int32_t u = blockIdx.x;
+    // units past the traversal's count, or the lists of a traversal that overflowed, are
+    // not read (the launch may be sized before the count is known on the host)
+    const int32_t u = L.unit_base + (int32_t)blockIdx.x;
+    if (u >= L.counters[1] || L.counters[2] != 0) return;
     if (L.unit_nch[u] == 0) return;   // a unit reserved but not used (its partials are never read)
     const int64_t g = L.unit_group[u];
     const int64_t t = g * WAVE + lane;
@@ -970,7 +974,10 @@ __global__ __launch_bounds__(WAVE) void k_eval64(WalkArgs a, ListArgs L, char* _
     const int quarter = lane / QL;
     const uint32_t bit = 1u << (lane & 31);
     const bool hi_half = lane >= 32;
-    const int32_t u = blockIdx.x;
+    // units past the traversal's count, or the lists of a traversal that overflowed, are
+    // not read (the launch may be sized before the count is known on the host)
+    const int32_t u = L.unit_base + (int32_t)blockIdx.x;
+    if (u >= L.counters[1] || L.counters[2] != 0) return;
     if (L.unit_nch[u] == 0) return;   // a unit reserved but not used (its partials are never read)
     const int64_t g = L.unit_group[u];
     const int64_t t = g * WAVE + lane;
@@ -1318,6 +1325,7 @@ ListArgs list_args(const sr_tree* t)
     L.counters = t->list_counters;
     L.cap_chunks = t->cap_chunks;
     L.cap_units = t->cap_units;
+    L.unit_base = 0;
     return L;
 }
 
@@ -1331,79 +1339,107 @@ bool same_lists(const sr_tree* t, const sr_params* p, int64_t n_t, const int32_t
 }
 
 // Phase 1, growing the list buffers (and the per-wave frontier) until everything fits.
-int traverse(sr_tree* t, const sr_params* p, int64_t n_t, const int32_t* active, const double* a_old,
-             hipStream_t st)
+// Phase 1 launch: reserve lists and frontier for `want` entries / `fcap` frontier
+// entries per wave, then the traversal.  No host synchronisation.
+int traverse_launch(sr_tree* t, const sr_params* p, int64_t n_t, const int32_t* active, const double* a_old,
+                    int64_t want, int64_t fcap, hipStream_t st)
 {
     t->lkey.valid = false;
     const int64_t groups = (n_t + WAVE - 1) / WAVE;
-    int64_t want = 32 * n_t;
-    if (want < (int64_t)1 << 16) want = (int64_t)1 << 16;
-    int64_t fcap = t->cap_front > 4096 ? t->cap_front : 4096;
     // persistent traversal workgroups of TW waves, at most one per group
     int dev = 0, cus = 0;
     SR_HIP(hipGetDevice(&dev));
     SR_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     const int64_t wgs = groups < SR_TRAV_WG_PER_CU * (int64_t)cus ? groups : SR_TRAV_WG_PER_CU * (int64_t)cus;
+    // every wave of a group may start a unit chain; each wave may leave a
+    // reserved batch of chunks and units unused
+    const int64_t chunks = (want + 63) / 64 + TW * wgs * (TRAV_CHUNK_BATCH + 2);
+    int rc = sr_list_reserve(t, groups, chunks, TW * groups + chunks / UCH + TW * wgs * TRAV_UNIT_BATCH + 1);
+    if (rc) return rc;
+    if ((rc = sr_front_reserve(t, wgs * TW, fcap))) return rc;
+    hipLaunchKernelGGL(k_fill_i32w, g256(groups), dim3(256), 0, st, t->group_head, groups, -1);
+    hipLaunchKernelGGL(k_fill_i32w, g256(8), dim3(256), 0, st, t->list_counters, (int64_t)8, 0);
+    const WalkArgs a = make_args(t, p, n_t, a_old);
+    const ListArgs L = list_args(t);
+    FrontArgs F{};
+    F.buf = t->frontier;
+    F.cap = t->cap_front;
+    F.next_group = t->list_counters + 3;
+    F.overflow = t->list_counters + 2;
+    F.w32 = t->wrec32;
+    F.w64 = t->wrec64;
+    F.contig = active == nullptr;
+    F.groups = groups;
+    sr_timing_mark(SR_T_TRAVERSE, true, st);
+    const dim3 gw((unsigned)wgs), bw(TW * WAVE);
+    const bool rel = p->criterion == SR_OPEN_RELATIVE, mix = t->mixed_soft;
+    const int variant = (p->precision == SR_FP64 ? 4 : 0) + (rel ? 2 : 0) + (mix ? 1 : 0);
+    switch (variant) {
+    case 0: hipLaunchKernelGGL((k_traverse<false, false, false>), gw, bw, 0, st, a, L, F); break;
+    case 1: hipLaunchKernelGGL((k_traverse<false, false, true>), gw, bw, 0, st, a, L, F); break;
+    case 2: hipLaunchKernelGGL((k_traverse<false, true, false>), gw, bw, 0, st, a, L, F); break;
+    case 3: hipLaunchKernelGGL((k_traverse<false, true, true>), gw, bw, 0, st, a, L, F); break;
+    case 4: hipLaunchKernelGGL((k_traverse<true, false, false>), gw, bw, 0, st, a, L, F); break;
+    case 5: hipLaunchKernelGGL((k_traverse<true, false, true>), gw, bw, 0, st, a, L, F); break;
+    case 6: hipLaunchKernelGGL((k_traverse<true, true, false>), gw, bw, 0, st, a, L, F); break;
+    default: hipLaunchKernelGGL((k_traverse<true, true, true>), gw, bw, 0, st, a, L, F); break;
+    }
+    sr_timing_mark(SR_T_TRAVERSE, false, st);
+    SR_HIP(hipGetLastError());
+    return SR_OK;
+}
+
+// After a traversal: read its counters (host synchronisation).  On success record
+// the list sizes and the key that identifies these lists; `overflow` tells the
+// caller to grow and traverse again.
+int traverse_finish(sr_tree* t, const sr_params* p, int64_t n_t, const int32_t* active, const double* a_old,
+                    hipStream_t st, bool& overflow)
+{
+    int32_t cnt[8];
+    SR_HIP(hipMemcpyAsync(cnt, t->list_counters, sizeof(cnt), hipMemcpyDeviceToHost, st));
+    SR_HIP(hipStreamSynchronize(st));
+    overflow = cnt[2] != 0;
+    if (overflow) return SR_OK;
+    t->n_units = cnt[1];
+    t->n_chunks = cnt[0];
+    int64_t tests;
+    memcpy(&tests, cnt + 4, sizeof(tests));
+    t->n_tests = tests;
+    ListKey& k = t->lkey;
+    k.valid = true;
+    k.gen = t->build_gen;
+    k.dec64 = p->precision == SR_FP64;
+    k.G = p->G;
+    k.r_s = p->r_s;
+    k.r_cut = p->r_cut;
+    k.theta = p->theta;
+    k.alpha = p->alpha;
+    k.criterion = p->criterion;
+    k.n_t = n_t;
+    k.active = active;
+    k.a_old = a_old;
+    return SR_OK;
+}
+
+int64_t initial_want(int64_t n_t)
+{
+    const int64_t want = 32 * n_t;
+    return want < ((int64_t)1 << 16) ? ((int64_t)1 << 16) : want;
+}
+
+// Phase 1 with its check: traverse, growing the lists (and the per-wave frontier)
+// until everything fits.
+int traverse(sr_tree* t, const sr_params* p, int64_t n_t, const int32_t* active, const double* a_old,
+             hipStream_t st)
+{
+    int64_t want = initial_want(n_t);
+    int64_t fcap = t->cap_front > 4096 ? t->cap_front : 4096;
     for (int attempt = 0; attempt < 8; ++attempt) {
-        // every wave of a group may start a unit chain; each wave may leave a
-        // reserved batch of chunks and units unused
-        const int64_t chunks = (want + 63) / 64 + TW * wgs * (TRAV_CHUNK_BATCH + 2);
-        int rc = sr_list_reserve(t, groups, chunks, TW * groups + chunks / UCH + TW * wgs * TRAV_UNIT_BATCH + 1);
+        int rc = traverse_launch(t, p, n_t, active, a_old, want, fcap, st);
         if (rc) return rc;
-        if ((rc = sr_front_reserve(t, wgs * TW, fcap))) return rc;
-        hipLaunchKernelGGL(k_fill_i32w, g256(groups), dim3(256), 0, st, t->group_head, groups, -1);
-        hipLaunchKernelGGL(k_fill_i32w, g256(8), dim3(256), 0, st, t->list_counters, (int64_t)8, 0);
-        const WalkArgs a = make_args(t, p, n_t, a_old);
-        const ListArgs L = list_args(t);
-        FrontArgs F{};
-        F.buf = t->frontier;
-        F.cap = t->cap_front;
-        F.next_group = t->list_counters + 3;
-        F.overflow = t->list_counters + 2;
-        F.w32 = t->wrec32;
-        F.w64 = t->wrec64;
-        F.contig = active == nullptr;
-        F.groups = groups;
-        sr_timing_mark(SR_T_TRAVERSE, true, st);
-        const dim3 gw((unsigned)wgs), bw(TW * WAVE);
-        const bool rel = p->criterion == SR_OPEN_RELATIVE, mix = t->mixed_soft;
-        const int variant = (p->precision == SR_FP64 ? 4 : 0) + (rel ? 2 : 0) + (mix ? 1 : 0);
-        switch (variant) {
-        case 0: hipLaunchKernelGGL((k_traverse<false, false, false>), gw, bw, 0, st, a, L, F); break;
-        case 1: hipLaunchKernelGGL((k_traverse<false, false, true>), gw, bw, 0, st, a, L, F); break;
-        case 2: hipLaunchKernelGGL((k_traverse<false, true, false>), gw, bw, 0, st, a, L, F); break;
-        case 3: hipLaunchKernelGGL((k_traverse<false, true, true>), gw, bw, 0, st, a, L, F); break;
-        case 4: hipLaunchKernelGGL((k_traverse<true, false, false>), gw, bw, 0, st, a, L, F); break;
-        case 5: hipLaunchKernelGGL((k_traverse<true, false, true>), gw, bw, 0, st, a, L, F); break;
-        case 6: hipLaunchKernelGGL((k_traverse<true, true, false>), gw, bw, 0, st, a, L, F); break;
-        default: hipLaunchKernelGGL((k_traverse<true, true, true>), gw, bw, 0, st, a, L, F); break;
-        }
-        sr_timing_mark(SR_T_TRAVERSE, false, st);
-        SR_HIP(hipGetLastError());
-        int32_t cnt[8];
-        SR_HIP(hipMemcpyAsync(cnt, t->list_counters, sizeof(cnt), hipMemcpyDeviceToHost, st));
-        SR_HIP(hipStreamSynchronize(st));
-        if (!cnt[2]) {
-            t->n_units = cnt[1];
-            t->n_chunks = cnt[0];
-            int64_t tests;
-            memcpy(&tests, cnt + 4, sizeof(tests));
-            t->n_tests = tests;
-            ListKey& k = t->lkey;
-            k.valid = true;
-            k.gen = t->build_gen;
-            k.dec64 = p->precision == SR_FP64;
-            k.G = p->G;
-            k.r_s = p->r_s;
-            k.r_cut = p->r_cut;
-            k.theta = p->theta;
-            k.alpha = p->alpha;
-            k.criterion = p->criterion;
-            k.n_t = n_t;
-            k.active = active;
-            k.a_old = a_old;
-            return SR_OK;
-        }
+        bool overflow = false;
+        if ((rc = traverse_finish(t, p, n_t, active, a_old, st, overflow))) return rc;
+        if (!overflow) return SR_OK;
         // something did not fit: grow both (a chunk overflow and a frontier overflow share the flag)
         want = 2 * t->cap_chunks * 64;
         fcap = 2 * t->cap_front;
@@ -1411,14 +1447,17 @@ int traverse(sr_tree* t, const sr_params* p, int64_t n_t, const int32_t* active,
     return sr_fail(SR_ENOMEM, "interaction lists did not fit after repeated growth");
 }
 
+// Phases 2 and 3: evaluate units [u0, u0 + nu) (units past the traversal's
+// count exit at once), then reduce every group.
 template <bool ADJ>
-int eval_and_reduce(sr_tree* t, const sr_params* p, const WalkArgs& a, hipStream_t st)
+int eval_and_reduce(sr_tree* t, const sr_params* p, const WalkArgs& a, int64_t u0, int64_t nu, hipStream_t st)
 {
     const int64_t groups = (a.n_t + WAVE - 1) / WAVE;
-    const ListArgs L = list_args(t);
-    const dim3 gu((unsigned)(t->n_units > 0 ? t->n_units : 1)), gg((unsigned)groups);
+    ListArgs L = list_args(t);
+    L.unit_base = (int32_t)u0;
+    const dim3 gu((unsigned)(nu > 0 ? nu : 1)), gg((unsigned)groups);
     const int ph_eval = ADJ ? SR_T_ADJ_EVAL : SR_T_EVAL, ph_red = ADJ ? SR_T_ADJ_REDUCE : SR_T_REDUCE;
-    if (t->n_units > 0) {
+    if (nu > 0) {
         sr_timing_mark(ph_eval, true, st);
         switch (p->precision) {
         case SR_FP64: hipLaunchKernelGGL((k_eval64<ADJ>), gu, dim3(WAVE), 0, st, a, L, t->partials); break;
@@ -1491,11 +1530,32 @@ int sr_walk_forward(sr_tree* t, const sr_params* p, int64_t n_t, const int32_t* 
         t->n_units = 0;
         t->lkey.valid = false;
         hipLaunchKernelGGL(k_fill_i32w, g256(groups), dim3(256), 0, st, t->group_head, groups, -1);
-        return eval_and_reduce<false>(t, p, a, st);
+        return eval_and_reduce<false>(t, p, a, 0, 0, st);
     }
-    int rc = traverse(t, p, n_t, active, a_old, st);
-    if (rc) return rc;
-    return eval_and_reduce<false>(t, p, a, st);
+    // traversal, evaluation and reduction go to the stream back to back, the
+    // evaluation sized by the previous unit count; the counters are checked once
+    // at the end (units beyond the estimate are evaluated then, an overflow
+    // grows the lists and starts again)
+    int64_t want = initial_want(n_t);
+    int64_t fcap = t->cap_front > 4096 ? t->cap_front : 4096;
+    for (int attempt = 0; attempt < 8; ++attempt) {
+        int rc = traverse_launch(t, p, n_t, active, a_old, want, fcap, st);
+        if (rc) return rc;
+        const int64_t guess = t->unit_hint > 0 && t->unit_hint < t->cap_units ? t->unit_hint : t->cap_units;
+        if ((rc = eval_and_reduce<false>(t, p, a, 0, guess, st))) return rc;
+        bool overflow = false;
+        if ((rc = traverse_finish(t, p, n_t, active, a_old, st, overflow))) return rc;
+        if (!overflow) {
+            if (t->n_units > guess) {
+                if ((rc = eval_and_reduce<false>(t, p, a, guess, t->n_units - guess, st))) return rc;
+            }
+            t->unit_hint = t->n_units + t->n_units / 8 + 64;
+            return SR_OK;
+        }
+        want = 2 * t->cap_chunks * 64;
+        fcap = 2 * t->cap_front;
+    }
+    return sr_fail(SR_ENOMEM, "interaction lists did not fit after repeated growth");
 }
 
 int sr_walk_adjoint(sr_tree* t, const sr_params* p, int64_t n_t, const int32_t* active, const double* a_old,
@@ -1516,7 +1576,7 @@ int sr_walk_adjoint(sr_tree* t, const sr_params* p, int64_t n_t, const int32_t* 
         a.pbar = t->pbar;
         a.tbar = t->tbar;
         a.nbar = t->nbar;
-        int rc = eval_and_reduce<true>(t, p, a, st);
+        int rc = eval_and_reduce<true>(t, p, a, 0, t->n_units, st);
         if (rc) return rc;
     }
     double sx = 1.0, sm = 1.0;
