@@ -237,10 +237,11 @@ template <bool DEC64>
 struct NodeRec;
 template <>
 struct NodeRec<false> {
+    // a Barnes-Hut decision reads the first 48 bytes only
     uint32_t cX, cY, cZ, tin;      // cube centre (ticks), 0.6 side rounded down (ticks)
     uint32_t X, Y, Z, l2;          // centre of mass (ticks), side^2 (float bits, ticks^2)
-    uint32_t half, M, hx, mixed;   // half side, mass, h_max (float bits), mixed softening
-    uint32_t rlo, rhi, id, meta;   // reach mask, node id, child count or META_BUCKET
+    uint32_t half, rlo, rhi, M;    // half side (float bits), reach mask, mass (float bits)
+    uint32_t hx, mixed, id, meta;  // h_max (float bits), mixed softening, node id, child count or META_BUCKET
 };
 template <>
 struct NodeRec<true> {
@@ -282,6 +283,10 @@ __device__ inline uint32_t wave_sum63_u32(uint32_t x)
 #endif
 
 constexpr int TW = SR_TRAV_WAVES;
+#ifndef SR_DEC_ILP
+#define SR_DEC_ILP 2
+#endif
+constexpr int DEC_ILP = SR_DEC_ILP;   // decisions interleaved in the traversal
 #ifndef SR_CHUNK_BATCH
 #define SR_CHUNK_BATCH 16
 #endif
@@ -563,10 +568,13 @@ __global__ __launch_bounds__(TW * WAVE) __attribute__((amdgpu_waves_per_eu(4, 8)
                 wave_sync();
 
                 // ---- decisions: all lanes against node j ----
+                // The masks come from one ballot per elementary test (each a single
+                // compare into a lane mask) and are combined on the scalar unit.
                 auto decide = [&](uint32_t j) __attribute__((always_inline)) -> Dec {
                     const NodeRec<DEC64> nr = rec[j];
-                    const uint64_t reach = ((uint64_t)nr.rhi << 32) | nr.rlo;
-                    bool keep, open, near;
+                    const uint64_t reach = ((uint64_t)__builtin_amdgcn_readfirstlane(nr.rhi) << 32) |
+                                           (uint32_t)__builtin_amdgcn_readfirstlane(nr.rlo);
+                    uint64_t keep_m, open_m, near_m;
                     if constexpr (DEC64) {
                         const double l = nr.l;
                         const double dcx = min_image(nr.cx - x64, a.box);
@@ -575,53 +583,59 @@ __global__ __launch_bounds__(TW * WAVE) __attribute__((amdgpu_waves_per_eu(4, 8)
                         const double tx = fmax(fabs(dcx) - 0.5 * l, 0.0);
                         const double ty = fmax(fabs(dcy) - 0.5 * l, 0.0);
                         const double tz = fmax(fabs(dcz) - 0.5 * l, 0.0);
-                        keep = !((tx * tx + ty * ty) + tz * tz > a.rc2 * (1.0 + 1e-6));
-                        const bool inside = fabs(dcx) < 0.6 * l && fabs(dcy) < 0.6 * l && fabs(dcz) < 0.6 * l;
+                        keep_m = __ballot(!((tx * tx + ty * ty) + tz * tz > a.rc2 * (1.0 + 1e-6)));
+                        const double am = fmax(fabs(dcx), fmax(fabs(dcy), fabs(dcz)));
+                        const uint64_t inside_m = __ballot(am < 0.6 * l);
                         const double dx = min_image(nr.X - x64, a.box);
                         const double dy = min_image(nr.Y - y64, a.box);
                         const double dz = min_image(nr.Z - z64, a.box);
                         const double r2 = (dx * dx + dy * dy) + dz * dz;
-                        open = inside | (l * l > a.theta2 * r2);
-                        if constexpr (REL) open = open || (a.G * nr.M) * (l * l) > (a.alpha * aold) * (r2 * r2);
-                        if constexpr (MIXED) open = open || (nr.hn != nr.hx && r2 < nr.hx * nr.hx);
-                        near = r2 < a.rc2;
+                        open_m = inside_m | __ballot(l * l > a.theta2 * r2);
+                        if constexpr (REL) open_m |= __ballot((a.G * nr.M) * (l * l) > (a.alpha * aold) * (r2 * r2));
+                        if constexpr (MIXED)
+                            if (__builtin_amdgcn_readfirstlane(nr.hn != nr.hx ? 1 : 0))
+                                open_m |= __ballot(r2 < nr.hx * nr.hx);
+                        near_m = __ballot(r2 < a.rc2);
                     } else {
                         const uint32_t bx = (uint32_t)abs((int32_t)(nr.cX - X));
                         const uint32_t by = (uint32_t)abs((int32_t)(nr.cY - Y));
                         const uint32_t bz = (uint32_t)abs((int32_t)(nr.cZ - Z));
                         const uint32_t bm = max(bx, max(by, bz));
                         // prune (work only): the cube lies beyond r_cut along some axis
-                        keep = !((float)bm - __uint_as_float(nr.half) > a.rct);
-                        const bool inside = bm <= nr.tin;
+                        keep_m = __ballot(!((float)bm - __uint_as_float(nr.half) > a.rct));
+                        const uint64_t inside_m = __ballot(bm <= nr.tin);
                         const float dx = (float)(int32_t)(nr.X - X);
                         const float dy = (float)(int32_t)(nr.Y - Y);
                         const float dz = (float)(int32_t)(nr.Z - Z);
                         const float r2 = r2_ticks(dx, dy, dz);
                         const float l2 = __uint_as_float(nr.l2);
-                        open = inside | (l2 > a.theta2f * r2);
+                        open_m = inside_m | __ballot(l2 > a.theta2f * r2);
                         if constexpr (REL) {
                             const double r2d = (double)r2;
-                            open = open || (a.G * (double)__uint_as_float(nr.M)) * (double)l2 > atau * (r2d * r2d);
+                            open_m |= __ballot((a.G * (double)__uint_as_float(nr.M)) * (double)l2 > atau * (r2d * r2d));
                         }
                         if constexpr (MIXED) {
                             const float hx = __uint_as_float(nr.hx);
-                            open = open || (nr.mixed && r2 < hx * hx);
+                            if (__builtin_amdgcn_readfirstlane(nr.mixed)) open_m |= __ballot(r2 < hx * hx);
                         }
-                        near = r2 < a.rc2t;
+                        near_m = __ballot(r2 < a.rc2t);
                     }
-                    const bool live = ((reach >> lane) & 1ull) && keep;
-                    return Dec{__ballot(live && open), __ballot(live && !open && near)};
+                    const uint64_t live = reach & keep_m;
+                    return Dec{live & open_m, live & ~open_m & near_m};
                 };
-                // lane j keeps the masks of node j; two decisions interleave
+                // lane j keeps the masks of node j; DEC_ILP independent decisions
+                // interleave (indices past the block repeat node j and are not kept)
                 uint64_t my_om = 0, my_am = 0;
-                for (uint32_t j = 0; j < cnt; j += 2) {
-                    const uint32_t j1 = j + 1 < cnt ? j + 1 : j;
-                    const Dec d0 = decide(j);
-                    const Dec d1 = decide(j1);
-                    my_om = (uint32_t)lane == j ? d0.om : my_om;
-                    my_am = (uint32_t)lane == j ? d0.am : my_am;
-                    my_om = (uint32_t)lane == j1 && j1 != j ? d1.om : my_om;
-                    my_am = (uint32_t)lane == j1 && j1 != j ? d1.am : my_am;
+                for (uint32_t j = 0; j < cnt; j += DEC_ILP) {
+                    Dec d[DEC_ILP];
+#pragma unroll
+                    for (int k = 0; k < DEC_ILP; ++k) d[k] = decide(j + k < cnt ? j + k : j);
+#pragma unroll
+                    for (int k = 0; k < DEC_ILP; ++k) {
+                        const bool mine = (uint32_t)lane == j + k && j + k < cnt;
+                        my_om = mine ? d[k].om : my_om;
+                        my_am = mine ? d[k].am : my_am;
+                    }
                 }
 
                 // ---- accepted nodes: one list entry each, in block order ----
@@ -904,7 +918,10 @@ __global__ __launch_bounds__(WAVE) void k_eval32(WalkArgs a, ListArgs L, char* _
                     sz = oct_sum(pz);
                     sm = oct_sum(K * wd);
                 }
-                if ((lane % QL) == QL - 1 && e < (uint32_t)WAVE) {
+                // (testing the sums before the branch keeps the butterfly's last step
+                // a fused DPP add; all-zero rows add nothing)
+                const bool nz = (sx != 0.0f) | (sy != 0.0f) | (sz != 0.0f) | (sm != 0.0f);
+                if ((lane % QL) == QL - 1 && e < (uint32_t)WAVE && nz) {
                     atomicAdd(&s_acc[0][e], sx);
                     atomicAdd(&s_acc[1][e], sy);
                     atomicAdd(&s_acc[2][e], sz);
@@ -1077,7 +1094,8 @@ __global__ __launch_bounds__(WAVE) void k_eval64(WalkArgs a, ListArgs L, char* _
                 const double sy = row_sum15_f64(vy);
                 const double sz = row_sum15_f64(vz);
                 const double sm = row_sum15_f64(vm);
-                if ((lane % QL) == QL - 1 && e < (uint32_t)WAVE) {
+                const bool nz = (sx != 0.0) | (sy != 0.0) | (sz != 0.0) | (sm != 0.0);
+                if ((lane % QL) == QL - 1 && e < (uint32_t)WAVE && nz) {
                     atomicAdd(&s_acc[0][e], sx);
                     atomicAdd(&s_acc[1][e], sy);
                     atomicAdd(&s_acc[2][e], sz);
