@@ -249,6 +249,33 @@ struct NodeRec<true> {
     uint32_t rlo, rhi, id, meta;
 };
 
+__device__ inline uint32_t wave_min_u32(uint32_t v)
+{
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o, WAVE));
+    return v;
+}
+__device__ inline uint32_t wave_max_u32(uint32_t v)
+{
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o, WAVE));
+    return v;
+}
+
+// Range of |c - x| (32-bit wrap-around differences) over x in [lo, hi]; false if
+// some difference in the range is not representable (the range crosses the
+// half-box point).
+__device__ inline bool axis_range(uint32_t c, uint32_t lo, uint32_t hi, int64_t& amin, int64_t& amax)
+{
+    const uint32_t mid = lo + ((hi - lo) >> 1);
+    const int64_t d0 = (int32_t)(c - mid);
+    const int64_t e0 = d0 - (int64_t)(hi - mid), e1 = d0 + (int64_t)(mid - lo);
+    if (e0 <= -((int64_t)1 << 31) || e1 >= ((int64_t)1 << 31) - 1) return false;
+    amin = e0 > 0 ? e0 : (e1 < 0 ? -e1 : 0);
+    amax = -e0 > e1 ? -e0 : e1;
+    return true;
+}
+
 // Sum of a uint32 over the 64 lanes (DPP, total in lane 63).
 __device__ inline uint32_t wave_sum63_u32(uint32_t x)
 {
@@ -376,6 +403,19 @@ __global__ __launch_bounds__(TW * WAVE) __attribute__((amdgpu_waves_per_eu(4, 8)
             }
         }
         const uint64_t active = __ballot(valid);
+        // bounding box of the group's targets (integer coordinates, FP32 decisions);
+        // a group wider than a quarter box on some axis is never classified as a whole
+        uint32_t bxlo = 0, bxhi = 0, bylo = 0, byhi = 0, bzlo = 0, bzhi = 0;
+        bool box_ok = false;
+        if constexpr (!DEC64) {
+            bxlo = wave_min_u32(valid ? X : 0xffffffffu);
+            bxhi = wave_max_u32(valid ? X : 0u);
+            bylo = wave_min_u32(valid ? Y : 0xffffffffu);
+            byhi = wave_max_u32(valid ? Y : 0u);
+            bzlo = wave_min_u32(valid ? Z : 0xffffffffu);
+            bzhi = wave_max_u32(valid ? Z : 0u);
+            box_ok = bxhi - bxlo < (1u << 30) && byhi - bylo < (1u << 30) && bzhi - bzlo < (1u << 30);
+        }
         if (wv == 0) {
             s_tgt[lane] = valid ? (uint32_t)s_i : 0xffffffffu;
             if (lane == 0) s_tgt[WAVE] = 0xffffffffu;
@@ -508,6 +548,8 @@ __global__ __launch_bounds__(TW * WAVE) __attribute__((amdgpu_waves_per_eu(4, 8)
                 const uint32_t cnt = (uint32_t)(e1 - b0 < WAVE ? e1 - b0 : WAVE);
                 // ---- stage the block's nodes ----
                 uint32_t fid = 0, fmeta = 0;
+                uint64_t fmask = 0;
+                int cls = 0;   // 0: decide per target, 1: pruned for all, 2: opened by all, 3: accepted by all
                 if ((uint32_t)lane < cnt) {
                     // entry e of the level lies in the region of the first wave whose
                     // cumulative count exceeds it
@@ -520,7 +562,7 @@ __global__ __launch_bounds__(TW * WAVE) __attribute__((amdgpu_waves_per_eu(4, 8)
                         r += past ? 1 : 0;
                     }
                     fid = rid(cur, r)[off];
-                    const uint64_t fmask = rmask(cur, r)[off];
+                    fmask = rmask(cur, r)[off];
                     tests += (uint32_t)__popcll(fmask);
                     const uint32_t nd = fid;
                     NodeRec<DEC64> nr;
@@ -564,6 +606,37 @@ __global__ __launch_bounds__(TW * WAVE) __attribute__((amdgpu_waves_per_eu(4, 8)
                     nr.id = nd;
                     nr.meta = fmeta;
                     rec[lane] = nr;
+                    // The node against the whole group: the per-target tests below are
+                    // monotone in the per-axis distances and rounding is monotone, so the
+                    // same operations on the extreme distances bound every target's
+                    // result.  A node whose outcome is the same for every target needs
+                    // no per-target decision.
+                    if constexpr (!DEC64) {
+                        int64_t c0, c1, c2, c3, c4, c5, p0, p1, p2, p3, p4, p5;
+                        if (box_ok && axis_range(nr.cX, bxlo, bxhi, c0, c1) && axis_range(nr.cY, bylo, byhi, c2, c3) &&
+                            axis_range(nr.cZ, bzlo, bzhi, c4, c5) && axis_range(nr.X, bxlo, bxhi, p0, p1) &&
+                            axis_range(nr.Y, bylo, byhi, p2, p3) && axis_range(nr.Z, bzlo, bzhi, p4, p5)) {
+                            const uint32_t bm_lo = (uint32_t)max(c0, max(c2, c4));
+                            const uint32_t bm_hi = (uint32_t)max(c1, max(c3, c5));
+                            const float half = __uint_as_float(nr.half), l2 = __uint_as_float(nr.l2);
+                            const bool prune_all = (float)bm_lo - half > a.rct;
+                            const bool keep_all = !((float)bm_hi - half > a.rct);
+                            const float r2_lo = r2_ticks((float)p0, (float)p2, (float)p4);
+                            const float r2_hi = r2_ticks((float)p1, (float)p3, (float)p5);
+                            const bool open_all = bm_hi <= nr.tin || l2 > a.theta2f * r2_hi;
+                            bool open_none = bm_lo > nr.tin && !(l2 > a.theta2f * r2_lo) && !REL;
+                            if constexpr (MIXED)
+                                open_none = open_none && !(nr.mixed && r2_lo < __uint_as_float(nr.hx) * __uint_as_float(nr.hx));
+                            const bool near_all = r2_hi < a.rc2t;
+                            if (prune_all) {
+                                cls = 1;
+                            } else if (keep_all && open_all) {
+                                cls = 2;
+                            } else if (keep_all && open_none && near_all) {
+                                cls = 3;
+                            }
+                        }
+                    }
                 }
                 wave_sync();
 
@@ -623,16 +696,26 @@ __global__ __launch_bounds__(TW * WAVE) __attribute__((amdgpu_waves_per_eu(4, 8)
                     const uint64_t live = reach & keep_m;
                     return Dec{live & open_m, live & ~open_m & near_m};
                 };
-                // lane j keeps the masks of node j; DEC_ILP independent decisions
-                // interleave (indices past the block repeat node j and are not kept)
-                uint64_t my_om = 0, my_am = 0;
-                for (uint32_t j = 0; j < cnt; j += DEC_ILP) {
-                    Dec d[DEC_ILP];
-#pragma unroll
-                    for (int k = 0; k < DEC_ILP; ++k) d[k] = decide(j + k < cnt ? j + k : j);
+                // lane j keeps the masks of node j: set at once for a node classified
+                // as a whole, else from the per-target decision; DEC_ILP independent
+                // decisions interleave (a missing one repeats the first and is not kept)
+                uint64_t my_om = cls == 2 ? fmask : 0ull, my_am = cls == 3 ? fmask : 0ull;
+                uint64_t todo = __ballot((uint32_t)lane < cnt && cls == 0);
+                while (todo) {
+                    uint32_t jj[DEC_ILP];
+                    bool use[DEC_ILP];
 #pragma unroll
                     for (int k = 0; k < DEC_ILP; ++k) {
-                        const bool mine = (uint32_t)lane == j + k && j + k < cnt;
+                        use[k] = todo != 0;
+                        jj[k] = use[k] ? (uint32_t)__builtin_ctzll(todo) : jj[0];
+                        todo &= todo - 1;
+                    }
+                    Dec d[DEC_ILP];
+#pragma unroll
+                    for (int k = 0; k < DEC_ILP; ++k) d[k] = decide(jj[k]);
+#pragma unroll
+                    for (int k = 0; k < DEC_ILP; ++k) {
+                        const bool mine = use[k] && (uint32_t)lane == jj[k];
                         my_om = mine ? d[k].om : my_om;
                         my_am = mine ? d[k].am : my_am;
                     }
