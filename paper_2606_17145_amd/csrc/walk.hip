@@ -821,42 +821,61 @@ __global__ __launch_bounds__(TW * WAVE) __attribute__((amdgpu_waves_per_eu(4, 8)
 // per-unit partial results: acc_t[3][64] then int32[2][64] (forward) or acc_t[3][64] (adjoint)
 constexpr int PARTIAL_BYTES = 64 * (3 * 8 + 2 * 4);
 
-// Sum over each row of 16 lanes by a rotation butterfly (DPP row_ror 1, 2, 4,
-// 8): every lane of row k ends with row k's total.
-__device__ inline float row_sum15(float x)
-{
-    float v = x + dpp_f32<0x121, 0xf, 0xf>(x);
-    v = v + dpp_f32<0x122, 0xf, 0xf>(v);
-    v = v + dpp_f32<0x124, 0xf, 0xf>(v);
-    v = v + dpp_f32<0x128, 0xf, 0xf>(v);
-    return v;
-}
-
-// Lanes (targets) per stream of the FP32 evaluation: 8 for the forward, 16 for
-// the adjoint (whose per-stream source sums are DPP row operations).
+// Lanes (targets) per stream of the FP32 evaluation, forward and adjoint.
+#ifndef SR_QL_ADJ
+#define SR_QL_ADJ 16
+#endif
 constexpr int QL_FWD = 8;
-constexpr int QL_ADJ = 16;
+constexpr int QL_ADJ = SR_QL_ADJ;
+static_assert(QL_ADJ == 8 || QL_ADJ == 16, "stream width");
 
-// Sum over each group of 8 lanes (DPP half-row mirror, then quad swaps): every
-// lane of the group ends with the group's total.
-__device__ inline float oct_sum(float x)
+// Sums four quantities over each stream of QL lanes at once by a transposing
+// butterfly: at each exchange a lane keeps half of what it holds and sends the
+// other half to its partner, so the four totals cost 11 adds and selects for 16
+// lanes (10 for 8) instead of 16 (12) adds.  Afterwards lane l holds the stream
+// total of quantity (l mod QL) / (QL/4) (0 x, 1 y, 2 z, 3 m).  Partners: for
+// 16-lane rows the row mirror (l^15), then the half-row mirror (l^7), then the
+// quad swaps (l^1, l^2); for 8-lane groups the half-row mirror and the quad
+// swaps.  Needs the full wave active.
+template <int QL>
+__device__ inline float stream_sum4(float x, float y, float z, float m, int lane)
 {
-    float v = x + dpp_f32<0x141, 0xf, 0xf>(x);
-    v = v + dpp_f32<0x4e, 0xf, 0xf>(v);
-    v = v + dpp_f32<0xb1, 0xf, 0xf>(v);
-    return v;
+    if constexpr (QL == 16) {
+        const bool b3 = lane & 8, b2 = lane & 4;
+        float k0 = b3 ? z : x, k1 = b3 ? m : y;
+        const float s0 = b3 ? x : z, s1 = b3 ? y : m;
+        k0 += dpp_f32<0x140, 0xf, 0xf>(s0);
+        k1 += dpp_f32<0x140, 0xf, 0xf>(s1);
+        float k = b2 ? k1 : k0;
+        const float s = b2 ? k0 : k1;
+        k += dpp_f32<0x141, 0xf, 0xf>(s);
+        k += dpp_f32<0xb1, 0xf, 0xf>(k);
+        k += dpp_f32<0x4e, 0xf, 0xf>(k);
+        return k;
+    } else {
+        const bool b2 = lane & 4, b1 = lane & 2;
+        float k0 = b2 ? z : x, k1 = b2 ? m : y;
+        const float s0 = b2 ? x : z, s1 = b2 ? y : m;
+        k0 += dpp_f32<0x141, 0xf, 0xf>(s0);
+        k1 += dpp_f32<0x141, 0xf, 0xf>(s1);
+        float k = b1 ? k1 : k0;
+        const float s = b1 ? k0 : k1;
+        k += dpp_f32<0x4e, 0xf, 0xf>(s);
+        k += dpp_f32<0xb1, 0xf, 0xf>(k);
+        return k;
+    }
 }
 
-// FP32 evaluation of one unit, packed by quarters.  A quarter is a row of 16
-// lanes (16 Morton-consecutive targets).  For each chunk the entries whose mask
-// touches quarter k form quarter k's stream; step s evaluates entry
-// stream_k[s] on the lanes of quarter k, for all four quarters at once, so a
-// chunk takes max_k |stream_k| steps instead of one step per entry.  Source
-// records are staged in LDS, 32 bytes per entry; each quarter reads its own
-// entry (a broadcast within the row).  Slots past the end of a stream name
-// entry 64, whose mask is empty.  The adjoint's source terms are summed per row
-// with DPP, collected per entry in LDS, and added to the source with one FP64
-// atomic per (entry, component) after the chunk.
+// FP32 evaluation of one unit, packed into streams.  A stream is a group of QL
+// lanes (QL Morton-consecutive targets).  For each chunk the entries whose mask
+// touches group k form stream k; step s evaluates entry stream_k[s] on the lanes
+// of group k, for all groups at once, so a chunk takes max_k |stream_k| steps
+// instead of one step per entry.  Source records are staged in LDS, 32 bytes
+// per entry; each group reads its own entry (a broadcast within the group).
+// Slots past the end of a stream name entry 64, whose mask is empty.  The
+// adjoint's source terms are summed per stream with DPP (stream_sum4),
+// collected per entry in LDS, and added to the source with one FP64 atomic per
+// (entry, component) after the chunk.
 struct SrcLds {
     uint32_t X, Y, Z, m;        // integer position, mass bits (mass scaled by 2^64)
     uint32_t h, inc, mlo, mhi;  // support h bits, count increment, mask of lanes 0-31 / 32-63
@@ -872,7 +891,7 @@ __global__ __launch_bounds__(WAVE) void k_eval32(WalkArgs a, ListArgs L, char* _
     __shared__ SrcLds s_ent[WAVE + 1];
     __shared__ uint32_t s_src[WAVE];
     __shared__ uint8_t s_stream[NQ][WAVE];
-    __shared__ float s_acc[ADJ ? 4 : 1][WAVE];   // adjoint: source terms of each entry
+    __shared__ float s_acc[ADJ ? 4 : 1][WAVE + 1];   // adjoint: source terms of each entry
     const int lane = threadIdx.x;
     const int quarter = lane / QL;
     const uint32_t bit = 1u << (lane & 31);
@@ -988,28 +1007,10 @@ __global__ __launch_bounds__(WAVE) void k_eval32(WalkArgs a, ListArgs L, char* _
                 tbx -= (acc_t)px;
                 tby -= (acc_t)py;
                 tbz -= (acc_t)pz;
-                // source terms: sums over each stream's lanes, collected per entry
-                float sx, sy, sz, sm;
-                if constexpr (QL == 16) {
-                    sx = row_sum15(px);
-                    sy = row_sum15(py);
-                    sz = row_sum15(pz);
-                    sm = row_sum15(K * wd);
-                } else {
-                    sx = oct_sum(px);
-                    sy = oct_sum(py);
-                    sz = oct_sum(pz);
-                    sm = oct_sum(K * wd);
-                }
-                // (testing the sums before the branch keeps the butterfly's last step
-                // a fused DPP add; all-zero rows add nothing)
-                const bool nz = (sx != 0.0f) | (sy != 0.0f) | (sz != 0.0f) | (sm != 0.0f);
-                if ((lane % QL) == QL - 1 && e < (uint32_t)WAVE && nz) {
-                    atomicAdd(&s_acc[0][e], sx);
-                    atomicAdd(&s_acc[1][e], sy);
-                    atomicAdd(&s_acc[2][e], sz);
-                    atomicAdd(&s_acc[3][e], sm);
-                }
+                // source terms: the stream's totals, one quantity per lane, collected per
+                // entry (the padding entry 64 has a column of its own that is never read)
+                const float ssum = stream_sum4<QL>(px, py, pz, K * wd, lane);
+                if (lane % (QL / 4) == 0) atomicAdd(&s_acc[(lane % QL) / (QL / 4)][e], ssum);
             }
         }
         wave_sync();
