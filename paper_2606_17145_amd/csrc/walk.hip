@@ -203,6 +203,7 @@ struct ListArgs {
     int64_t cap_chunks;
     int64_t cap_units;
     int32_t unit_base;      // evaluation: first unit of this launch
+    int32_t unit_end;       // evaluation: one past the last unit of this launch
 };
 
 // open and accept masks of one decision
@@ -821,6 +822,13 @@ __global__ __launch_bounds__(TW * WAVE) __attribute__((amdgpu_waves_per_eu(4, 8)
 // per-unit partial results: acc_t[3][64] then int32[2][64] (forward) or acc_t[3][64] (adjoint)
 constexpr int PARTIAL_BYTES = 64 * (3 * 8 + 2 * 4);
 
+// Waves per workgroup of the FP32 evaluation, one unit per wave (2 and 4 were
+// measured no faster than 1 on the clustered 262,144-particle step).
+#ifndef SR_EVAL_WAVES
+#define SR_EVAL_WAVES 1
+#endif
+constexpr int EVAL_WAVES = SR_EVAL_WAVES;
+
 // Lanes (targets) per stream of the FP32 evaluation, forward and adjoint.
 #ifndef SR_QL_ADJ
 #define SR_QL_ADJ 16
@@ -882,24 +890,32 @@ struct SrcLds {
 };
 
 template <int PREC, bool ADJ>
-__global__ __launch_bounds__(WAVE) void k_eval32(WalkArgs a, ListArgs L, char* __restrict__ partials)
+__global__ __launch_bounds__(EVAL_WAVES * WAVE) void k_eval32(WalkArgs a, ListArgs L, char* __restrict__ partials)
 {
     using acc_t = typename std::conditional<PREC == PR32, float, double>::type;
     static_assert(PREC != PR64, "FP32 kernel");
     constexpr int QL = ADJ ? QL_ADJ : QL_FWD;
     constexpr int NQ = WAVE / QL;
-    __shared__ SrcLds s_ent[WAVE + 1];
-    __shared__ uint32_t s_src[WAVE];
-    __shared__ uint8_t s_stream[NQ][WAVE];
-    __shared__ float s_acc[ADJ ? 4 : 1][WAVE + 1];   // adjoint: source terms of each entry
-    const int lane = threadIdx.x;
+    // every wave of the workgroup evaluates a unit of its own with LDS of its own
+    __shared__ SrcLds s_ent_w[EVAL_WAVES][WAVE + 1];
+    __shared__ uint32_t s_src_w[EVAL_WAVES][WAVE];
+    __shared__ uint8_t s_stream_w[EVAL_WAVES][NQ][WAVE];
+    // adjoint: the four source terms of each (stream, entry) pair of the chunk; a stream
+    // visits an entry at most once per chunk, so every slot is written at most once
+    __shared__ float4 s_part_w[EVAL_WAVES][ADJ ? NQ : 1][ADJ ? WAVE + 1 : 1];
+    const int wv = threadIdx.x / WAVE;
+    auto& s_ent = s_ent_w[wv];
+    auto& s_src = s_src_w[wv];
+    auto& s_stream = s_stream_w[wv];
+    auto& s_part = s_part_w[wv];
+    const int lane = threadIdx.x % WAVE;
     const int quarter = lane / QL;
     const uint32_t bit = 1u << (lane & 31);
     const bool hi_half = lane >= 32;
     // units past the traversal's count, or the lists of a traversal that overflowed, are
     // not read (the launch may be sized before the count is known on the host)
-    const int32_t u = L.unit_base + (int32_t)blockIdx.x;
-    if (u >= L.counters[1] || L.counters[2] != 0) return;
+    const int32_t u = L.unit_base + (int32_t)(blockIdx.x * EVAL_WAVES + wv);
+    if (u >= L.unit_end || u >= L.counters[1] || L.counters[2] != 0) return;
     if (L.unit_nch[u] == 0) return;   // a unit reserved but not used (its partials are never read)
     const int64_t g = L.unit_group[u];
     const int64_t t = g * WAVE + lane;
@@ -939,10 +955,6 @@ __global__ __launch_bounds__(WAVE) void k_eval32(WalkArgs a, ListArgs L, char* _
             s_ent[lane] = SrcLds{r.X, r.Y, r.Z, __float_as_uint(r.m * TWO64_F), __float_as_uint(hs),
                                  isp ? 1u : 0x10000u, (uint32_t)lmask, (uint32_t)(lmask >> 32)};
             s_src[lane] = lsrc;
-        }
-        if constexpr (ADJ) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) s_acc[k][lane] = 0.0f;
         }
         // the streams (one per group of QL lanes), each in entry order, padded with entry 64
         const uint64_t below = (1ull << lane) - 1ull;
@@ -1007,10 +1019,11 @@ __global__ __launch_bounds__(WAVE) void k_eval32(WalkArgs a, ListArgs L, char* _
                 tbx -= (acc_t)px;
                 tby -= (acc_t)py;
                 tbz -= (acc_t)pz;
-                // source terms: the stream's totals, one quantity per lane, collected per
-                // entry (the padding entry 64 has a column of its own that is never read)
+                // source terms: the stream's totals, one quantity per lane, stored in the
+                // (stream, entry) slot (the padding entry 64 has a slot that is never read);
+                // the QL/4 lanes that hold one quantity store the same value
                 const float ssum = stream_sum4<QL>(px, py, pz, K * wd, lane);
-                if (lane % (QL / 4) == 0) atomicAdd(&s_acc[(lane % QL) / (QL / 4)][e], ssum);
+                reinterpret_cast<float*>(&s_part[quarter][e])[(lane % QL) / (QL / 4)] = ssum;
             }
         }
         wave_sync();
@@ -1019,11 +1032,22 @@ __global__ __launch_bounds__(WAVE) void k_eval32(WalkArgs a, ListArgs L, char* _
                 const uint32_t sid = s_src[lane];
                 double* dst = (sid & ITEM_PARTICLE) ? a.pbar + 4 * (int64_t)(sid & ~ITEM_PARTICLE)
                                                     : a.nbar + 4 * (int64_t)sid;
+                // the streams that visited this entry, in stream order
+                float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const float v = s_acc[k][lane];
-                    if (v != 0.0f) unsafeAtomicAdd(dst + k, (double)v);
+                for (int k = 0; k < NQ; ++k) {
+                    if (((lmask >> (QL * k)) & QMASK) != 0) {
+                        const float4 pk = s_part[k][lane];
+                        v.x += pk.x;
+                        v.y += pk.y;
+                        v.z += pk.z;
+                        v.w += pk.w;
+                    }
                 }
+                if (v.x != 0.0f) unsafeAtomicAdd(dst + 0, (double)v.x);
+                if (v.y != 0.0f) unsafeAtomicAdd(dst + 1, (double)v.y);
+                if (v.z != 0.0f) unsafeAtomicAdd(dst + 2, (double)v.z);
+                if (v.w != 0.0f) unsafeAtomicAdd(dst + 3, (double)v.w);
             }
             wave_sync();
         }
@@ -1078,7 +1102,7 @@ __global__ __launch_bounds__(WAVE) void k_eval64(WalkArgs a, ListArgs L, char* _
     // units past the traversal's count, or the lists of a traversal that overflowed, are
     // not read (the launch may be sized before the count is known on the host)
     const int32_t u = L.unit_base + (int32_t)blockIdx.x;
-    if (u >= L.counters[1] || L.counters[2] != 0) return;
+    if (u >= L.unit_end || u >= L.counters[1] || L.counters[2] != 0) return;
     if (L.unit_nch[u] == 0) return;   // a unit reserved but not used (its partials are never read)
     const int64_t g = L.unit_group[u];
     const int64_t t = g * WAVE + lane;
@@ -1428,6 +1452,7 @@ ListArgs list_args(const sr_tree* t)
     L.cap_chunks = t->cap_chunks;
     L.cap_units = t->cap_units;
     L.unit_base = 0;
+    L.unit_end = 0;
     return L;
 }
 
@@ -1557,14 +1582,20 @@ int eval_and_reduce(sr_tree* t, const sr_params* p, const WalkArgs& a, int64_t u
     const int64_t groups = (a.n_t + WAVE - 1) / WAVE;
     ListArgs L = list_args(t);
     L.unit_base = (int32_t)u0;
-    const dim3 gu((unsigned)(nu > 0 ? nu : 1)), gg((unsigned)groups);
+    L.unit_end = (int32_t)(u0 + nu);
+    const dim3 gu((unsigned)(nu > 0 ? nu : 1)), gu32((unsigned)(nu > 0 ? (nu + EVAL_WAVES - 1) / EVAL_WAVES : 1)),
+        gg((unsigned)groups);
     const int ph_eval = ADJ ? SR_T_ADJ_EVAL : SR_T_EVAL, ph_red = ADJ ? SR_T_ADJ_REDUCE : SR_T_REDUCE;
     if (nu > 0) {
         sr_timing_mark(ph_eval, true, st);
         switch (p->precision) {
         case SR_FP64: hipLaunchKernelGGL((k_eval64<ADJ>), gu, dim3(WAVE), 0, st, a, L, t->partials); break;
-        case SR_FP32: hipLaunchKernelGGL((k_eval32<PR32, ADJ>), gu, dim3(WAVE), 0, st, a, L, t->partials); break;
-        default: hipLaunchKernelGGL((k_eval32<PR32A, ADJ>), gu, dim3(WAVE), 0, st, a, L, t->partials); break;
+        case SR_FP32:
+            hipLaunchKernelGGL((k_eval32<PR32, ADJ>), gu32, dim3(EVAL_WAVES * WAVE), 0, st, a, L, t->partials);
+            break;
+        default:
+            hipLaunchKernelGGL((k_eval32<PR32A, ADJ>), gu32, dim3(EVAL_WAVES * WAVE), 0, st, a, L, t->partials);
+            break;
         }
         sr_timing_mark(ph_eval, false, st);
     }
