@@ -131,7 +131,7 @@ void free_workspace(sr_tree* t)
 int allocate_workspace(sr_tree* t, int64_t cap)
 {
     const int64_t nb_rs = (cap + 255) / 256;             // radix-sort tiles (at least 256 keys each)
-    const int64_t hist = 256 * nb_rs + 1;
+    const int64_t hist = 256 * nb_rs + 256 + 1;          // per-tile digit counts, then the digit totals
     const int64_t scan_tiles = (hist > cap + 1 ? hist : cap + 1) / 2048 + 2;
     const int64_t nodes = cap > 1 ? cap - 1 : 1;
     int rc = SR_OK;

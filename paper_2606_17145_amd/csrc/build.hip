@@ -244,18 +244,44 @@ __global__ void k_rs_hist(const uint64_t* __restrict__ hi, const uint64_t* __res
     hist[threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
 }
 
+// Per digit (one block each): exclusive scan, in place, of the digit's tile
+// counts (row d of the digit-major histogram), and the digit's total into
+// tot[d].  The scatter adds the digits' base offsets (the exclusive scan of tot)
+// itself, so a pass needs no device-wide scan.
+__global__ void k_rs_digit_scan(uint32_t* __restrict__ hist, int64_t nb, uint32_t* __restrict__ tot)
+{
+    uint32_t* row = hist + blockIdx.x * nb;
+    const int64_t per = (nb + TPB - 1) / TPB;
+    const int64_t b = threadIdx.x * per, e = b + per < nb ? b + per : nb;
+    uint32_t acc = 0;
+    for (int64_t i = b; i < e; ++i) acc += row[i];
+    uint32_t total;
+    uint32_t off = block_exclusive_scan(acc, &total);
+    for (int64_t i = b; i < e; ++i) {
+        const uint32_t v = row[i];
+        row[i] = off;
+        off += v;
+    }
+    if (threadIdx.x == 0) tot[blockIdx.x] = total;
+}
+
 // Stable scatter: within a tile, keys keep their order (rounds in order, waves
-// in order, lanes in order); tiles take their offsets from the digit-major scan.
+// in order, lanes in order); a tile's offset for digit d is the digit's base
+// (keys with a smaller digit) plus the keys of digit d in earlier tiles.
 template <int RS_ITEMS>
 __global__ void k_rs_scatter(const uint64_t* __restrict__ hi, const uint64_t* __restrict__ lo,
                              const uint32_t* __restrict__ idx, uint64_t* __restrict__ ohi,
                              uint64_t* __restrict__ olo, uint32_t* __restrict__ oidx, int64_t n,
-                             int pass, const uint32_t* __restrict__ offs, int64_t nb)
+                             int pass, const uint32_t* __restrict__ offs, int64_t nb,
+                             const uint32_t* __restrict__ tot)
 {
+    static_assert(TPB == 256, "one thread per digit");
     __shared__ uint32_t s_off[256];
     __shared__ uint32_t s_w[TPB / 64][256];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    s_off[threadIdx.x] = offs[threadIdx.x * nb + blockIdx.x];
+    uint32_t all;
+    const uint32_t dbase = block_exclusive_scan(tot[threadIdx.x], &all);
+    s_off[threadIdx.x] = dbase + offs[threadIdx.x * nb + blockIdx.x];
     const uint64_t lt = (1ull << lane) - 1ull;
     int64_t base = blockIdx.x * (int64_t)(TPB * RS_ITEMS);
     for (int r = 0; r < RS_ITEMS; ++r) {
@@ -550,7 +576,11 @@ __global__ void k_child_table(int64_t m, const Item* __restrict__ items, const i
 // folded left to right over the children in digit order without FMA, the
 // support range, the cube geometry and the FP32 record.  All children's data
 // are loaded before the fold.
-__global__ void k_moments(const int32_t* __restrict__ order, int64_t count, double box,
+// One node per thread in blocks of one wave: a depth holds 10^3 - 10^5 nodes and
+// each thread waits on two rounds of dependent loads, so small blocks spread a
+// depth over all CUs.
+constexpr int MOM_TPB = 64;
+__global__ __launch_bounds__(MOM_TPB) void k_moments(const int32_t* __restrict__ order, int64_t count, double box,
                           const int32_t* __restrict__ n_first, const int32_t* __restrict__ n_level,
                           const uint32_t* __restrict__ n_corner, const Rec64* __restrict__ r64,
                           const double* __restrict__ h64, Rec64* __restrict__ nrec64, double* __restrict__ nS,
@@ -560,7 +590,7 @@ __global__ void k_moments(const int32_t* __restrict__ order, int64_t count, doub
                           const int32_t* __restrict__ n_count, WalkRec32* __restrict__ w32,
                           WalkRec64* __restrict__ w64)
 {
-    int64_t t = blockIdx.x * (int64_t)TPB + threadIdx.x;
+    int64_t t = blockIdx.x * (int64_t)MOM_TPB + threadIdx.x;
     if (t >= count) return;
     const int32_t nd = order[t];
     const uint32_t mt = meta[nd];
@@ -733,17 +763,17 @@ int sr_build_device(sr_tree* t, const double* pos, const double* mass, const dou
             hipLaunchKernelGGL(k_rs_hist<4>, gb, tb, 0, st, t->khi[cur], t->klo[cur], n, pass, t->hist, nb);
         else
             hipLaunchKernelGGL(k_rs_hist<8>, gb, tb, 0, st, t->khi[cur], t->klo[cur], n, pass, t->hist, nb);
-        int rc = sr_scan_exclusive(t->hist, t->hist, 256 * nb, t->scan_tmp, st);
-        if (rc) return rc;
+        uint32_t* tot = t->hist + 256 * nb;
+        hipLaunchKernelGGL(k_rs_digit_scan, dim3(256), tb, 0, st, t->hist, nb, tot);
         if (items == 2)
             hipLaunchKernelGGL(k_rs_scatter<2>, gb, tb, 0, st, t->khi[cur], t->klo[cur], t->kidx[cur],
-                               t->khi[cur ^ 1], t->klo[cur ^ 1], t->kidx[cur ^ 1], n, pass, t->hist, nb);
+                               t->khi[cur ^ 1], t->klo[cur ^ 1], t->kidx[cur ^ 1], n, pass, t->hist, nb, tot);
         else if (items == 4)
             hipLaunchKernelGGL(k_rs_scatter<4>, gb, tb, 0, st, t->khi[cur], t->klo[cur], t->kidx[cur],
-                               t->khi[cur ^ 1], t->klo[cur ^ 1], t->kidx[cur ^ 1], n, pass, t->hist, nb);
+                               t->khi[cur ^ 1], t->klo[cur ^ 1], t->kidx[cur ^ 1], n, pass, t->hist, nb, tot);
         else
             hipLaunchKernelGGL(k_rs_scatter<8>, gb, tb, 0, st, t->khi[cur], t->klo[cur], t->kidx[cur],
-                               t->khi[cur ^ 1], t->klo[cur ^ 1], t->kidx[cur ^ 1], n, pass, t->hist, nb);
+                               t->khi[cur ^ 1], t->klo[cur ^ 1], t->kidx[cur ^ 1], n, pass, t->hist, nb, tot);
         cur ^= 1;
     }
     // 12 passes leave the sorted keys in buffer 0
@@ -806,7 +836,7 @@ int sr_build_device(sr_tree* t, const double* pos, const double* mass, const dou
     for (int d = t->max_depth; d >= 0; --d) {
         int64_t cnt = t->depth_hist[d];
         if (!cnt) continue;
-        hipLaunchKernelGGL(k_moments, grid_for(cnt), dim3(TPB), 0, st, t->depth_order + offs[d], cnt, box,
+        hipLaunchKernelGGL(k_moments, dim3((unsigned)cdiv(cnt, MOM_TPB)), dim3(MOM_TPB), 0, st, t->depth_order + offs[d], cnt, box,
                            t->n_first, t->n_level, t->n_corner, t->prec64, t->ph64, t->nrec64, t->nS, t->ngeo64,
                            t->nhmax, t->nhmin, t->nrec32, t->nhmax32, t->n_kids, t->n_meta, t->n_count,
                            t->wrec32, t->wrec64);
