@@ -465,7 +465,9 @@ __global__ void k_node_arrays(int64_t n, const int32_t* __restrict__ b_lo, const
     n_corner[3 * pre + 2] = (uint32_t)(q.Z & keep);
 }
 
-__global__ void k_node_depth(int64_t m, const int32_t* __restrict__ n_parent, const int32_t* __restrict__ n_first,
+// Launched for the N - 1 node bound; the node count m is read on the device.
+__global__ void k_node_depth(const int32_t* __restrict__ m_dev, const int32_t* __restrict__ n_parent,
+                             const int32_t* __restrict__ n_first,
                              const int32_t* __restrict__ n_count, const int32_t* __restrict__ base,
                              int32_t* __restrict__ n_depth, Item* __restrict__ items,
                              int32_t* __restrict__ status)
@@ -476,6 +478,7 @@ __global__ void k_node_depth(int64_t m, const int32_t* __restrict__ n_parent, co
     if (threadIdx.x < SR_MAX_DEPTH) h[threadIdx.x] = 0;
     if (threadIdx.x == 0) dmax = 0;
     __syncthreads();
+    const int64_t m = *m_dev;
     int64_t nd = blockIdx.x * (int64_t)TPB + threadIdx.x;
     if (nd < m) {
         int d = 0;
@@ -793,9 +796,15 @@ int sr_build_device(sr_tree* t, const double* pos, const double* mass, const dou
         hipLaunchKernelGGL(k_node_arrays, grid_for(n - 1), dim3(TPB), 0, st, n, t->b_lo, t->b_hi, t->b_lambda,
                            t->b_parent, t->b_pre, t->base, t->prec32, t->n_level, t->n_first, t->n_count,
                            t->n_parent, t->n_skip, t->n_corner);
-        // the node count is base[n]; read it back with the status words
+        // the node count is base[n]; it is read back with the status words, and the
+        // depth pass (sized for the N - 1 bound) reads it on the device
         SR_HIP(hipMemcpyAsync(t->status + ST_NODES, t->base + n, sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+        hipLaunchKernelGGL(k_node_depth, grid_for(n - 1), dim3(TPB), 0, st, t->status + ST_NODES, t->n_parent,
+                           t->n_first, t->n_count, t->base, t->n_depth, t->items, t->status);
     }
+    hipLaunchKernelGGL(k_particle_items, grid_for(n), dim3(TPB), 0, st, n, t->leaf_bparent, t->b_parent,
+                       t->b_pre, t->base, t->n_depth, t->pparent, t->items);
+    // the build's one synchronisation: input flags, node count, depth histogram
     int32_t hstat[ST_WORDS];
     SR_HIP(hipMemcpyAsync(hstat, t->status, sizeof(hstat), hipMemcpyDeviceToHost, st));
     SR_HIP(hipStreamSynchronize(st));
@@ -804,15 +813,6 @@ int sr_build_device(sr_tree* t, const double* pos, const double* mass, const dou
     t->mixed_soft = (hstat[ST_FLAGS] & 2) != 0;
     const int64_t m = n > 1 ? hstat[ST_NODES] : 0;
     t->n_nodes = m;
-    if (m > 0) {
-        hipLaunchKernelGGL(k_fill_i32, grid_for(ST_WORDS), dim3(TPB), 0, st, t->status, (int64_t)ST_WORDS, 0);
-        hipLaunchKernelGGL(k_node_depth, grid_for(m), dim3(TPB), 0, st, m, t->n_parent, t->n_first, t->n_count,
-                           t->base, t->n_depth, t->items, t->status);
-        SR_HIP(hipMemcpyAsync(hstat, t->status, sizeof(hstat), hipMemcpyDeviceToHost, st));
-    }
-    hipLaunchKernelGGL(k_particle_items, grid_for(n), dim3(TPB), 0, st, n, t->leaf_bparent, t->b_parent,
-                       t->b_pre, t->base, t->n_depth, t->pparent, t->items);
-    SR_HIP(hipStreamSynchronize(st));
     if (m == 0) {
         t->max_depth = 0;
         t->mixed_soft = false;
