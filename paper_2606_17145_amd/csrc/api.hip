@@ -86,6 +86,12 @@ void free_workspace(sr_tree* t)
     release(t->b_pre);
     release(t->leaf_bparent);
     release(t->status);
+    if (t->h_status) (void)hipHostFree(t->h_status);
+    if (t->h_counters) (void)hipHostFree(t->h_counters);
+    if (t->ev_status) (void)hipEventDestroy(t->ev_status);
+    if (t->ev_counters) (void)hipEventDestroy(t->ev_counters);
+    t->h_status = t->h_counters = nullptr;
+    t->ev_status = t->ev_counters = nullptr;
     release(t->depth_order);
     release(t->depth_cursor);
     release(t->perm);
@@ -157,6 +163,13 @@ int allocate_workspace(sr_tree* t, int64_t cap)
     A(t->b_pre, nodes);
     A(t->leaf_bparent, cap);
     A(t->status, ST_WORDS);
+    if (hipHostMalloc((void**)&t->h_status, ST_WORDS * sizeof(int32_t), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&t->h_counters, 8 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&t->ev_status, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&t->ev_counters, hipEventDisableTiming) != hipSuccess) {
+        free_workspace(t);
+        return sr_fail(SR_ENOMEM, "pinned host read-back buffers or their events could not be created");
+    }
     A(t->depth_order, nodes);
     A(t->depth_cursor, SR_MAX_DEPTH);
     A(t->perm, cap);

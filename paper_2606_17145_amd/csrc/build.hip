@@ -802,12 +802,14 @@ int sr_build_device(sr_tree* t, const double* pos, const double* mass, const dou
         hipLaunchKernelGGL(k_node_depth, grid_for(n - 1), dim3(TPB), 0, st, t->status + ST_NODES, t->n_parent,
                            t->n_first, t->n_count, t->base, t->n_depth, t->items, t->status);
     }
+    // the build's one synchronisation: input flags, node count and depth histogram go
+    // to pinned host memory, and the host waits for that copy while the particle pass runs
+    SR_HIP(hipMemcpyAsync(t->h_status, t->status, ST_WORDS * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    SR_HIP(hipEventRecord(t->ev_status, st));
     hipLaunchKernelGGL(k_particle_items, grid_for(n), dim3(TPB), 0, st, n, t->leaf_bparent, t->b_parent,
                        t->b_pre, t->base, t->n_depth, t->pparent, t->items);
-    // the build's one synchronisation: input flags, node count, depth histogram
-    int32_t hstat[ST_WORDS];
-    SR_HIP(hipMemcpyAsync(hstat, t->status, sizeof(hstat), hipMemcpyDeviceToHost, st));
-    SR_HIP(hipStreamSynchronize(st));
+    SR_HIP(hipEventSynchronize(t->ev_status));
+    const int32_t* hstat = t->h_status;
     if (hstat[ST_FLAGS] & 1) return sr_fail(SR_EINVAL, "tree_build: non-finite position or non-positive / non-finite mass or softening");
     // softenings that are not all equal select the walk's mixed-softening opening rule
     t->mixed_soft = (hstat[ST_FLAGS] & 2) != 0;

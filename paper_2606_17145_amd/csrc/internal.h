@@ -104,6 +104,11 @@ struct sr_tree {
     int32_t* b_pre = nullptr;         // pre-order index, -1 if not an octree node
     int32_t* leaf_bparent = nullptr;
     int32_t* status = nullptr;        // ST_WORDS
+    // pinned host copies of the status words and of the list counters, and the
+    // events recorded after those copies: the host waits for these points only
+    int32_t* h_status = nullptr;      // ST_WORDS
+    int32_t* h_counters = nullptr;    // 8
+    hipEvent_t ev_status = nullptr, ev_counters = nullptr;
     int32_t* depth_order = nullptr;   // node indices grouped by depth
     int32_t* depth_cursor = nullptr;  // SR_MAX_DEPTH
 

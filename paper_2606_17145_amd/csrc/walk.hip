@@ -1513,18 +1513,23 @@ int traverse_launch(sr_tree* t, const sr_params* p, int64_t n_t, const int32_t* 
     }
     sr_timing_mark(SR_T_TRAVERSE, false, st);
     SR_HIP(hipGetLastError());
+    // the counters go to pinned host memory right behind the traversal, so that the
+    // check waits for the traversal only and not for the work queued after it
+    SR_HIP(hipMemcpyAsync(t->h_counters, t->list_counters, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    SR_HIP(hipEventRecord(t->ev_counters, st));
     return SR_OK;
 }
 
-// After a traversal: read its counters (host synchronisation).  On success record
+// After a traversal: read its counters (the host waits until they have been
+// copied, which is right after the traversal kernel).  On success record
 // the list sizes and the key that identifies these lists; `overflow` tells the
 // caller to grow and traverse again.
 int traverse_finish(sr_tree* t, const sr_params* p, int64_t n_t, const int32_t* active, const double* a_old,
                     hipStream_t st, bool& overflow)
 {
     int32_t cnt[8];
-    SR_HIP(hipMemcpyAsync(cnt, t->list_counters, sizeof(cnt), hipMemcpyDeviceToHost, st));
-    SR_HIP(hipStreamSynchronize(st));
+    SR_HIP(hipEventSynchronize(t->ev_counters));
+    memcpy(cnt, t->h_counters, sizeof(cnt));
     overflow = cnt[2] != 0;
     if (overflow) return SR_OK;
     t->n_units = cnt[1];
