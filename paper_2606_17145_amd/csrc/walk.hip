@@ -157,30 +157,37 @@ __device__ inline double dpp_f64(double v)
 // cross-lane helpers
 // ----------------------------------------------------------------------------------
 //
-// v_readlane at a uniform lane index (a VGPR value as a scalar), and a lane
-// select that writes one lane of a VGPR.
+// v_readlane at a uniform lane index (a VGPR value as a scalar), and
+// v_writelane (a scalar value into one lane of a VGPR).
 
 __device__ inline uint32_t rl(uint32_t v, uint32_t l) { return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)l); }
 __device__ inline uint64_t rl64(uint64_t v, uint32_t l)
 {
     return ((uint64_t)rl((uint32_t)(v >> 32), l) << 32) | rl((uint32_t)v, l);
 }
-template <class T>
-__device__ inline T wl(T v, uint32_t l, T old)
+// (the compiler's writelane intrinsic, named directly: clang has no builtin for it)
+__device__ int amdgcn_writelane_i32(int v, int l, int old) __asm("llvm.amdgcn.writelane.i32");
+__device__ inline uint64_t wl64(uint64_t v, uint32_t l, uint64_t old)
 {
-    return (threadIdx.x & (WAVE - 1)) == l ? v : old;
+    const uint32_t lo = (uint32_t)amdgcn_writelane_i32((int)(uint32_t)v, (int)l, (int)(uint32_t)old);
+    const uint32_t hi = (uint32_t)amdgcn_writelane_i32((int)(uint32_t)(v >> 32), (int)l, (int)(uint32_t)(old >> 32));
+    return ((uint64_t)hi << 32) | lo;
 }
 
 // ----------------------------------------------------------------------------------
 // phase 1: traversal -> interaction lists
 // ----------------------------------------------------------------------------------
 //
-// One wave per group of 64 Morton-consecutive targets.  Each lane takes the
-// decisions of a depth-first walk of its own target; the wave shares the
-// traversal through ballots over the pre-order item sequence (a node's
-// children are entered when any lane opens it, its subtree skipped otherwise).
-// Accepted nodes and reached particles become list entries (source, lane
-// mask); the target's own particle is removed from its mask here.  Entries go
+// A workgroup of TW waves per group of 64 Morton-consecutive targets (lane l =
+// target l in every wave).  Each lane takes exactly the decisions of its own
+// target's walk; the group walks breadth-first, a level being a list of
+// (node, reach mask) entries, where the reach mask holds the targets whose walk
+// opened every ancestor.  The waves split a level, stage its nodes' records in
+// LDS, decide (per-target ballots, or the whole group at once when the group's
+// bounding box settles the outcome) and expand: opened nodes' children form
+// the next level with the opening lanes as their reach.  Accepted nodes and
+// reached particles become list entries (source, lane mask); the target's own
+// particle is removed from its mask here.  Entries go
 // to global memory in chunks of 64; up to UCH consecutive chunks of a group
 // form a unit, the work item of the evaluation phase.  This is the paper's
 // chunked neighbour processing (neighbours gathered in chunks and evaluated
@@ -714,11 +721,11 @@ __global__ __launch_bounds__(TW * WAVE) __attribute__((amdgpu_waves_per_eu(4, 8)
                     Dec d[DEC_ILP];
 #pragma unroll
                     for (int k = 0; k < DEC_ILP; ++k) d[k] = decide(jj[k]);
+                    // (a repeated node wrote the same masks to the same lane already)
 #pragma unroll
                     for (int k = 0; k < DEC_ILP; ++k) {
-                        const bool mine = use[k] && (uint32_t)lane == jj[k];
-                        my_om = mine ? d[k].om : my_om;
-                        my_am = mine ? d[k].am : my_am;
+                        my_om = wl64(d[k].om, jj[k], my_om);
+                        my_am = wl64(d[k].am, jj[k], my_am);
                     }
                 }
 
