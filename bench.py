@@ -31,6 +31,7 @@ FLOP_PER_ADJOINT_INTERACTION = 48  # forward pair force plus its vector-Jacobian
 FLOP_PER_NODE_TEST = 13            # r^2 (5), opening angle (2), enlarged-cube guard (6)
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_clustered_262k.md")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "walk_clustered_262k_counters.md")
 
 
 def kernel_source_hash():
@@ -41,19 +42,22 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def committed_traffic(phase):
-    """HBM bytes per launch of `phase` from the committed counter summary, if it was
-    taken on the current kernel source; else None."""
-    if not os.path.exists(TRAFFIC_FILE):
-        return None
+def committed_values(path):
+    """The machine-readable `- key: value` lines of a committed counter summary, if it
+    was taken on the current kernel source; else an empty dict."""
+    if not os.path.exists(path):
+        return {}
     vals = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if ":" in line and line.strip().startswith("- "):
             k, v = line.strip()[2:].split(":", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
-        return None
-    v = vals.get(f"{phase}_bytes_per_launch")
+    return vals if vals.get("kernel_source_sha256_16") == kernel_source_hash() else {}
+
+
+def committed_traffic(phase):
+    """HBM bytes per launch of `phase` (FETCH_SIZE + WRITE_SIZE, copy-calibrated)."""
+    v = committed_values(TRAFFIC_FILE).get(f"{phase}_bytes_per_launch")
     return float(v) if v else None
 
 
@@ -192,6 +196,18 @@ def main():
     out["roofline"] = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
                        "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
                        "traffic": committed_traffic(dom)}
+    # executed VALU FLOP (counters: 64 x (ADD + MUL + 2 FMA + TRANS) per launch) over the
+    # live launch time, beside the algorithmic rate above
+    cv = committed_values(COUNTERS_FILE)
+    valu = {}
+    for ph in ("traverse", "eval", "adjoint_eval"):
+        f = cv.get(f"{ph}_valu_flop_per_launch")
+        if f and avg[ph] > 0:
+            ex = float(f) / (avg[ph] * 1e-3) / 1e12
+            valu[ph] = {"executed_tflops": ex, "executed_frac": ex / FP32_PEAK_TFLOPS,
+                        "valu_busy": float(cv[f"{ph}_valu_busy"]),
+                        "algorithmic_tflops": work[ph] / (avg[ph] * 1e-3) / 1e12}
+    out["valu_counters"] = valu or None
 
     if not args.no_error_check:
         from oracle import oracle as O
