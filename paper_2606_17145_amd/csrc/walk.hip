@@ -284,6 +284,44 @@ __device__ inline bool axis_range(uint32_t c, uint32_t lo, uint32_t hi, int64_t&
     return true;
 }
 
+__device__ inline double wave_min_f64(double v)
+{
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) v = fmin(v, __shfl_xor(v, o, WAVE));
+    return v;
+}
+__device__ inline double wave_max_f64(double v)
+{
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) v = fmax(v, __shfl_xor(v, o, WAVE));
+    return v;
+}
+
+// FP64 counterpart of axis_range: bounds of |min_image(c - x, L)| over the targets'
+// coordinates x in [lo, hi], with the same roundings as the per-target test.  The
+// rounded difference c - x is monotone in x, so the two ends bound every target's;
+// the minimum image is bounded only when it takes the same branch over the range.
+__device__ inline bool axis_range64(double c, double lo, double hi, double L, double& amin, double& amax)
+{
+    const double dlo = c - hi, dhi = c - lo;
+    if (dlo >= -(0.5 * L) && dhi <= 0.5 * L) {   // no wrap for any target
+        amin = (dlo <= 0.0 && dhi >= 0.0) ? 0.0 : fmin(fabs(dlo), fabs(dhi));
+        amax = fmax(fabs(dlo), fabs(dhi));
+        return true;
+    }
+    if (dlo > 0.5 * L) {                         // every target wraps down
+        amin = fabs(dhi - L);
+        amax = fabs(dlo - L);
+        return true;
+    }
+    if (dhi < -(0.5 * L)) {                      // every target wraps up
+        amin = dlo + L;
+        amax = dhi + L;
+        return true;
+    }
+    return false;
+}
+
 // Sum of a uint32 over the 64 lanes (DPP, total in lane 63).
 __device__ inline uint32_t wave_sum63_u32(uint32_t x)
 {
@@ -411,11 +449,21 @@ __global__ __launch_bounds__(TW * WAVE) __attribute__((amdgpu_waves_per_eu(4, 8)
             }
         }
         const uint64_t active = __ballot(valid);
-        // bounding box of the group's targets (integer coordinates, FP32 decisions);
-        // a group wider than a quarter box on some axis is never classified as a whole
+        // bounding box of the group's targets (integer coordinates for FP32 decisions, a
+        // group wider than a quarter box on some axis is never classified as a whole;
+        // FP64 coordinates for FP64 decisions)
         uint32_t bxlo = 0, bxhi = 0, bylo = 0, byhi = 0, bzlo = 0, bzhi = 0;
+        double gxlo = 0, gxhi = 0, gylo = 0, gyhi = 0, gzlo = 0, gzhi = 0;   // FP64 decisions
         bool box_ok = false;
-        if constexpr (!DEC64) {
+        if constexpr (DEC64) {
+            gxlo = wave_min_f64(valid ? x64 : INFINITY);
+            gxhi = wave_max_f64(valid ? x64 : -INFINITY);
+            gylo = wave_min_f64(valid ? y64 : INFINITY);
+            gyhi = wave_max_f64(valid ? y64 : -INFINITY);
+            gzlo = wave_min_f64(valid ? z64 : INFINITY);
+            gzhi = wave_max_f64(valid ? z64 : -INFINITY);
+            box_ok = gxlo <= gxhi;
+        } else {
             bxlo = wave_min_u32(valid ? X : 0xffffffffu);
             bxhi = wave_max_u32(valid ? X : 0u);
             bylo = wave_min_u32(valid ? Y : 0xffffffffu);
@@ -635,13 +683,43 @@ __global__ __launch_bounds__(TW * WAVE) __attribute__((amdgpu_waves_per_eu(4, 8)
                             bool open_none = bm_lo > nr.tin && !(l2 > a.theta2f * r2_lo) && !REL;
                             if constexpr (MIXED)
                                 open_none = open_none && !(nr.mixed && r2_lo < __uint_as_float(nr.hx) * __uint_as_float(nr.hx));
-                            const bool near_all = r2_hi < a.rc2t;
+                            const bool near_all = r2_hi < a.rc2t, far_all = !(r2_lo < a.rc2t);
                             if (prune_all) {
                                 cls = 1;
                             } else if (keep_all && open_all) {
                                 cls = 2;
                             } else if (keep_all && open_none && near_all) {
                                 cls = 3;
+                            } else if (keep_all && open_none && far_all) {
+                                cls = 1;   // accepted by every target, beyond r_cut for all
+                            }
+                        }
+                    } else {
+                        double c0, c1, c2, c3, c4, c5, p0, p1, p2, p3, p4, p5;
+                        const double L = a.box;
+                        if (box_ok && axis_range64(nr.cx, gxlo, gxhi, L, c0, c1) &&
+                            axis_range64(nr.cy, gylo, gyhi, L, c2, c3) && axis_range64(nr.cz, gzlo, gzhi, L, c4, c5) &&
+                            axis_range64(nr.X, gxlo, gxhi, L, p0, p1) && axis_range64(nr.Y, gylo, gyhi, L, p2, p3) &&
+                            axis_range64(nr.Z, gzlo, gzhi, L, p4, p5)) {
+                            const double l = nr.l, thr = a.rc2 * (1.0 + 1e-6);
+                            const double txl = fmax(c0 - 0.5 * l, 0.0), tyl = fmax(c2 - 0.5 * l, 0.0), tzl = fmax(c4 - 0.5 * l, 0.0);
+                            const double txh = fmax(c1 - 0.5 * l, 0.0), tyh = fmax(c3 - 0.5 * l, 0.0), tzh = fmax(c5 - 0.5 * l, 0.0);
+                            const bool prune_all = (txl * txl + tyl * tyl) + tzl * tzl > thr;
+                            const bool keep_all = !((txh * txh + tyh * tyh) + tzh * tzh > thr);
+                            const double am_lo = fmax(c0, fmax(c2, c4)), am_hi = fmax(c1, fmax(c3, c5));
+                            const double r2_lo = (p0 * p0 + p2 * p2) + p4 * p4, r2_hi = (p1 * p1 + p3 * p3) + p5 * p5;
+                            const bool open_all = am_hi < 0.6 * l || l * l > a.theta2 * r2_hi;
+                            bool open_none = !(am_lo < 0.6 * l) && !(l * l > a.theta2 * r2_lo) && !REL;
+                            if constexpr (MIXED) open_none = open_none && !(nr.hn != nr.hx && r2_lo < nr.hx * nr.hx);
+                            const bool near_all = r2_hi < a.rc2, far_all = !(r2_lo < a.rc2);
+                            if (prune_all) {
+                                cls = 1;
+                            } else if (keep_all && open_all) {
+                                cls = 2;
+                            } else if (keep_all && open_none && near_all) {
+                                cls = 3;
+                            } else if (keep_all && open_none && far_all) {
+                                cls = 1;
                             }
                         }
                     }
