@@ -69,7 +69,9 @@ typedef struct sr_tree sr_tree;
 typedef struct {
     double G;              /* gravitational constant (1 in all synthetic workloads) */
     double r_s;            /* PM split scale, r_s = 1.25 L / N_mesh in Gadget's default */
-    double r_cut;          /* short-range cutoff (4.5 r_s by default); 0 < r_cut < L/2 */
+    double r_cut;          /* short-range cutoff (4.5 r_s by default); 0 < r_cut < L/2, and
+                              r_cut <= 4.6 r_s for SR_FP32 / SR_FP32_ACC64 (SR_EUNSUPPORTED otherwise:
+                              the FP32 split factor is fitted on r / 2 r_s <= 2.3) */
     int32_t criterion;     /* SR_OPEN_BH or SR_OPEN_RELATIVE */
     double theta;          /* opening angle (BH), or the geometric guard (RELATIVE); >= 0 */
     double alpha;          /* relative tolerance (RELATIVE only); >= 0 */

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "gpoly.h"
 
 namespace {
 thread_local char g_err[512] = "";
@@ -225,6 +226,10 @@ int check_params(const sr_tree* t, const sr_params* p)
         return sr_fail(SR_EINVAL, "alpha must be finite and >= 0");
     if (p->precision != SR_FP64 && p->precision != SR_FP32 && p->precision != SR_FP32_ACC64)
         return sr_fail(SR_EINVAL, "unknown precision %d", p->precision);
+    // the FP32 split factor is a polynomial fitted for u = r / (2 r_s) <= GPOLY_U_MAX
+    if (p->precision != SR_FP64 && p->r_cut > 2.0 * GPOLY_U_MAX * p->r_s)
+        return sr_fail(SR_EUNSUPPORTED, "FP32 precisions need r_cut <= %g r_s (got r_cut / r_s = %g)",
+                       2.0 * GPOLY_U_MAX, p->r_cut / p->r_s);
     return SR_OK;
 }
 

@@ -259,6 +259,12 @@ def test_error_paths(sg):
     with pytest.raises(sg.SrgravError):
         sg.shortrange_accel(t, dict(r_s=0.2, r_cut=0.5))                   # r_cut >= L/2
     p = w.params("fp64")
+    # FP32 split-factor polynomial range: r_cut / r_s above 4.6 is refused, FP64 accepts it
+    wide = dict(p, r_cut=5.0 * p["r_s"])
+    with pytest.raises(sg.SrgravError) as ei:
+        sg.shortrange_accel(t, dict(wide, precision="fp32"))
+    assert ei.value.code == -5
+    sg.shortrange_accel(t, wide)
     with pytest.raises(sg.SrgravError):
         sg.shortrange_accel(t, p, active=torch.tensor([0, 5, w.n], device=DEV))
     with pytest.raises(sg.SrgravError):
