@@ -144,6 +144,36 @@ def test_fp64_walk_clustered_262k_sampled(sg, oracle):
     assert e.max() <= 1e-12
 
 
+def test_list_growth_and_unit_estimate(sg, oracle):
+    """One handle rebuilt in place between a sparse and a dense particle set drives
+    the forward through both of its recovery paths: interaction lists that outgrow
+    their reservation (grown, traversal run again) and more evaluation units than
+    the previous call produced (the extra units are evaluated once the counters
+    have been read).  Every call must still equal the oracle."""
+    rng = np.random.default_rng(11)
+    n = 4096
+    uni = rng.random((n, 3))
+    ball = 0.5 + 0.02 * (rng.random((n, 3)) - 0.5)     # every pair within r_cut
+    mass = torch.full((n,), 1.0 / n, dtype=torch.float64, device=DEV)
+    eps = torch.full((n,), 1 / 600.0, dtype=torch.float64, device=DEV)
+    t = None
+    units = []
+    for k, (pos, theta) in enumerate([(uni, 0.5), (ball, 0.0), (uni, 0.5), (ball, 0.0)]):
+        w = WL.Workload(f"regrow{k}", pos, np.full(n, 1.0 / n), np.full(n, 1 / 600.0))
+        w.r_s, w.r_cut = WL.split_scales(48)
+        say(f"list growth / unit estimate: call {k}, theta {theta}")
+        t = sg.tree_build(torch.tensor(pos, device=DEV), mass, eps=eps, tree=t)
+        p = dict(w.params("fp64"), theta=theta)
+        acc, cnt = sg.shortrange_accel(t, p)
+        units.append(t.walk_stats()["units"])
+        ref = oracle.Tree(w.pos, w.mass, w.eps)
+        acc_ref, cnt_ref = oracle.walk(ref, p)
+        assert np.array_equal(cnt.cpu().numpy(), cnt_ref)
+        assert rel_err(acc.cpu().numpy(), acc_ref).max() <= 1e-12
+    # the dense calls need far more units than the sparse calls before them
+    assert units[1] > 2 * units[0] and units[3] > 2 * units[2]
+
+
 def test_theta_zero_is_direct_sum(sg, oracle):
     w = WL.clustered(8000, seed=8, n_spheres=5)
     say(f"theta=0: N={w.n}")
