@@ -1162,14 +1162,21 @@ struct alignas(16) SrcLds64 {
     uint32_t pad[2];
 };
 
-// FP64 sum over each row of 16 lanes (rotation butterfly on both halves).
-__device__ inline double row_sum15_f64(double x)
+// FP64 form of stream_sum4 for 16-lane streams (each exchange moves both 32-bit
+// halves): lane l ends with the row total of quantity (l mod 16) / 4.
+__device__ inline double stream_sum4_f64(double x, double y, double z, double m, int lane)
 {
-    double v = x + dpp_f64<0x121, 0xf, 0xf>(x);
-    v = v + dpp_f64<0x122, 0xf, 0xf>(v);
-    v = v + dpp_f64<0x124, 0xf, 0xf>(v);
-    v = v + dpp_f64<0x128, 0xf, 0xf>(v);
-    return v;
+    const bool b3 = lane & 8, b2 = lane & 4;
+    double k0 = b3 ? z : x, k1 = b3 ? m : y;
+    const double s0 = b3 ? x : z, s1 = b3 ? y : m;
+    k0 += dpp_f64<0x140, 0xf, 0xf>(s0);
+    k1 += dpp_f64<0x140, 0xf, 0xf>(s1);
+    double k = b2 ? k1 : k0;
+    const double s = b2 ? k0 : k1;
+    k += dpp_f64<0x141, 0xf, 0xf>(s);
+    k += dpp_f64<0xb1, 0xf, 0xf>(k);
+    k += dpp_f64<0x4e, 0xf, 0xf>(k);
+    return k;
 }
 
 template <bool ADJ>
@@ -1179,7 +1186,9 @@ __global__ __launch_bounds__(WAVE) void k_eval64(WalkArgs a, ListArgs L, char* _
     constexpr int NQ = WAVE / QL;
     __shared__ SrcLds64 s_ent[WAVE + 1];
     __shared__ uint8_t s_stream[NQ][WAVE];
-    __shared__ double s_acc[ADJ ? 4 : 1][WAVE];   // adjoint: source terms of each entry
+    // adjoint: the four source terms of each (stream, entry) pair of the chunk, each
+    // slot written at most once per chunk
+    __shared__ double4 s_part[ADJ ? NQ : 1][ADJ ? WAVE + 1 : 1];
     const int lane = threadIdx.x;
     const int quarter = lane / QL;
     const uint32_t bit = 1u << (lane & 31);
@@ -1224,10 +1233,6 @@ __global__ __launch_bounds__(WAVE) void k_eval64(WalkArgs a, ListArgs L, char* _
             const double hs = isp ? a.ph64[idx] : a.nhmax[idx];
             s_ent[lane] = SrcLds64{r.x, r.y, r.z, r.m, hs, lsrc, isp ? 1u : 0x10000u, (uint32_t)lmask,
                                    (uint32_t)(lmask >> 32), {0u, 0u}};
-        }
-        if constexpr (ADJ) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) s_acc[k][lane] = 0.0;
         }
         const uint64_t below = (1ull << lane) - 1ull;
         constexpr uint64_t QMASK = (1ull << QL) - 1ull;
@@ -1282,18 +1287,11 @@ __global__ __launch_bounds__(WAVE) void k_eval64(WalkArgs a, ListArgs L, char* _
                 }
             }
             if constexpr (ADJ) {
-                // source terms: sums over each stream's lanes, collected per entry
-                const double sx = row_sum15_f64(vx);
-                const double sy = row_sum15_f64(vy);
-                const double sz = row_sum15_f64(vz);
-                const double sm = row_sum15_f64(vm);
-                const bool nz = (sx != 0.0) | (sy != 0.0) | (sz != 0.0) | (sm != 0.0);
-                if ((lane % QL) == QL - 1 && e < (uint32_t)WAVE && nz) {
-                    atomicAdd(&s_acc[0][e], sx);
-                    atomicAdd(&s_acc[1][e], sy);
-                    atomicAdd(&s_acc[2][e], sz);
-                    atomicAdd(&s_acc[3][e], sm);
-                }
+                // source terms: the stream's totals, one quantity per lane, stored in the
+                // (stream, entry) slot (the padding entry 64 has a slot that is never read)
+                static_assert(QL == 16, "16-lane streams");
+                const double ssum = stream_sum4_f64(vx, vy, vz, vm, lane);
+                reinterpret_cast<double*>(&s_part[quarter][e])[(lane % QL) / 4] = ssum;
             }
         }
         wave_sync();
@@ -1302,11 +1300,21 @@ __global__ __launch_bounds__(WAVE) void k_eval64(WalkArgs a, ListArgs L, char* _
                 const uint32_t sid = s_ent[lane].sid;
                 double* dst = (sid & ITEM_PARTICLE) ? a.pbar + 4 * (int64_t)(sid & ~ITEM_PARTICLE)
                                                     : a.nbar + 4 * (int64_t)sid;
+                // the streams that visited this entry, in stream order
+                double v[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const double v = s_acc[k][lane];
-                    if (v != 0.0) unsafeAtomicAdd(dst + k, v);
+                for (int k = 0; k < NQ; ++k) {
+                    if (((lmask >> (QL * k)) & QMASK) != 0) {
+                        const double4 pk = s_part[k][lane];
+                        v[0] += pk.x;
+                        v[1] += pk.y;
+                        v[2] += pk.z;
+                        v[3] += pk.w;
+                    }
                 }
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (v[k] != 0.0) unsafeAtomicAdd(dst + k, v[k]);
             }
             wave_sync();
         }
