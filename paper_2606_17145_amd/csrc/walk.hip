@@ -17,6 +17,9 @@
 #include "gpoly.h"
 #include "internal.h"
 
+// the compiler's writelane intrinsic, named directly (clang has no builtin for it)
+__device__ int amdgcn_writelane_i32(int v, int l, int old) __asm("llvm.amdgcn.writelane.i32");
+
 namespace {
 
 constexpr int WAVE = 64;
@@ -165,8 +168,6 @@ __device__ inline uint64_t rl64(uint64_t v, uint32_t l)
 {
     return ((uint64_t)rl((uint32_t)(v >> 32), l) << 32) | rl((uint32_t)v, l);
 }
-// (the compiler's writelane intrinsic, named directly: clang has no builtin for it)
-__device__ int amdgcn_writelane_i32(int v, int l, int old) __asm("llvm.amdgcn.writelane.i32");
 __device__ inline uint64_t wl64(uint64_t v, uint32_t l, uint64_t old)
 {
     const uint32_t lo = (uint32_t)amdgcn_writelane_i32((int)(uint32_t)v, (int)l, (int)(uint32_t)old);
@@ -1055,10 +1056,8 @@ __global__ __launch_bounds__(EVAL_WAVES * WAVE) void k_eval32(WalkArgs a, ListAr
         }
         const int32_t cnext = L.chunk_next[c];
         wave_sync();
-        // two steps interleaved (their streams' entries are independent): 8% faster
-        // forward, the same adjoint
-#pragma unroll 2
-        for (uint32_t st = 0; st < steps; ++st) {
+        // one step: entry stream_k[st] on each group's lanes
+        auto step = [&](uint32_t st) __attribute__((always_inline)) {
             const uint32_t e = s_stream[quarter][st];
             const SrcLds src = s_ent[e];
             const uint32_t mw = hi_half ? src.mhi : src.mlo;
@@ -1113,6 +1112,14 @@ __global__ __launch_bounds__(EVAL_WAVES * WAVE) void k_eval32(WalkArgs a, ListAr
                 const float ssum = stream_sum4<QL>(px, py, pz, K * wd, lane);
                 reinterpret_cast<float*>(&s_part[quarter][e])[(lane % QL) / (QL / 4)] = ssum;
             }
+        };
+        // the forward takes two steps interleaved (their entries are independent):
+        // 8% faster; the adjoint gains nothing from it
+        if constexpr (!ADJ) {
+#pragma unroll 2
+            for (uint32_t st = 0; st < steps; ++st) step(st);
+        } else {
+            for (uint32_t st = 0; st < steps; ++st) step(st);
         }
         wave_sync();
         if constexpr (ADJ) {
@@ -1437,10 +1444,21 @@ __global__ void k_axpy(Y* __restrict__ y, const X* __restrict__ x, double a, int
     if (i < n) y[i] = (Y)((double)y[i] + a * (double)x[i]);
 }
 
-__global__ void k_zero_f64(double* p, int64_t n)
+// Clears three FP64 arrays in one launch (the adjoint's accumulators).
+__global__ void k_zero3_f64(double* a, int64_t na, double* b, int64_t nb, double* c, int64_t nc)
 {
     int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x;
-    if (i < n) p[i] = 0.0;
+    if (i < na) {
+        a[i] = 0.0;
+        return;
+    }
+    i -= na;
+    if (i < nb) {
+        b[i] = 0.0;
+        return;
+    }
+    i -= nb;
+    if (i < nc) c[i] = 0.0;
 }
 
 __global__ void k_targets_all(int64_t n, const int32_t* __restrict__ perm, int32_t* __restrict__ tgt_sorted,
@@ -1796,9 +1814,8 @@ int sr_walk_adjoint(sr_tree* t, const sr_params* p, int64_t n_t, const int32_t* 
                     const void* w, double* dLdx, double* dLdm, hipStream_t st)
 {
     const int64_t n = t->n, m = t->n_nodes;
-    hipLaunchKernelGGL(k_zero_f64, g256(4 * n), dim3(256), 0, st, t->pbar, 4 * n);
-    hipLaunchKernelGGL(k_zero_f64, g256(3 * n), dim3(256), 0, st, t->tbar, 3 * n);
-    if (m) hipLaunchKernelGGL(k_zero_f64, g256(4 * m), dim3(256), 0, st, t->nbar, 4 * m);
+    hipLaunchKernelGGL(k_zero3_f64, g256(7 * n + 4 * m), dim3(256), 0, st, t->pbar, 4 * n, t->tbar, 3 * n, t->nbar,
+                       4 * m);
     if (n_t > 0 && m > 0) {
         // the forward's lists carry the frozen decisions; walk again only if they are not those of this call
         if (!same_lists(t, p, n_t, active, a_old)) {
