@@ -25,7 +25,8 @@
  *     the current device, contiguous, owned by the caller.  Nothing is
  *     retained after a call except inside an sr_tree handle.
  *   - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream).
- *     Calls synchronise that stream only where stated.
+ *     The host waits only where stated, and then for one point of the
+ *     stream (an event behind a small copy), not for all work queued on it.
  *   - Every call returns SR_OK (0) or a negative error code and never throws;
  *     srgrav_last_error() gives a message for the calling thread.
  *   - Outputs are overwritten, never accumulated into.
@@ -95,8 +96,10 @@ typedef struct {
  *
  * The node set is the compressed octree of the 90-bit Morton keys (cells with
  * at least two non-empty children, and level-30 buckets of identical keys), in
- * pre-order.  Synchronises `stream` once, to read the node count and the
- * finiteness flag.  SR_EINVAL on NaN/Inf positions, masses or softenings.
+ * pre-order.  The host waits once, for the point of `stream` where the node
+ * count, the depth histogram and the input flags have been copied back (the
+ * remaining build kernels are queued afterwards and run asynchronously).
+ * SR_EINVAL on NaN/Inf positions, masses or softenings.
  */
 int tree_build(const double* pos, const double* mass, const double* eps, double eps_scalar,
                int64_t n, double box, int32_t leaf_size, void* stream, sr_tree** tree);
@@ -114,8 +117,12 @@ int tree_build(const double* pos, const double* mass, const double* eps, double 
  *             interactions per target), or NULL
  *
  * Per-target semantics are those of a depth-first walk of one particle; the
- * group walk only shares the traversal.  Synchronises `stream` once when
- * `active` is given, to report out-of-range or repeated indices.
+ * group walk only shares the traversal.  The host waits once for the
+ * traversal's list counters (the point right behind the traversal kernel; the
+ * evaluation is already queued and may still run when the call returns), and
+ * once more when `active` is given, to report out-of-range or repeated
+ * indices.  Lists that outgrow their reservation are grown and the traversal
+ * repeated within the call; the reservation is kept on the handle.
  */
 int shortrange_accel(sr_tree* tree, const sr_params* p, const int32_t* active, int64_t n_active,
                      const double* a_old, void* acc, int32_t* counts, void* stream);
@@ -136,7 +143,9 @@ int shortrange_accel(sr_tree* tree, const sr_params* p, const int32_t* active, i
  *   dLdm  DEVICE double[n]    output, input order
  *
  * Node terms are scattered with device atomics, so the low bits of the result
- * may differ from run to run.
+ * may differ from run to run.  The host does not wait when the forward's lists
+ * are reused; otherwise it waits for the repeated traversal's counters as
+ * shortrange_accel does.
  */
 int shortrange_accel_adjoint(sr_tree* tree, const sr_params* p, const int32_t* active,
                              int64_t n_active, const double* a_old, const void* w, double* dLdx,
