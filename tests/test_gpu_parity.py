@@ -263,16 +263,19 @@ def test_adjoint_fp64_matches_oracle(sg, oracle, case):
     assert np.allclose(dm.cpu().numpy(), gm, rtol=1e-10, atol=1e-11 * sm)
 
 
-def test_adjoint_fp32_close_to_oracle(sg, oracle):
+@pytest.mark.parametrize("prec", ["fp32", "fp32_acc64"])
+def test_adjoint_fp32_close_to_oracle(sg, oracle, prec):
     w = WL.clustered(12_000, seed=17, n_spheres=6)
     t = gpu_tree(sg, w)
     wt = np.random.default_rng(18).standard_normal((w.n, 3))
-    dx, dm = sg.shortrange_accel_adjoint(t, w.params("fp32"), torch.tensor(wt, device=DEV, dtype=torch.float32))
+    # the cotangent has the accumulator's type: float for fp32, double for fp32_acc64
+    wdt = torch.float32 if prec == "fp32" else torch.float64
+    dx, dm = sg.shortrange_accel_adjoint(t, w.params(prec), torch.tensor(wt, device=DEV, dtype=wdt))
     ref = oracle.Tree(w.pos, w.mass, w.eps)
     gx, gm = oracle.adjoint(ref, w.params("fp64"), wt)
     ex = np.linalg.norm(dx.cpu().numpy() - gx, axis=1) / np.maximum(np.linalg.norm(gx, axis=1), 1e-6 * np.median(np.linalg.norm(gx, axis=1)))
     em = np.abs(dm.cpu().numpy() - gm) / np.maximum(np.abs(gm), 1e-6 * np.median(np.abs(gm)))
-    say(f"adjoint fp32: dx median {np.median(ex):.3e} p99.9 {np.quantile(ex, 0.999):.3e}; dm median {np.median(em):.3e} p99.9 {np.quantile(em, 0.999):.3e}")
+    say(f"adjoint {prec}: dx median {np.median(ex):.3e} p99.9 {np.quantile(ex, 0.999):.3e}; dm median {np.median(em):.3e} p99.9 {np.quantile(em, 0.999):.3e}")
     assert np.median(ex) <= 1e-4 and np.median(em) <= 1e-4
 
 
