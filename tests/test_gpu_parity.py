@@ -238,6 +238,27 @@ def test_mixed_softening_zoom(sg, oracle):
     assert rel_err(acc.cpu().numpy(), acc_ref).max() <= 1e-12
 
 
+def test_relative_criterion_mixed_softening(sg, oracle):
+    """The relative criterion on a zoom (softenings differ between particles):
+    both opening rules at once, FP64 exact and FP32 to the force-error bar."""
+    w = WL.zoom(20_000, 16, seed=23)
+    ref = oracle.Tree(w.pos, w.mass, w.eps)
+    a_bh, _ = oracle.walk(ref, w.params("fp64"))
+    a_old = np.linalg.norm(a_bh, axis=1)
+    p = dict(w.params("fp64"), criterion="relative", alpha=0.005, theta=0.7)
+    say(f"relative criterion, mixed softening: N={w.n}")
+    t = gpu_tree(sg, w)
+    ao = torch.tensor(a_old, device=DEV)
+    acc, cnt = sg.shortrange_accel(t, p, a_old=ao)
+    acc_ref, cnt_ref = oracle.walk(ref, p, a_old=a_old)
+    assert np.array_equal(cnt.cpu().numpy(), cnt_ref)
+    assert rel_err(acc.cpu().numpy(), acc_ref).max() <= 1e-12
+    acc32, _ = sg.shortrange_accel(t, dict(p, precision="fp32"), a_old=ao)
+    e = rel_err(acc32.double().cpu().numpy(), acc_ref)
+    say(f"   fp32 median {np.median(e):.3e} p99.9 {np.quantile(e, 0.999):.3e}")
+    assert np.median(e) <= 1e-5 and np.quantile(e, 0.999) <= 1e-4
+
+
 def test_forward_is_deterministic(sg):
     w = WL.clustered(30_000, seed=14, n_spheres=9)
     t = gpu_tree(sg, w)
