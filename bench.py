@@ -232,8 +232,10 @@ def main():
         _, cs = O.walk(ref, p64)
         O.adjoint(ref, p64, wt)
         cpu_s = time.perf_counter() - t0
+        cpu_model = next((ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo")
+                          if ln.startswith("model name")), "unknown") if os.path.exists("/proc/cpuinfo") else "unknown"
         out["cpu_baseline"] = {"value": float(cs.sum()) / cpu_s, "unit": "interactions/s",
-                               "cores": O.num_threads(), "kind": "oracle",
+                               "cores": O.num_threads(), "kind": "oracle", "cpu_model": cpu_model,
                                "sample": "the whole step on the same workload: FP64 oracle tree build of all "
                                          "262,144 particles, walk and adjoint of all 262,144 targets"}
         log(f"bench: oracle {cpu_s:.2f} s on {O.num_threads()} threads")
