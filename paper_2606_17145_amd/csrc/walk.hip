@@ -601,16 +601,14 @@ __global__ __launch_bounds__(TW * WAVE) __attribute__((amdgpu_waves_per_eu(4, 8)
                 }
                 nb += k;
             };
-            for (int64_t b0 = e0; b0 < e1 && !overflow; b0 += WAVE) {
-                const uint32_t cnt = (uint32_t)(e1 - b0 < WAVE ? e1 - b0 : WAVE);
-                // ---- stage the block's nodes ----
-                uint32_t fid = 0, fmeta = 0;
-                uint64_t fmask = 0;
-                int cls = 0;   // 0: decide per target, 1: pruned for all, 2: opened by all, 3: accepted by all
-                if ((uint32_t)lane < cnt) {
-                    // entry e of the level lies in the region of the first wave whose
-                    // cumulative count exceeds it
-                    int64_t off = b0 + lane;
+            // the level's entry b0 + lane: it lies in the region of the first wave whose
+            // cumulative count exceeds it.  Entries are read one block ahead, so that a
+            // block's staging waits for its node records only.
+            auto load_entry = [&](int64_t b, uint32_t& id, uint64_t& m) __attribute__((always_inline)) {
+                id = 0;
+                m = 0;
+                if (b + lane < e1) {
+                    int64_t off = b + lane;
                     int r = 0;
 #pragma unroll
                     for (int w = 0; w < TW - 1; ++w) {
@@ -618,8 +616,21 @@ __global__ __launch_bounds__(TW * WAVE) __attribute__((amdgpu_waves_per_eu(4, 8)
                         off -= past ? c[w] : 0;
                         r += past ? 1 : 0;
                     }
-                    fid = rid(cur, r)[off];
-                    fmask = rmask(cur, r)[off];
+                    id = rid(cur, r)[off];
+                    m = rmask(cur, r)[off];
+                }
+            };
+            uint32_t nxt_id;
+            uint64_t nxt_mask;
+            load_entry(e0, nxt_id, nxt_mask);
+            for (int64_t b0 = e0; b0 < e1 && !overflow; b0 += WAVE) {
+                const uint32_t cnt = (uint32_t)(e1 - b0 < WAVE ? e1 - b0 : WAVE);
+                // ---- stage the block's nodes ----
+                uint32_t fid = nxt_id, fmeta = 0;
+                uint64_t fmask = nxt_mask;
+                load_entry(b0 + WAVE, nxt_id, nxt_mask);
+                int cls = 0;   // 0: decide per target, 1: pruned for all, 2: opened by all, 3: accepted by all
+                if ((uint32_t)lane < cnt) {
                     tests += (uint32_t)__popcll(fmask);
                     const uint32_t nd = fid;
                     NodeRec<DEC64> nr;
