@@ -1,0 +1,144 @@
+"""FP64 oracle of the particle-mesh (PM) long-range force of the TreePM split.
+
+TEST INFRASTRUCTURE ONLY: the test-suite uses it to produce expected values.
+It imports nothing from the GPU package and the GPU package never imports it.
+
+The paper computes the long-range half of the TreePM force on the CPU with
+FFTW (Sec. 3.1) and defines no scheme of its own; this follows the published
+Gadget-2 PM scheme (Springel 2005, Sec. 3.1 there), written out plainly:
+
+1. periodic cloud-in-cell (CIC) assignment of the masses to an N^3 mesh whose
+   points sit at (i, j, k) L / N, giving the density rho = mass per cell / h^3;
+2. rho_hat = DFT(rho);
+3. phi_hat(k) = -4 pi G rho_hat(k) exp(-k^2 r_s^2) / k^2, phi_hat(0) = 0, divided
+   by the CIC window twice (assignment and interpolation): prod_d sinc(pi n_d / N)^4
+   with n_d the signed integer wavenumber and sinc(x) = sin(x) / x;
+4. a_hat_d(k) = -i k_d phi_hat(k) (a = -grad phi), zero on the Nyquist plane of
+   axis d (the derivative of a real field there has no real representation);
+5. a_d = inverse DFT (normalised by 1/N^3) on the mesh;
+6. CIC interpolation of a_d back to the particles with the assignment weights.
+
+The exp(-k^2 r_s^2) filter is the Fourier transform of the long-range part
+G m erf(r / 2 r_s) / r of the potential, the complement of the short-range
+erfc(r / 2 r_s) / r that the tree walk applies.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def wrap_unit(pos: np.ndarray, box: float) -> np.ndarray:
+    """u = x / L - floor(x / L) in [0, 1); a rounding to 1 maps to 0."""
+    u = pos / box
+    u = u - np.floor(u)
+    u[u >= 1.0] = 0.0
+    return u
+
+
+def cic_weights(pos: np.ndarray, box: float, n_mesh: int):
+    """Per particle and axis: the lower mesh index and the weight of the upper one."""
+    s = wrap_unit(np.asarray(pos, dtype=np.float64), box) * n_mesh
+    i0 = np.floor(s).astype(np.int64)
+    f = s - i0
+    i0 %= n_mesh
+    return i0, f
+
+
+def cic_assign(pos: np.ndarray, mass: np.ndarray, box: float, n_mesh: int) -> np.ndarray:
+    """Density on the mesh: each particle's mass spread over the 8 surrounding mesh
+    points with weights prod_d (1 - f_d or f_d), divided by the cell volume."""
+    i0, f = cic_weights(pos, box, n_mesh)
+    rho = np.zeros((n_mesh, n_mesh, n_mesh))
+    h3 = (box / n_mesh) ** 3
+    for cx in (0, 1):
+        wx = f[:, 0] if cx else 1.0 - f[:, 0]
+        ix = (i0[:, 0] + cx) % n_mesh
+        for cy in (0, 1):
+            wy = f[:, 1] if cy else 1.0 - f[:, 1]
+            iy = (i0[:, 1] + cy) % n_mesh
+            for cz in (0, 1):
+                wz = f[:, 2] if cz else 1.0 - f[:, 2]
+                iz = (i0[:, 2] + cz) % n_mesh
+                np.add.at(rho, (ix, iy, iz), mass * (wx * wy * wz) / h3)
+    return rho
+
+
+def cic_interpolate(field: np.ndarray, pos: np.ndarray, box: float) -> np.ndarray:
+    """Value of a mesh field at the particles with the assignment weights."""
+    n_mesh = field.shape[0]
+    i0, f = cic_weights(pos, box, n_mesh)
+    out = np.zeros(len(i0))
+    for cx in (0, 1):
+        wx = f[:, 0] if cx else 1.0 - f[:, 0]
+        ix = (i0[:, 0] + cx) % n_mesh
+        for cy in (0, 1):
+            wy = f[:, 1] if cy else 1.0 - f[:, 1]
+            iy = (i0[:, 1] + cy) % n_mesh
+            for cz in (0, 1):
+                wz = f[:, 2] if cz else 1.0 - f[:, 2]
+                iz = (i0[:, 2] + cz) % n_mesh
+                out += (wx * wy * wz) * field[ix, iy, iz]
+    return out
+
+
+def wavenumbers(n_mesh: int):
+    """Signed integer wavenumbers of the full axes and of the halved last axis."""
+    n = np.arange(n_mesh)
+    full = np.where(n <= n_mesh // 2, n, n - n_mesh)
+    half = np.arange(n_mesh // 2 + 1)
+    return full, half
+
+
+def potential_spectrum(rho_hat: np.ndarray, box: float, r_s: float, G: float) -> np.ndarray:
+    """phi_hat = -4 pi G rho_hat exp(-k^2 r_s^2) / k^2 / W_CIC(k)^2, phi_hat(0) = 0."""
+    n_mesh = rho_hat.shape[0]
+    full, half = wavenumbers(n_mesh)
+    nx, ny, nz = np.meshgrid(full, full, half, indexing="ij")
+    two_pi_l = 2.0 * np.pi / box
+    k2 = (two_pi_l * nx) ** 2 + (two_pi_l * ny) ** 2 + (two_pi_l * nz) ** 2
+
+    def sinc(n):
+        x = np.pi * n / n_mesh
+        return np.where(n == 0, 1.0, np.sin(x) / np.where(n == 0, 1.0, x))
+
+    w = sinc(nx) * sinc(ny) * sinc(nz)          # one CIC window is w^2
+    with np.errstate(divide="ignore", invalid="ignore"):
+        green = -4.0 * np.pi * G * np.exp(-k2 * r_s * r_s) / k2 / (w ** 4)
+    green[0, 0, 0] = 0.0
+    return rho_hat * green
+
+
+def pm_accel(pos: np.ndarray, mass: np.ndarray, box: float, n_mesh: int, r_s: float,
+             G: float = 1.0) -> np.ndarray:
+    """Long-range (PM) accelerations (N, 3) of all particles, in input order."""
+    pos = np.asarray(pos, dtype=np.float64)
+    mass = np.asarray(mass, dtype=np.float64)
+    rho = cic_assign(pos, mass, box, n_mesh)
+    phi_hat = potential_spectrum(np.fft.rfftn(rho), box, r_s, G)
+    full, half = wavenumbers(n_mesh)
+    two_pi_l = 2.0 * np.pi / box
+    acc = np.zeros((len(pos), 3))
+    for d in range(3):
+        n_d = (full if d < 2 else half)
+        kd = two_pi_l * np.where(np.abs(n_d) == n_mesh // 2, 0, n_d)   # Nyquist plane: zero
+        shape = [1, 1, 1]
+        shape[d] = -1
+        a_hat = -1j * kd.reshape(shape) * phi_hat
+        a_mesh = np.fft.irfftn(a_hat, s=(n_mesh, n_mesh, n_mesh), axes=(0, 1, 2))
+        acc[:, d] = cic_interpolate(a_mesh, pos, box)
+    return acc
+
+
+def long_range_pair(d: np.ndarray, m: float, r_s: float, G: float = 1.0) -> np.ndarray:
+    """Acceleration of a test particle at separation vector d (N, 3) from a point mass m
+    under the long-range part of the split alone, in infinite space (no images):
+    a = -G m d / r^3 [erf(u) - 2u/sqrt(pi) exp(-u^2)], u = r / 2 r_s, pointing to the mass."""
+    from math import erf, exp, pi, sqrt
+    d = np.atleast_2d(np.asarray(d, dtype=np.float64))
+    out = np.zeros_like(d)
+    for i, v in enumerate(d):
+        r = float(np.linalg.norm(v))
+        u = r / (2.0 * r_s)
+        f = erf(u) - 2.0 * u / sqrt(pi) * exp(-u * u)
+        out[i] = -G * m * v / r ** 3 * f
+    return out
