@@ -4,8 +4,8 @@ TEST INFRASTRUCTURE ONLY: the test-suite uses it to produce expected values.
 It imports nothing from the GPU package and the GPU package never imports it.
 
 The paper computes the long-range half of the TreePM force on the CPU with
-FFTW (Sec. 3.1) and defines no scheme of its own; this follows the published
-Gadget-2 PM scheme (Springel 2005, Sec. 3.1 there), written out plainly:
+FFTW (Sec. 3.1) and defines no scheme of its own; this follows Gadget-2's
+periodic PM (Springel 2005, its TreePM section), written out plainly:
 
 1. periodic cloud-in-cell (CIC) assignment of the masses to an N^3 mesh whose
    points sit at (i, j, k) L / N, giving the density rho = mass per cell / h^3;
@@ -13,10 +13,11 @@ Gadget-2 PM scheme (Springel 2005, Sec. 3.1 there), written out plainly:
 3. phi_hat(k) = -4 pi G rho_hat(k) exp(-k^2 r_s^2) / k^2, phi_hat(0) = 0, divided
    by the CIC window twice (assignment and interpolation): prod_d sinc(pi n_d / N)^4
    with n_d the signed integer wavenumber and sinc(x) = sin(x) / x;
-4. a_hat_d(k) = -i k_d phi_hat(k) (a = -grad phi), zero on the Nyquist plane of
-   axis d (the derivative of a real field there has no real representation);
-5. a_d = inverse DFT (normalised by 1/N^3) on the mesh;
-6. CIC interpolation of a_d back to the particles with the assignment weights.
+4. phi = inverse DFT (normalised by 1/N^3) on the mesh;
+5. the force field F = -grad phi on the mesh by the fourth-order central
+   difference along each axis:
+   F_d(i) = [8 (phi(i - e_d) - phi(i + e_d)) - (phi(i - 2 e_d) - phi(i + 2 e_d))] / (12 h);
+6. CIC interpolation of F_d back to the particles with the assignment weights.
 
 The exp(-k^2 r_s^2) filter is the Fourier transform of the long-range part
 G m erf(r / 2 r_s) / r of the potential, the complement of the short-range
@@ -108,25 +109,99 @@ def potential_spectrum(rho_hat: np.ndarray, box: float, r_s: float, G: float) ->
     return rho_hat * green
 
 
+def potential_mesh(pos: np.ndarray, mass: np.ndarray, box: float, n_mesh: int, r_s: float,
+                   G: float = 1.0) -> np.ndarray:
+    """The long-range potential phi on the mesh (steps 1-4)."""
+    rho = cic_assign(pos, mass, box, n_mesh)
+    phi_hat = potential_spectrum(np.fft.rfftn(rho), box, r_s, G)
+    return np.fft.irfftn(phi_hat, s=(n_mesh, n_mesh, n_mesh), axes=(0, 1, 2))
+
+
+def mesh_force(phi: np.ndarray, box: float) -> np.ndarray:
+    """-grad phi (3, N, N, N) by the periodic fourth-order central difference (step 5).
+    np.roll(phi, s, axis=d)[i] is phi(i - s e_d)."""
+    h = box / phi.shape[0]
+    out = np.empty((3,) + phi.shape)
+    for d in range(3):
+        out[d] = (8.0 * (np.roll(phi, 1, d) - np.roll(phi, -1, d))
+                  - (np.roll(phi, 2, d) - np.roll(phi, -2, d))) / (12.0 * h)
+    return out
+
+
 def pm_accel(pos: np.ndarray, mass: np.ndarray, box: float, n_mesh: int, r_s: float,
              G: float = 1.0) -> np.ndarray:
     """Long-range (PM) accelerations (N, 3) of all particles, in input order."""
     pos = np.asarray(pos, dtype=np.float64)
     mass = np.asarray(mass, dtype=np.float64)
-    rho = cic_assign(pos, mass, box, n_mesh)
-    phi_hat = potential_spectrum(np.fft.rfftn(rho), box, r_s, G)
-    full, half = wavenumbers(n_mesh)
-    two_pi_l = 2.0 * np.pi / box
+    force = mesh_force(potential_mesh(pos, mass, box, n_mesh, r_s, G), box)
     acc = np.zeros((len(pos), 3))
     for d in range(3):
-        n_d = (full if d < 2 else half)
-        kd = two_pi_l * np.where(np.abs(n_d) == n_mesh // 2, 0, n_d)   # Nyquist plane: zero
-        shape = [1, 1, 1]
-        shape[d] = -1
-        a_hat = -1j * kd.reshape(shape) * phi_hat
-        a_mesh = np.fft.irfftn(a_hat, s=(n_mesh, n_mesh, n_mesh), axes=(0, 1, 2))
-        acc[:, d] = cic_interpolate(a_mesh, pos, box)
+        acc[:, d] = cic_interpolate(force[d], pos, box)
     return acc
+
+
+def cic_gradient_interpolate(field: np.ndarray, pos: np.ndarray, box: float) -> np.ndarray:
+    """(N, 3): d/dx_e of the interpolated field value at each particle with the mesh
+    field held fixed.  The weight of axis e is 1 - f_e or f_e with df_e/dx_e = N / L,
+    so its derivative is -N / L or +N / L (the derivative inside a cell)."""
+    n_mesh = field.shape[0]
+    i0, f = cic_weights(pos, box, n_mesh)
+    inv_h = n_mesh / box
+    out = np.zeros((len(i0), 3))
+    for cx in (0, 1):
+        wx = f[:, 0] if cx else 1.0 - f[:, 0]
+        dx = inv_h if cx else -inv_h
+        ix = (i0[:, 0] + cx) % n_mesh
+        for cy in (0, 1):
+            wy = f[:, 1] if cy else 1.0 - f[:, 1]
+            dy = inv_h if cy else -inv_h
+            iy = (i0[:, 1] + cy) % n_mesh
+            for cz in (0, 1):
+                wz = f[:, 2] if cz else 1.0 - f[:, 2]
+                dz = inv_h if cz else -inv_h
+                iz = (i0[:, 2] + cz) % n_mesh
+                v = field[ix, iy, iz]
+                out[:, 0] += dx * wy * wz * v
+                out[:, 1] += wx * dy * wz * v
+                out[:, 2] += wx * wy * dz * v
+    return out
+
+
+def pm_adjoint(pos: np.ndarray, mass: np.ndarray, box: float, n_mesh: int, r_s: float, w: np.ndarray,
+               G: float = 1.0):
+    """Gradient of L = sum_i w_i . a_i (a the PM accelerations) with respect to the
+    positions (N, 3) and the masses (N,), taking the forward steps in reverse:
+
+    With W_i(c) the CIC weight of particle i at mesh point c, rho = sum_j m_j W_j / h^3,
+    phi = K rho (K the filtered Green's convolution of steps 2-4, a symmetric
+    operator), F_d = D_d phi (D_d the difference rule of step 5, an odd operator:
+    its transpose is -D_d) and a_i,d = sum_c W_i(c) F_d(c):
+
+      omega_d(c) = sum_i w_i,d W_i(c)                    (the weights assigned to the mesh)
+      psi        = K^T sum_d D_d^T omega_d = -K sum_d D_d omega_d
+      dL/dm_j    = sum_c W_j(c) psi(c) / h^3
+      dL/dx_j    = sum_d w_j,d sum_c grad W_j(c) F_d(c) + m_j / h^3 sum_c grad W_j(c) psi(c)
+
+    The second term of dL/dx_j is particle j as a source, the first as a target.
+    The CIC weights are piecewise linear, so this is the derivative inside the mesh
+    cells (a position exactly on a mesh plane takes the one-sided value of the
+    cell that holds it)."""
+    pos = np.asarray(pos, dtype=np.float64)
+    mass = np.asarray(mass, dtype=np.float64)
+    w = np.asarray(w, dtype=np.float64)
+    h3 = (box / n_mesh) ** 3
+    force = mesh_force(potential_mesh(pos, mass, box, n_mesh, r_s, G), box)
+    chi = np.zeros((n_mesh, n_mesh, n_mesh))
+    for d in range(3):
+        omega = cic_assign(pos, w[:, d], box, n_mesh) * h3          # without the 1/h^3 of a density
+        chi -= mesh_force(omega, box)[d]
+    psi = np.fft.irfftn(potential_spectrum(np.fft.rfftn(chi), box, r_s, G),
+                        s=(n_mesh, n_mesh, n_mesh), axes=(0, 1, 2))
+    dmass = cic_interpolate(psi, pos, box) / h3
+    dpos = mass[:, None] * cic_gradient_interpolate(psi, pos, box) / h3
+    for d in range(3):
+        dpos += w[:, d][:, None] * cic_gradient_interpolate(force[d], pos, box)
+    return dpos, dmass
 
 
 def long_range_pair(d: np.ndarray, m: float, r_s: float, G: float = 1.0) -> np.ndarray:
