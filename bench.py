@@ -159,6 +159,24 @@ def main():
     inter64 = int(c64.cpu().numpy().astype(np.int64).sum())
     log(f"bench: fwd64 {fwd64_ms:.3f} ms")
 
+    # PM leg (not in the step): long-range force of the same particles on the 128^3 mesh
+    pmh = sg.PM(128)
+    for _ in range(2):
+        a_pm = pmh.accel(pos, mass, box=w.box, r_s=w.r_s)
+    torch.cuda.synchronize()
+    _lib.timing(True)
+    e_pm = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    e_pm[0].record()
+    for _ in range(reps):
+        a_pm = pmh.accel(pos, mass, box=w.box, r_s=w.r_s)
+    e_pm[1].record()
+    torch.cuda.synchronize()
+    pm_ms = e_pm[0].elapsed_time(e_pm[1]) / reps
+    pm_phases = {k: ms / reps for k, (ms, n) in _lib.timing_read().items() if k.startswith("pm_") and n}
+    _lib.timing(False)
+    del pmh
+    log(f"bench: pm 128^3 {pm_ms:.3f} ms {pm_phases}")
+
     out = {
         "metric": METRIC,
         "value": inter / (ms_step * 1e-3),
@@ -188,6 +206,8 @@ def main():
     avg = {k: (ms / n if n else 0.0) for k, (ms, n) in phases.items()}
     out["kernel_ms_per_launch"] = avg
     out["walk_stats"] = stats
+    out["pm_long_range"] = {"n_mesh": 128, "ms_per_call": pm_ms, "phases_ms_per_call": pm_phases,
+                            "particles_per_s": w.n / (pm_ms * 1e-3)}
     work = {"eval": FLOP_PER_INTERACTION * inter,
             "adjoint_eval": FLOP_PER_ADJOINT_INTERACTION * inter,
             "traverse": FLOP_PER_NODE_TEST * stats["node_tests"]}

@@ -180,7 +180,13 @@ enum {
     SR_T_ADJ_EVAL = 4,     /* adjoint pair terms */
     SR_T_ADJ_REDUCE = 5,   /* per-target adjoint sums */
     SR_T_PUSHDOWN = 6,     /* node adjoints to particles */
-    SR_T_COUNT = 7
+    SR_T_PM_DEPOSIT = 7,   /* PM: mesh clear and CIC mass assignment */
+    SR_T_PM_FFT = 8,       /* PM: one 3D FFT (two per pm_accel) */
+    SR_T_PM_GREEN = 9,     /* PM: Green's function applied to the density spectrum */
+    SR_T_PM_INTERP = 10,   /* PM: finite-difference force and CIC interpolation */
+    SR_T_PM_STENCIL = 11,  /* PM adjoint: transposed difference rule on one weight mesh */
+    SR_T_PM_ADJ_GATHER = 12, /* PM adjoint: per-particle position and mass gradients */
+    SR_T_COUNT = 13
 };
 int srgrav_timing(int32_t enable);
 int srgrav_timing_read(double* ms, int64_t* calls);
@@ -215,6 +221,75 @@ void tree_free(sr_tree* tree);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* srgrav_last_error(void);
+
+/*
+ * PM long-range force -- the mesh half of the TreePM split, the complement of
+ * the short-range erfc force above (the paper computes it on the host with
+ * FFTW, Sec. 3.1; the scheme is Gadget-2's periodic PM):
+ *
+ *   rho   = CIC assignment of the masses to an n_mesh^3 periodic mesh (mesh
+ *           points at (i, j, k) L / n_mesh), mass per cell / h^3
+ *   phi^  = -4 pi G rho^ exp(-k^2 r_s^2) / k^2 / W(k)^2,  phi^(0) = 0,
+ *           W(k) = prod_d sinc(pi n_d / n_mesh)^2 the CIC window
+ *   phi   = inverse transform of phi^ on the mesh
+ *   F_d   = -dphi/dx_d on the mesh by the fourth-order central difference
+ *           [8 (phi(i - e_d) - phi(i + e_d)) - (phi(i - 2 e_d) - phi(i + 2 e_d))] / 12h
+ *   a_i   = CIC interpolation of F at particle i (the assignment weights)
+ *
+ * The two 3D FFTs are hipFFT's; everything else is this library's kernels.
+ *
+ * pm_create -- mesh workspace (about 16 n_mesh^3 bytes plus hipFFT's work
+ *   area) and FFT plans on the
+ *   current device.  n_mesh even, in [2, 2048].  *pm is NULL on failure.
+ */
+typedef struct sr_pm sr_pm;
+int pm_create(int32_t n_mesh, sr_pm** pm);
+
+/*
+ * pm_accel -- long-range accelerations of all n particles.
+ *
+ *   pos   DEVICE double[n*3]  positions (any real values, wrapped into the box; a
+ *                             non-finite coordinate is taken as 0, not reported)
+ *   mass  DEVICE double[n]
+ *   acc   DEVICE double[n*3]  output, input order, overwritten
+ *   box   L > 0;  r_s the split scale (> 0), the same as the short-range call's
+ *
+ * Work is enqueued on `stream`; the host does not wait.  The mass assignment
+ * uses device atomics, so the low bits may differ from run to run.  Calls on
+ * one handle must not overlap (the mesh is shared).  SR_ESTATE for a handle of
+ * another device.
+ */
+int pm_accel(sr_pm* pm, const double* pos, const double* mass, int64_t n, double box, double r_s,
+             double G, double* acc, void* stream);
+
+/*
+ * pm_accel_adjoint -- gradient of L = sum_i w_i . a_i, a the pm_accel
+ * accelerations of the same arguments, with respect to the positions and the
+ * masses.  With W_j(c) the CIC weights, D_d the difference rule above (an odd
+ * operator) and K the filtered Green's convolution (a symmetric one):
+ *
+ *   omega_d = sum_i w_i,d W_i        (the weights assigned to the mesh)
+ *   psi     = -K sum_d D_d omega_d
+ *   dmass_j = sum_c W_j(c) psi(c) / h^3
+ *   dpos_j  = sum_d w_j,d sum_c grad W_j(c) F_d(c) + m_j / h^3 sum_c grad W_j(c) psi(c)
+ *
+ * grad W is the derivative inside a mesh cell (the CIC weights are piecewise
+ * linear); the second term of dpos is particle j as a source, the first as a
+ * target.
+ *
+ *   w      DEVICE double[n*3]  the cotangent of acc
+ *   dpos   DEVICE double[n*3]  output dL/dpos, overwritten
+ *   dmass  DEVICE double[n]    output dL/dmass, overwritten
+ *
+ * The other arguments, the stream and the host behaviour are pm_accel's.  The
+ * first call on a handle allocates two more n_mesh^3 meshes (16 n_mesh^3 bytes),
+ * kept until pm_free; SR_ENOMEM if that fails.
+ */
+int pm_accel_adjoint(sr_pm* pm, const double* pos, const double* mass, int64_t n, double box, double r_s,
+                     double G, const double* w, double* dpos, double* dmass, void* stream);
+
+/* pm_free -- waits for the device and releases the handle (NULL is ignored). */
+void pm_free(sr_pm* pm);
 
 #ifdef __cplusplus
 }

@@ -24,7 +24,7 @@ from . import _lib
 from ._lib import SrgravError  # noqa: F401
 
 __all__ = ["Tree", "tree_build", "shortrange_accel", "shortrange_accel_adjoint", "ShortRangeAccel",
-           "kdk_rollout", "SrgravError"]
+           "kdk_rollout", "SrgravError", "PM", "PMAccel", "pm_accel", "pm_accel_adjoint"]
 
 
 def _dev_f64(x, n=None, name="tensor"):
@@ -173,6 +173,93 @@ class ShortRangeAccel(torch.autograd.Function):
         dx, dm = shortrange_accel_adjoint(ctx.tree, ctx.params, grad.contiguous(), active=ctx.active,
                                           a_old=ctx.a_old)
         return dx.to(ctx.pos_dtype), dm.to(ctx.mass_dtype), None, None, None, None, None
+
+
+class PM:
+    """An sr_pm handle: mesh workspace and FFT plans of one n_mesh^3 periodic mesh."""
+
+    def __init__(self, n_mesh: int):
+        self._h = C.c_void_p(None)
+        self.n_mesh = int(n_mesh)
+        _lib.check(_lib.lib().pm_create(self.n_mesh, C.byref(self._h)))
+        self.device = torch.device("cuda", torch.cuda.current_device())
+
+    def __del__(self):
+        try:
+            if self._h:
+                _lib.lib().pm_free(self._h)
+                self._h = C.c_void_p(None)
+        except Exception:
+            pass
+
+    def accel(self, pos, mass, *, box: float, r_s: float, G: float = 1.0):
+        """Long-range (PM) accelerations (N, 3) float64 of all particles, input order."""
+        pos = _dev_f64(pos, name="pos")
+        n = pos.shape[0]
+        if pos.shape != (n, 3):
+            raise ValueError("pos must have shape (N, 3)")
+        mass = torch.as_tensor(mass, dtype=torch.float64, device=pos.device)
+        mass = mass.expand(n).contiguous() if mass.dim() == 0 else mass.contiguous()
+        acc = torch.empty((n, 3), dtype=torch.float64, device=pos.device)
+        with torch.cuda.device(pos.device):
+            _lib.check(_lib.lib().pm_accel(self._h, _lib.ptr(pos), _lib.ptr(mass), n, float(box), float(r_s),
+                                           float(G), _lib.ptr(acc), _lib.stream_handle()))
+        return acc
+
+    def accel_adjoint(self, pos, mass, w, *, box: float, r_s: float, G: float = 1.0):
+        """(dL/dpos (N, 3), dL/dmass (N,)) float64 of L = sum(w * accel(pos, mass))."""
+        pos = _dev_f64(pos, name="pos")
+        n = pos.shape[0]
+        if pos.shape != (n, 3):
+            raise ValueError("pos must have shape (N, 3)")
+        mass = torch.as_tensor(mass, dtype=torch.float64, device=pos.device)
+        mass = mass.expand(n).contiguous() if mass.dim() == 0 else mass.contiguous()
+        w = _dev_f64(w, name="w")
+        if w.shape != (n, 3):
+            raise ValueError("w must have shape (N, 3)")
+        dpos = torch.empty((n, 3), dtype=torch.float64, device=pos.device)
+        dmass = torch.empty(n, dtype=torch.float64, device=pos.device)
+        with torch.cuda.device(pos.device):
+            _lib.check(_lib.lib().pm_accel_adjoint(self._h, _lib.ptr(pos), _lib.ptr(mass), n, float(box), float(r_s),
+                                                   float(G), _lib.ptr(w), _lib.ptr(dpos), _lib.ptr(dmass),
+                                                   _lib.stream_handle()))
+        return dpos, dmass
+
+
+def _pm_handle(pm, n_mesh):
+    h = pm if pm is not None else PM(n_mesh)
+    if h.n_mesh != n_mesh:
+        raise ValueError(f"pm handle has n_mesh {h.n_mesh}, not {n_mesh}")
+    return h
+
+
+def pm_accel_adjoint(pos, mass, w, *, box: float, n_mesh: int, r_s: float, G: float = 1.0, pm: PM | None = None):
+    """(dL/dpos (N, 3), dL/dmass (N,)) of L = sum(w * pm_accel(pos, mass, ...))."""
+    return _pm_handle(pm, n_mesh).accel_adjoint(pos, mass, w, box=box, r_s=r_s, G=G)
+
+
+class PMAccel(torch.autograd.Function):
+    """Differentiable PM accelerations: PMAccel.apply(pos, mass, pm, box, r_s[, G])."""
+
+    @staticmethod
+    def forward(ctx, pos, mass, pm, box, r_s, G=1.0):
+        ctx.save_for_backward(pos, mass)
+        ctx.args = (pm, float(box), float(r_s), float(G))
+        ctx.dtypes = (pos.dtype, mass.dtype)
+        return pm.accel(pos, mass, box=box, r_s=r_s, G=G)
+
+    @staticmethod
+    def backward(ctx, grad):
+        pos, mass = ctx.saved_tensors
+        pm, box, r_s, G = ctx.args
+        dx, dm = pm.accel_adjoint(pos, mass, grad, box=box, r_s=r_s, G=G)
+        dm = dm if mass.dim() > 0 else dm.sum()
+        return dx.to(ctx.dtypes[0]), dm.to(ctx.dtypes[1]), None, None, None, None
+
+
+def pm_accel(pos, mass, *, box: float, n_mesh: int, r_s: float, G: float = 1.0, pm: PM | None = None):
+    """Long-range (PM) accelerations on an n_mesh^3 mesh (pass `pm` to reuse its plans)."""
+    return _pm_handle(pm, n_mesh).accel(pos, mass, box=box, r_s=r_s, G=G)
 
 
 def kdk_rollout(*args, **kwargs):

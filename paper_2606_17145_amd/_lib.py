@@ -21,8 +21,9 @@ PRECISIONS = {"fp64": SR_FP64, "fp32": SR_FP32, "fp32_acc64": SR_FP32_ACC64}
 CRITERIA = {"bh": SR_OPEN_BH, "relative": SR_OPEN_RELATIVE}
 EXPORTED = ("tree_build", "shortrange_accel", "shortrange_accel_adjoint", "tree_node_count",
             "tree_export", "tree_free", "srgrav_last_error", "sr_axpy", "srgrav_timing",
-            "srgrav_timing_read", "tree_walk_stats")
-PHASES = ("tree_build", "traverse", "eval", "reduce", "adjoint_eval", "adjoint_reduce", "pushdown")
+            "srgrav_timing_read", "tree_walk_stats", "pm_create", "pm_accel", "pm_accel_adjoint", "pm_free")
+PHASES = ("tree_build", "traverse", "eval", "reduce", "adjoint_eval", "adjoint_reduce", "pushdown",
+          "pm_deposit", "pm_fft", "pm_green", "pm_interp", "pm_stencil", "pm_adj_gather")
 
 
 class SrgravError(RuntimeError):
@@ -70,6 +71,14 @@ def lib():
         L.tree_walk_stats.restype = C.c_int
         L.tree_free.argtypes = [vp]
         L.tree_free.restype = None
+        L.pm_create.argtypes = [C.c_int32, C.POINTER(vp)]
+        L.pm_create.restype = C.c_int
+        L.pm_accel.argtypes = [vp, vp, vp, i64, d, d, d, vp, vp]
+        L.pm_accel.restype = C.c_int
+        L.pm_accel_adjoint.argtypes = [vp, vp, vp, i64, d, d, d, vp, vp, vp, vp]
+        L.pm_accel_adjoint.restype = C.c_int
+        L.pm_free.argtypes = [vp]
+        L.pm_free.restype = None
         L.srgrav_last_error.restype = C.c_char_p
         for name in ("tree_build", "shortrange_accel", "shortrange_accel_adjoint", "tree_node_count",
                      "tree_export"):

@@ -8,7 +8,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB_PATH = os.path.join(PKG, "libsrgrav.so")
-SOURCES = ["api.hip", "build.hip", "walk.hip"]
+SOURCES = ["api.hip", "build.hip", "walk.hip", "pm.hip"]
 
 # -ffp-contract=off: the FP64 decisions and moment folds are reproduced bit for
 # bit, so nothing may be fused behind the source's back (FP32 code asks for FMA
@@ -29,7 +29,9 @@ def build(verbose: bool = False) -> str:
         subprocess.run(cmd, check=True)
         objs.append(obj)
     tmp = LIB_PATH + ".tmp"
-    subprocess.run(["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp], check=True)
+    # hipFFT provides the PM mesh's 3D FFTs
+    subprocess.run(["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp,
+                    "-L/opt/rocm/lib", "-lhipfft", "-Wl,-rpath,/opt/rocm/lib"], check=True)
     os.replace(tmp, LIB_PATH)
     for o in objs:
         os.remove(o)
