@@ -204,6 +204,44 @@ def pm_adjoint(pos: np.ndarray, mass: np.ndarray, box: float, n_mesh: int, r_s: 
     return dpos, dmass
 
 
+def pm_accel_torch(x, mass, box: float, n_mesh: int, r_s: float, G: float = 1.0):
+    """The same PM accelerations in PyTorch FP64 (CPU), differentiable in x and mass
+    by autograd: an independent route to the gradient that pm_adjoint composes by
+    hand.  Inside a mesh cell the CIC weights are linear in x, and the cell index is
+    held fixed (floor carries no gradient)."""
+    import torch
+    x = torch.as_tensor(x, dtype=torch.float64)
+    mass = torch.as_tensor(mass, dtype=torch.float64)
+    n = n_mesh
+    h = box / n
+    u = x / box
+    u = u - torch.floor(u).detach()
+    s = u * n
+    lo = torch.floor(s).detach()
+    f = s - lo
+    i0 = lo.long() % n
+    green = torch.as_tensor(potential_spectrum(np.ones((n, n, n // 2 + 1), dtype=np.complex128), box, r_s, G))
+    corners = []
+    for cx in (0, 1):
+        for cy in (0, 1):
+            for cz in (0, 1):
+                wgt = ((f[:, 0] if cx else 1 - f[:, 0]) * (f[:, 1] if cy else 1 - f[:, 1])
+                       * (f[:, 2] if cz else 1 - f[:, 2]))
+                flat = (((i0[:, 0] + cx) % n) * n + (i0[:, 1] + cy) % n) * n + (i0[:, 2] + cz) % n
+                corners.append((wgt, flat))
+    rho = torch.zeros(n ** 3, dtype=torch.float64)
+    for wgt, flat in corners:
+        rho = rho.index_add(0, flat, mass * wgt / h ** 3)
+    phi = torch.fft.irfftn(torch.fft.rfftn(rho.view(n, n, n)) * green, s=(n, n, n), dim=(0, 1, 2))
+    acc = []
+    for d in range(3):
+        F = (8.0 * (torch.roll(phi, 1, d) - torch.roll(phi, -1, d))
+             - (torch.roll(phi, 2, d) - torch.roll(phi, -2, d))) / (12.0 * h)
+        Ff = F.reshape(-1)
+        acc.append(sum(wgt * Ff[flat] for wgt, flat in corners))
+    return torch.stack(acc, dim=1)
+
+
 def long_range_pair(d: np.ndarray, m: float, r_s: float, G: float = 1.0) -> np.ndarray:
     """Acceleration of a test particle at separation vector d (N, 3) from a point mass m
     under the long-range part of the split alone, in infinite space (no images):

@@ -16,54 +16,69 @@ import numpy as np
 import torch
 
 from . import oracle as O
+from . import pm as PM
 from .frozen import frozen_loss
 
 
-def accel(x, mass, eps, params, box=1.0):
+def _mass_array(mass, n):
+    return np.broadcast_to(np.asarray(mass, np.float64), (n,)).copy()
+
+
+def accel(x, mass, eps, params, box=1.0, n_mesh=None):
+    """Short-range tree force, plus the PM long-range force on an n_mesh^3 mesh
+    (same r_s and G) when n_mesh is given: the whole TreePM force."""
     t = O.Tree(x, mass, eps, box)
     a, _ = O.walk(t, params)
+    if n_mesh:
+        a = a + PM.pm_accel(x, _mass_array(mass, len(x)), box, n_mesh, params["r_s"], params.get("G", 1.0))
     return a, t
 
 
-def rollout(x0, v0, mass, eps, params, n_steps, dt, box=1.0):
+def rollout(x0, v0, mass, eps, params, n_steps, dt, box=1.0, n_mesh=None):
     x = np.array(x0, dtype=np.float64)
     v = np.array(v0, dtype=np.float64)
-    a, _ = accel(x, mass, eps, params, box)
+    a, _ = accel(x, mass, eps, params, box, n_mesh)
     for _ in range(n_steps):
         v = v + 0.5 * dt * a
         x = x + dt * v
-        a, _ = accel(x, mass, eps, params, box)
+        a, _ = accel(x, mass, eps, params, box, n_mesh)
         v = v + 0.5 * dt * a
     return x, v
 
 
-def rollout_grad(x0, v0, mass, eps, params, n_steps, dt, wx, box=1.0):
+def _adjoint(t, x, mass, params, w, box, n_mesh):
+    g, _ = O.adjoint(t, params, w)
+    if n_mesh:
+        g = g + PM.pm_adjoint(x, _mass_array(mass, len(x)), box, n_mesh, params["r_s"], w, params.get("G", 1.0))[0]
+    return g
+
+
+def rollout_grad(x0, v0, mass, eps, params, n_steps, dt, wx, box=1.0, n_mesh=None):
     """dL/dx0, dL/dv0 of L = sum(wx . x_final) with the decisions of every force
-    evaluation frozen (the oracle's adjoint at each evaluation)."""
+    evaluation frozen (the oracle's adjoint at each evaluation, plus the PM
+    adjoint when n_mesh is given)."""
     xs, vs = [np.array(x0, dtype=np.float64)], [np.array(v0, dtype=np.float64)]
     for _ in range(n_steps):
-        x, v = rollout(xs[-1], vs[-1], mass, eps, params, 1, dt, box)
+        x, v = rollout(xs[-1], vs[-1], mass, eps, params, 1, dt, box, n_mesh)
         xs.append(x)
         vs.append(v)
     xb = np.array(wx, dtype=np.float64)
     vb = np.zeros_like(xb)
     for k in reversed(range(n_steps)):
-        a0, t0 = accel(xs[k], mass, eps, params, box)
+        a0, t0 = accel(xs[k], mass, eps, params, box, n_mesh)
         vh = vs[k] + 0.5 * dt * a0
         x1 = xs[k] + dt * vh
-        _, t1 = accel(x1, mass, eps, params, box)
-        g1, _ = O.adjoint(t1, params, 0.5 * dt * vb)
-        xb = xb + g1
+        _, t1 = accel(x1, mass, eps, params, box, n_mesh)
+        xb = xb + _adjoint(t1, x1, mass, params, 0.5 * dt * vb, box, n_mesh)
         vb = vb + dt * xb
-        g0, _ = O.adjoint(t0, params, 0.5 * dt * vb)
-        xb = xb + g0
+        xb = xb + _adjoint(t0, xs[k], mass, params, 0.5 * dt * vb, box, n_mesh)
     return xb, vb
 
 
-def frozen_replay(x0, v0, mass, eps, params, n_steps, dt, box=1.0):
+def frozen_replay(x0, v0, mass, eps, params, n_steps, dt, box=1.0, n_mesh=None):
     """Returns f(x0_t, v0_t) -> x_final (torch), replaying the rollout with each
     force evaluation's tree topology and interaction lists recorded from the
-    unperturbed run."""
+    unperturbed run (and, with n_mesh, the PM force in PyTorch)."""
     recs = []
     x = np.array(x0, dtype=np.float64)
     v = np.array(v0, dtype=np.float64)
@@ -71,7 +86,7 @@ def frozen_replay(x0, v0, mass, eps, params, n_steps, dt, box=1.0):
     def record(xx):
         t = O.Tree(xx, mass, eps, box)
         starts, ent = O.interaction_lists(t, params)
-        a, _ = O.walk(t, params)
+        a, _ = accel(xx, mass, eps, params, box, n_mesh)
         recs.append((t, starts, ent))
         return a
 
@@ -88,6 +103,8 @@ def frozen_replay(x0, v0, mass, eps, params, n_steps, dt, box=1.0):
         t, starts, ent = recs[k]
         xw = xt - box * torch.floor(xt / box).detach()
         _, acc = frozen_loss(t, starts, ent, tg, xw, m_t, params, np.zeros((x.shape[0], 3)))
+        if n_mesh:
+            acc = acc + PM.pm_accel_torch(xt, m_t, box, n_mesh, params["r_s"], params.get("G", 1.0))
         return acc
 
     def f(x0_t, v0_t):

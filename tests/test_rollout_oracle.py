@@ -42,3 +42,42 @@ def test_rollout_gradient_matches_autograd_of_frozen_replay(oracle):
     assert np.allclose(gv, vt.grad.numpy(), rtol=1e-9, atol=1e-10 * np.abs(gv).max())
     # the rollout is not the identity map: the force terms matter in the gradient
     assert np.abs(gx - wx).max() > 1e-6 * np.abs(wx).max()
+
+
+def test_pm_autograd_agrees_with_forward_and_adjoint():
+    # the PyTorch PM gives the same forces, and autograd through it the same
+    # gradient that pm_adjoint composes from the transposed steps
+    from oracle import pm
+    rng = np.random.default_rng(33)
+    x = rng.uniform(-0.5, 1.5, (50, 3))
+    m = rng.uniform(0.5, 1.5, 50)
+    w = rng.standard_normal((50, 3))
+    xt = torch.tensor(x, requires_grad=True)
+    mt = torch.tensor(m, requires_grad=True)
+    a = pm.pm_accel_torch(xt, mt, 1.0, 12, 1.25 / 12)
+    ref = pm.pm_accel(x, m, 1.0, 12, 1.25 / 12)
+    assert np.abs(a.detach().numpy() - ref).max() <= 1e-12 * np.abs(ref).max()
+    (torch.tensor(w) * a).sum().backward()
+    dx, dm = pm.pm_adjoint(x, m, 1.0, 12, 1.25 / 12, w)
+    assert np.abs(xt.grad.numpy() - dx).max() <= 1e-11 * np.abs(dx).max()
+    assert np.abs(mt.grad.numpy() - dm).max() <= 1e-11 * np.abs(dm).max()
+
+
+def test_treepm_rollout_gradient_matches_autograd_of_frozen_replay(oracle):
+    # short-range tree force plus the PM force on a 14^3 mesh (r_s = 1.25 L / 14)
+    from oracle import rollout as R
+    x, v, m, eps, p = _case(n=160, seed=34)
+    wx = np.random.default_rng(35).standard_normal(x.shape)
+    gx, gv = R.rollout_grad(x, v, m, eps, p, 2, 2e-3, wx, n_mesh=14)
+    f = R.frozen_replay(x, v, m, eps, p, 2, 2e-3, n_mesh=14)
+    xt = torch.tensor(x, requires_grad=True)
+    vt = torch.tensor(v, requires_grad=True)
+    xf, _ = f(xt, vt)
+    xr, _ = R.rollout(x, v, m, eps, p, 2, 2e-3, n_mesh=14)
+    assert np.allclose(xf.detach().numpy(), xr, rtol=0, atol=1e-13)
+    (torch.tensor(wx) * xf).sum().backward()
+    assert np.allclose(gx, xt.grad.numpy(), rtol=1e-9, atol=1e-10 * np.abs(gx).max())
+    assert np.allclose(gv, vt.grad.numpy(), rtol=1e-9, atol=1e-10 * np.abs(gv).max())
+    # the mesh force changes the result
+    xs, _ = R.rollout(x, v, m, eps, p, 2, 2e-3)
+    assert np.abs(xs - xr).max() > 1e-6
