@@ -174,8 +174,20 @@ def main():
     pm_ms = e_pm[0].elapsed_time(e_pm[1]) / reps
     pm_phases = {k: ms / reps for k, (ms, n) in _lib.timing_read().items() if k.startswith("pm_") and n}
     _lib.timing(False)
+    for _ in range(2):
+        pm_dx, pm_dm = pmh.accel_adjoint(pos, mass, cot, box=w.box, r_s=w.r_s)
+    torch.cuda.synchronize()
+    _lib.timing(True)
+    e_pm[0].record()
+    for _ in range(reps):
+        pm_dx, pm_dm = pmh.accel_adjoint(pos, mass, cot, box=w.box, r_s=w.r_s)
+    e_pm[1].record()
+    torch.cuda.synchronize()
+    pm_adj_ms = e_pm[0].elapsed_time(e_pm[1]) / reps
+    pm_adj_phases = {k: ms / reps for k, (ms, n) in _lib.timing_read().items() if k.startswith("pm_") and n}
+    _lib.timing(False)
     del pmh
-    log(f"bench: pm 128^3 {pm_ms:.3f} ms {pm_phases}")
+    log(f"bench: pm 128^3 {pm_ms:.3f} ms {pm_phases}; adjoint {pm_adj_ms:.3f} ms")
 
     out = {
         "metric": METRIC,
@@ -207,7 +219,8 @@ def main():
     out["kernel_ms_per_launch"] = avg
     out["walk_stats"] = stats
     out["pm_long_range"] = {"n_mesh": 128, "ms_per_call": pm_ms, "phases_ms_per_call": pm_phases,
-                            "particles_per_s": w.n / (pm_ms * 1e-3)}
+                            "particles_per_s": w.n / (pm_ms * 1e-3), "adjoint_ms_per_call": pm_adj_ms,
+                            "adjoint_phases_ms_per_call": pm_adj_phases}
     work = {"eval": FLOP_PER_INTERACTION * inter,
             "adjoint_eval": FLOP_PER_ADJOINT_INTERACTION * inter,
             "traverse": FLOP_PER_NODE_TEST * stats["node_tests"]}

@@ -180,13 +180,14 @@ enum {
     SR_T_ADJ_EVAL = 4,     /* adjoint pair terms */
     SR_T_ADJ_REDUCE = 5,   /* per-target adjoint sums */
     SR_T_PUSHDOWN = 6,     /* node adjoints to particles */
-    SR_T_PM_DEPOSIT = 7,   /* PM: mesh clear and CIC mass assignment */
+    SR_T_PM_DEPOSIT = 7,   /* PM: mesh clear and CIC assignment (masses, or adjoint weights) */
     SR_T_PM_FFT = 8,       /* PM: one 3D FFT (two per pm_accel) */
     SR_T_PM_GREEN = 9,     /* PM: Green's function applied to the density spectrum */
     SR_T_PM_INTERP = 10,   /* PM: finite-difference force and CIC interpolation */
     SR_T_PM_STENCIL = 11,  /* PM adjoint: transposed difference rule on one weight mesh */
     SR_T_PM_ADJ_GATHER = 12, /* PM adjoint: per-particle position and mass gradients */
-    SR_T_COUNT = 13
+    SR_T_PM_SORT = 13,     /* PM: particles sorted by mesh cell for the assignment */
+    SR_T_COUNT = 14
 };
 int srgrav_timing(int32_t enable);
 int srgrav_timing_read(double* ms, int64_t* calls);

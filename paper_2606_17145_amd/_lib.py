@@ -23,7 +23,7 @@ EXPORTED = ("tree_build", "shortrange_accel", "shortrange_accel_adjoint", "tree_
             "tree_export", "tree_free", "srgrav_last_error", "sr_axpy", "srgrav_timing",
             "srgrav_timing_read", "tree_walk_stats", "pm_create", "pm_accel", "pm_accel_adjoint", "pm_free")
 PHASES = ("tree_build", "traverse", "eval", "reduce", "adjoint_eval", "adjoint_reduce", "pushdown",
-          "pm_deposit", "pm_fft", "pm_green", "pm_interp", "pm_stencil", "pm_adj_gather")
+          "pm_deposit", "pm_fft", "pm_green", "pm_interp", "pm_stencil", "pm_adj_gather", "pm_sort")
 
 
 class SrgravError(RuntimeError):

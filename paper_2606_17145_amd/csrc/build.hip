@@ -8,6 +8,7 @@
 #include <stdio.h>
 
 #include "internal.h"
+#include "sort.h"
 
 namespace {
 
@@ -223,12 +224,16 @@ __global__ void k_scan_tiles(const uint32_t* __restrict__ in, uint32_t* __restri
 // LSD radix sort of 90-bit keys (two 45-bit words) with the original index as payload
 // ------------------------------------------------------------------------------------
 
+// Digit `pass` of a key: with HI, the 96-bit tree key (lo word bits 0..47, then
+// hi word bits 0..47); without, byte `pass` of a single 64-bit key.
+template <bool HI>
 __device__ inline uint32_t rs_digit(uint64_t hi, uint64_t lo, int pass)
 {
+    if (!HI) return (uint32_t)(lo >> (8 * pass)) & 0xffu;
     return pass < 6 ? (uint32_t)(lo >> (8 * pass)) & 0xffu : (uint32_t)(hi >> (8 * (pass - 6))) & 0xffu;
 }
 
-template <int RS_ITEMS>
+template <int RS_ITEMS, bool HI>
 __global__ void k_rs_hist(const uint64_t* __restrict__ hi, const uint64_t* __restrict__ lo, int64_t n,
                           int pass, uint32_t* __restrict__ hist, int64_t nb)
 {
@@ -238,7 +243,7 @@ __global__ void k_rs_hist(const uint64_t* __restrict__ hi, const uint64_t* __res
     int64_t base = blockIdx.x * (int64_t)(TPB * RS_ITEMS);
     for (int r = 0; r < RS_ITEMS; ++r) {
         int64_t i = base + r * TPB + threadIdx.x;
-        if (i < n) atomicAdd(&h[rs_digit(hi[i], lo[i], pass)], 1u);
+        if (i < n) atomicAdd(&h[rs_digit<HI>(HI ? hi[i] : 0, lo[i], pass)], 1u);
     }
     __syncthreads();
     hist[threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
@@ -268,7 +273,7 @@ __global__ void k_rs_digit_scan(uint32_t* __restrict__ hist, int64_t nb, uint32_
 // Stable scatter: within a tile, keys keep their order (rounds in order, waves
 // in order, lanes in order); a tile's offset for digit d is the digit's base
 // (keys with a smaller digit) plus the keys of digit d in earlier tiles.
-template <int RS_ITEMS>
+template <int RS_ITEMS, bool HI>
 __global__ void k_rs_scatter(const uint64_t* __restrict__ hi, const uint64_t* __restrict__ lo,
                              const uint32_t* __restrict__ idx, uint64_t* __restrict__ ohi,
                              uint64_t* __restrict__ olo, uint32_t* __restrict__ oidx, int64_t n,
@@ -290,10 +295,10 @@ __global__ void k_rs_scatter(const uint64_t* __restrict__ hi, const uint64_t* __
         uint64_t h = 0, l = 0;
         uint32_t v = 0, d = 0;
         if (valid) {
-            h = hi[i];
+            if (HI) h = hi[i];
             l = lo[i];
             v = idx[i];
-            d = rs_digit(h, l, pass);
+            d = rs_digit<HI>(h, l, pass);
         }
         uint64_t peers = __ballot(valid);
         for (int b = 0; b < 8; ++b) {
@@ -316,7 +321,7 @@ __global__ void k_rs_scatter(const uint64_t* __restrict__ hi, const uint64_t* __
         s_off[threadIdx.x] += add;
         __syncthreads();
         if (valid) {
-            ohi[p] = h;
+            if (HI) ohi[p] = h;
             olo[p] = l;
             oidx[p] = v;
         }
@@ -746,6 +751,47 @@ int sr_scan_exclusive(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* tm
     return SR_OK;
 }
 
+namespace {
+
+template <int ITEMS>
+void sort64_pass(uint64_t* const keys[2], uint32_t* const idx[2], int cur, int64_t n, int pass, uint32_t* hist,
+                 int64_t nb, hipStream_t st)
+{
+    const dim3 gb((unsigned)nb), tb(TPB);
+    uint32_t* tot = hist + 256 * nb;
+    hipLaunchKernelGGL((k_rs_hist<ITEMS, false>), gb, tb, 0, st, nullptr, keys[cur], n, pass, hist, nb);
+    hipLaunchKernelGGL(k_rs_digit_scan, dim3(256), tb, 0, st, hist, nb, tot);
+    hipLaunchKernelGGL((k_rs_scatter<ITEMS, false>), gb, tb, 0, st, nullptr, keys[cur], idx[cur], nullptr,
+                       keys[cur ^ 1], idx[cur ^ 1], n, pass, hist, nb, tot);
+}
+
+int sort_items(int64_t n) { return n <= 384 * 1024 ? 2 : n <= 1536 * 1024 ? 4 : 8; }
+
+}  // namespace
+
+int64_t sr_sort_hist_words(int64_t n)
+{
+    return 256 * cdiv(n > 0 ? n : 1, (int64_t)TPB * sort_items(n)) + 256 + 1;
+}
+
+int sr_sort_keys64(uint64_t* const keys[2], uint32_t* const idx[2], int64_t n, int passes, uint32_t* hist,
+                   hipStream_t st)
+{
+    const int items = sort_items(n);
+    const int64_t nb = cdiv(n > 0 ? n : 1, (int64_t)TPB * items);
+    for (int pass = 0; pass < passes; ++pass) {
+        const int cur = pass & 1;
+        if (items == 2)
+            sort64_pass<2>(keys, idx, cur, n, pass, hist, nb, st);
+        else if (items == 4)
+            sort64_pass<4>(keys, idx, cur, n, pass, hist, nb, st);
+        else
+            sort64_pass<8>(keys, idx, cur, n, pass, hist, nb, st);
+    }
+    SR_HIP(hipGetLastError());
+    return SR_OK;
+}
+
 int sr_build_device(sr_tree* t, const double* pos, const double* mass, const double* eps,
                     double eps_scalar, hipStream_t st)
 {
@@ -761,21 +807,21 @@ int sr_build_device(sr_tree* t, const double* pos, const double* mass, const dou
     for (int pass = 0; pass < 12; ++pass) {
         const dim3 gb((unsigned)nb), tb(TPB);
         if (items == 2)
-            hipLaunchKernelGGL(k_rs_hist<2>, gb, tb, 0, st, t->khi[cur], t->klo[cur], n, pass, t->hist, nb);
+            hipLaunchKernelGGL((k_rs_hist<2, true>), gb, tb, 0, st, t->khi[cur], t->klo[cur], n, pass, t->hist, nb);
         else if (items == 4)
-            hipLaunchKernelGGL(k_rs_hist<4>, gb, tb, 0, st, t->khi[cur], t->klo[cur], n, pass, t->hist, nb);
+            hipLaunchKernelGGL((k_rs_hist<4, true>), gb, tb, 0, st, t->khi[cur], t->klo[cur], n, pass, t->hist, nb);
         else
-            hipLaunchKernelGGL(k_rs_hist<8>, gb, tb, 0, st, t->khi[cur], t->klo[cur], n, pass, t->hist, nb);
+            hipLaunchKernelGGL((k_rs_hist<8, true>), gb, tb, 0, st, t->khi[cur], t->klo[cur], n, pass, t->hist, nb);
         uint32_t* tot = t->hist + 256 * nb;
         hipLaunchKernelGGL(k_rs_digit_scan, dim3(256), tb, 0, st, t->hist, nb, tot);
         if (items == 2)
-            hipLaunchKernelGGL(k_rs_scatter<2>, gb, tb, 0, st, t->khi[cur], t->klo[cur], t->kidx[cur],
+            hipLaunchKernelGGL((k_rs_scatter<2, true>), gb, tb, 0, st, t->khi[cur], t->klo[cur], t->kidx[cur],
                                t->khi[cur ^ 1], t->klo[cur ^ 1], t->kidx[cur ^ 1], n, pass, t->hist, nb, tot);
         else if (items == 4)
-            hipLaunchKernelGGL(k_rs_scatter<4>, gb, tb, 0, st, t->khi[cur], t->klo[cur], t->kidx[cur],
+            hipLaunchKernelGGL((k_rs_scatter<4, true>), gb, tb, 0, st, t->khi[cur], t->klo[cur], t->kidx[cur],
                                t->khi[cur ^ 1], t->klo[cur ^ 1], t->kidx[cur ^ 1], n, pass, t->hist, nb, tot);
         else
-            hipLaunchKernelGGL(k_rs_scatter<8>, gb, tb, 0, st, t->khi[cur], t->klo[cur], t->kidx[cur],
+            hipLaunchKernelGGL((k_rs_scatter<8, true>), gb, tb, 0, st, t->khi[cur], t->klo[cur], t->kidx[cur],
                                t->khi[cur ^ 1], t->klo[cur ^ 1], t->kidx[cur ^ 1], n, pass, t->hist, nb, tot);
         cur ^= 1;
     }

@@ -18,6 +18,7 @@
 #include <hipfft/hipfft.h>
 
 #include "internal.h"
+#include "sort.h"
 
 #define PM_TRY(call)                     \
     do {                                 \
@@ -35,6 +36,13 @@ struct sr_pm {
     double* axis = nullptr;                   // N: the per-axis filter factor of the Green's function
     double* work = nullptr;                   // N^3, adjoint only: one component of the assigned weights, then psi
     double* chi = nullptr;                    // N^3, adjoint only: the differenced weights
+    // particle workspace, grown on demand: base-cell keys and particle indices
+    // (two buffers each for the radix sort) and the sort's histogram
+    int64_t cap = 0;
+    uint64_t* key[2] = {};
+    uint32_t* idx[2] = {};
+    uint32_t* hist = nullptr;
+    int sorted = 0;                           // the buffer that holds the sorted keys
 };
 
 namespace {
@@ -63,28 +71,68 @@ __global__ void k_pm_clear(double* __restrict__ p, int64_t count)
     if (i < count) p[i] = 0.0;
 }
 
-// Each particle adds v w * scale to its eight mesh points (FP64 atomics), v its
-// value (mass, or one component of the adjoint weights) at val[p * stride].
-__global__ void k_pm_deposit(const double* __restrict__ pos, const double* __restrict__ val, int stride,
-                             int64_t np, double box, int n, double scale, double* __restrict__ mesh)
+// Key of a particle: the linear index of its lower CIC mesh point.
+__global__ void k_pm_keys(const double* __restrict__ pos, int64_t np, double box, int n,
+                          uint64_t* __restrict__ key, uint32_t* __restrict__ idx)
 {
     const int64_t p = blockIdx.x * (int64_t)PM_TPB + threadIdx.x;
     if (p >= np) return;
     int i[3];
     double f[3];
     for (int d = 0; d < 3; ++d) cic_axis(pos[3 * p + d], box, n, i[d], f[d]);
-    const double m = val[p * stride];
+    key[p] = ((uint64_t)i[0] * (uint64_t)n + (uint64_t)i[1]) * (uint64_t)n + (uint64_t)i[2];
+    idx[p] = (uint32_t)p;
+}
+
+// Mass (or weight) assignment in key order: particle idx[q] adds v w * scale to
+// its eight mesh points, v = val[idx[q] * stride].  Lanes of a wave whose
+// particles share a lower mesh point (a run of equal keys) share all eight
+// targets: a segmented sum over the run leaves the totals in its last lane,
+// which alone issues the eight FP64 atomics.  A wave without such runs adds
+// directly.
+__global__ void k_pm_deposit(const double* __restrict__ pos, const double* __restrict__ val, int stride,
+                             const uint64_t* __restrict__ key, const uint32_t* __restrict__ idx, int64_t np,
+                             double box, int n, double scale, double* __restrict__ mesh)
+{
+    const int64_t q = blockIdx.x * (int64_t)PM_TPB + threadIdx.x;
+    const int lane = (int)(threadIdx.x & 63);
+    const bool valid = q < np;
+    const uint64_t k = valid ? key[q] : ~0ull;
+    const uint64_t k_prev = __shfl_up(k, 1);
+    const bool head = !valid || lane == 0 || k != k_prev;
+    const uint64_t heads = __ballot(head);
+    int i[3] = {0, 0, 0};
+    double f[3] = {0.0, 0.0, 0.0}, v = 0.0;
+    if (valid) {
+        const int64_t p = idx[q];
+        for (int d = 0; d < 3; ++d) cic_axis(pos[3 * p + d], box, n, i[d], f[d]);
+        v = val[p * stride] * scale;
+    }
+    double c[8];
+    for (int cx = 0; cx < 2; ++cx)
+        for (int cy = 0; cy < 2; ++cy)
+            for (int cz = 0; cz < 2; ++cz) {
+                const double wx = cx ? f[0] : 1.0 - f[0], wy = cy ? f[1] : 1.0 - f[1], wz = cz ? f[2] : 1.0 - f[2];
+                c[(cx * 2 + cy) * 2 + cz] = v * ((wx * wy) * wz);
+            }
+    bool issue = valid;
+    if (heads != ~0ull) {          // some run spans lanes (uniform over the wave)
+        const uint64_t upto = lane == 63 ? heads : heads & ((2ull << lane) - 1ull);
+        const int start = 63 - __clzll(upto);          // first lane of this lane's run
+        for (int off = 1; off < 64; off <<= 1)
+            for (int r = 0; r < 8; ++r) {
+                const double t = __shfl_up(c[r], off);
+                if (lane - off >= start) c[r] += t;
+            }
+        issue = valid && (lane == 63 || ((heads >> (lane + 1)) & 1ull));
+    }
+    if (!issue) return;
     for (int cx = 0; cx < 2; ++cx) {
-        const double wx = cx ? f[0] : 1.0 - f[0];
         const int64_t ix = (i[0] + cx) % n;
         for (int cy = 0; cy < 2; ++cy) {
-            const double wy = cy ? f[1] : 1.0 - f[1];
             const int64_t iy = (i[1] + cy) % n;
-            for (int cz = 0; cz < 2; ++cz) {
-                const double wz = cz ? f[2] : 1.0 - f[2];
-                const int64_t iz = (i[2] + cz) % n;
-                unsafeAtomicAdd(mesh + (ix * n + iy) * n + iz, m * ((wx * wy) * wz) * scale);
-            }
+            for (int cz = 0; cz < 2; ++cz)
+                unsafeAtomicAdd(mesh + (ix * n + iy) * n + (i[2] + cz) % n, c[(cx * 2 + cy) * 2 + cz]);
         }
     }
 }
@@ -141,11 +189,15 @@ __device__ inline double fd4(double p0, double p1, double p3, double p4)
 // a_i = scale * sum over the eight CIC mesh points c of w_c * fd4 along each
 // axis at c.  Along axis d the two corners that differ in d share one line of
 // six potential values (offsets -2..+3 from the lower corner).
-__global__ void k_pm_interp(const double* __restrict__ pos, int64_t np, double box, int n,
-                            const double* __restrict__ phi, double scale, double* __restrict__ acc)
+// Particles are taken in key order (idx), so the lanes of a wave read nearby
+// mesh points.
+__global__ void k_pm_interp(const double* __restrict__ pos, const uint32_t* __restrict__ order, int64_t np,
+                            double box, int n, const double* __restrict__ phi, double scale,
+                            double* __restrict__ acc)
 {
-    const int64_t p = blockIdx.x * (int64_t)PM_TPB + threadIdx.x;
-    if (p >= np) return;
+    const int64_t q = blockIdx.x * (int64_t)PM_TPB + threadIdx.x;
+    if (q >= np) return;
+    const int64_t p = order[q];
     int i[3];
     double f[3];
     for (int d = 0; d < 3; ++d) cic_axis(pos[3 * p + d], box, n, i[d], f[d]);
@@ -194,12 +246,14 @@ __global__ void k_pm_stencil(const double* __restrict__ a, double* __restrict__ 
 // phi and psi are the unnormalised potential and adjoint meshes, so one scale
 // 1 / (12 h N^3) covers both.
 __global__ void k_pm_adjoint_gather(const double* __restrict__ pos, const double* __restrict__ mass,
-                                    const double* __restrict__ w, int64_t np, double box, int n,
-                                    const double* __restrict__ phi, const double* __restrict__ psi, double scale,
-                                    double inv_h3, double* __restrict__ dpos, double* __restrict__ dmass)
+                                    const double* __restrict__ w, const uint32_t* __restrict__ order, int64_t np,
+                                    double box, int n, const double* __restrict__ phi,
+                                    const double* __restrict__ psi, double scale, double inv_h3,
+                                    double* __restrict__ dpos, double* __restrict__ dmass)
 {
-    const int64_t p = blockIdx.x * (int64_t)PM_TPB + threadIdx.x;
-    if (p >= np) return;
+    const int64_t q = blockIdx.x * (int64_t)PM_TPB + threadIdx.x;
+    if (q >= np) return;
+    const int64_t p = order[q];          // key order, as in the interpolation
     int i[3];
     double f[3];
     for (int d = 0; d < 3; ++d) cic_axis(pos[3 * p + d], box, n, i[d], f[d]);
@@ -264,6 +318,15 @@ void pm_release(sr_pm* m)
     (void)hipFree(m->axis);
     (void)hipFree(m->work);
     (void)hipFree(m->chi);
+    for (int b = 0; b < 2; ++b) {
+        (void)hipFree(m->key[b]);
+        (void)hipFree(m->idx[b]);
+        m->key[b] = nullptr;
+        m->idx[b] = nullptr;
+    }
+    (void)hipFree(m->hist);
+    m->hist = nullptr;
+    m->cap = 0;
     m->mesh = nullptr;
     m->spec = nullptr;
     m->axis = nullptr;
@@ -322,6 +385,7 @@ int pm_check(sr_pm* m, const char* fn, const double* pos, const double* mass, in
     if (n < 0 || (n > 0 && (!pos || !mass))) return sr_fail(SR_EINVAL, "%s: bad particle arrays", fn);
     if (!(box > 0.0 && isfinite(box))) return sr_fail(SR_EINVAL, "%s: box must be finite and > 0", fn);
     if (!(r_s > 0.0 && isfinite(r_s) && isfinite(G))) return sr_fail(SR_EINVAL, "%s: r_s > 0 and finite G required", fn);
+    if (n > INT32_MAX) return sr_fail(SR_EINVAL, "%s: at most 2^31 - 1 particles", fn);
     int dev = 0;
     SR_HIP(hipGetDevice(&dev));
     if (dev != m->device) return sr_fail(SR_ESTATE, "%s: handle belongs to device %d, current is %d", fn, m->device, dev);
@@ -354,18 +418,63 @@ int pm_convolve(sr_pm* m, double* src, double* dst, double box, double r_s, doub
     return SR_OK;
 }
 
-// m->mesh = N^3 times the long-range potential of the particles.
+// Particle workspace for n particles; a larger n frees and reallocates it (the
+// free waits for the device).
+int pm_reserve(sr_pm* m, int64_t n, const char* fn)
+{
+    if (n <= m->cap) return SR_OK;
+    if (m->cap > 0) SR_HIP(hipDeviceSynchronize());     // earlier calls may still use the buffers
+    for (int b = 0; b < 2; ++b) {
+        (void)hipFree(m->key[b]);
+        (void)hipFree(m->idx[b]);
+        m->key[b] = nullptr;
+        m->idx[b] = nullptr;
+    }
+    (void)hipFree(m->hist);
+    m->hist = nullptr;
+    m->cap = 0;
+    bool ok = hipMalloc((void**)&m->hist, sizeof(uint32_t) * sr_sort_hist_words(n)) == hipSuccess;
+    for (int b = 0; b < 2 && ok; ++b)
+        ok = hipMalloc((void**)&m->key[b], sizeof(uint64_t) * n) == hipSuccess &&
+             hipMalloc((void**)&m->idx[b], sizeof(uint32_t) * n) == hipSuccess;
+    if (!ok) return sr_fail(SR_ENOMEM, "%s: device allocation for %lld particles failed", fn, (long long)n);
+    m->cap = n;
+    return SR_OK;
+}
+
+// Deposit val (stride apart, times scale) into `mesh`, cleared first, in the
+// key order of the last pm_sort.
+void pm_deposit(sr_pm* m, const double* pos, const double* val, int stride, int64_t n, double box, double scale,
+                double* mesh, hipStream_t st)
+{
+    const int N = m->n;
+    const int64_t n3 = (int64_t)N * N * N;
+    sr_timing_mark(SR_T_PM_DEPOSIT, true, st);
+    hipLaunchKernelGGL(k_pm_clear, pm_grid(n3), dim3(PM_TPB), 0, st, mesh, n3);
+    hipLaunchKernelGGL(k_pm_deposit, pm_grid(n), dim3(PM_TPB), 0, st, pos, val, stride, m->key[m->sorted],
+                       m->idx[m->sorted], n, box, N, scale, mesh);
+    sr_timing_mark(SR_T_PM_DEPOSIT, false, st);
+}
+
+// Sort the particles by lower mesh point, then m->mesh = N^3 times their
+// long-range potential.
 int pm_potential(sr_pm* m, const double* pos, const double* mass, int64_t n, double box, double r_s, double G,
                  hipStream_t st, const char* fn)
 {
     const int N = m->n;
-    const int64_t n3 = (int64_t)N * N * N;
     const double h = box / N;
-    sr_timing_mark(SR_T_PM_DEPOSIT, true, st);
-    hipLaunchKernelGGL(k_pm_clear, pm_grid(n3), dim3(PM_TPB), 0, st, m->mesh, n3);
-    hipLaunchKernelGGL(k_pm_deposit, pm_grid(n), dim3(PM_TPB), 0, st, pos, mass, 1, n, box, N, 1.0 / (h * h * h),
-                       m->mesh);
-    sr_timing_mark(SR_T_PM_DEPOSIT, false, st);
+    PM_TRY(pm_reserve(m, n, fn));
+    const uint64_t n3 = (uint64_t)N * N * N;
+    int bits = 1;
+    while (bits < 64 && (n3 - 1) >> bits) ++bits;
+    const int passes = (bits + 7) / 8;
+    sr_timing_mark(SR_T_PM_SORT, true, st);
+    hipLaunchKernelGGL(k_pm_keys, pm_grid(n), dim3(PM_TPB), 0, st, pos, n, box, N, m->key[0], m->idx[0]);
+    SR_HIP(hipGetLastError());
+    PM_TRY(sr_sort_keys64(m->key, m->idx, n, passes, m->hist, st));
+    sr_timing_mark(SR_T_PM_SORT, false, st);
+    m->sorted = passes & 1;
+    pm_deposit(m, pos, mass, 1, n, box, 1.0 / (h * h * h), m->mesh, st);
     SR_HIP(hipGetLastError());
     return pm_convolve(m, m->mesh, m->mesh, box, r_s, G, st, fn);
 }
@@ -385,7 +494,7 @@ int pm_accel(sr_pm* m, const double* pos, const double* mass, int64_t n, double 
     const double h = box / N;
     PM_TRY(pm_potential(m, pos, mass, n, box, r_s, G, st, "pm_accel"));
     sr_timing_mark(SR_T_PM_INTERP, true, st);
-    hipLaunchKernelGGL(k_pm_interp, pm_grid(n), dim3(PM_TPB), 0, st, pos, n, box, N, m->mesh,
+    hipLaunchKernelGGL(k_pm_interp, pm_grid(n), dim3(PM_TPB), 0, st, pos, m->idx[m->sorted], n, box, N, m->mesh,
                        1.0 / (12.0 * h * (double)N * N * N), acc);
     sr_timing_mark(SR_T_PM_INTERP, false, st);
     SR_HIP(hipGetLastError());
@@ -414,10 +523,7 @@ int pm_accel_adjoint(sr_pm* m, const double* pos, const double* mass, int64_t n,
     PM_TRY(pm_potential(m, pos, mass, n, box, r_s, G, st, "pm_accel_adjoint"));
     // chi = -sum_d fd4_d (the weights' component d assigned to the mesh)
     for (int d = 0; d < 3; ++d) {
-        sr_timing_mark(SR_T_PM_DEPOSIT, true, st);
-        hipLaunchKernelGGL(k_pm_clear, pm_grid(n3), dim3(PM_TPB), 0, st, m->work, n3);
-        hipLaunchKernelGGL(k_pm_deposit, pm_grid(n), dim3(PM_TPB), 0, st, pos, w + d, 3, n, box, N, 1.0, m->work);
-        sr_timing_mark(SR_T_PM_DEPOSIT, false, st);
+        pm_deposit(m, pos, w + d, 3, n, box, 1.0, m->work, st);
         sr_timing_mark(SR_T_PM_STENCIL, true, st);
         hipLaunchKernelGGL(k_pm_stencil, pm_grid(n3), dim3(PM_TPB), 0, st, m->work, m->chi, N, d, d > 0 ? 1 : 0);
         sr_timing_mark(SR_T_PM_STENCIL, false, st);
@@ -425,7 +531,8 @@ int pm_accel_adjoint(sr_pm* m, const double* pos, const double* mass, int64_t n,
     }
     PM_TRY(pm_convolve(m, m->chi, m->work, box, r_s, G, st, "pm_accel_adjoint"));
     sr_timing_mark(SR_T_PM_ADJ_GATHER, true, st);
-    hipLaunchKernelGGL(k_pm_adjoint_gather, pm_grid(n), dim3(PM_TPB), 0, st, pos, mass, w, n, box, N, m->mesh,
+    hipLaunchKernelGGL(k_pm_adjoint_gather, pm_grid(n), dim3(PM_TPB), 0, st, pos, mass, w, m->idx[m->sorted], n,
+                       box, N, m->mesh,
                        m->work, 1.0 / (12.0 * h * (double)n3), 1.0 / (h * h * h), dpos, dmass);
     sr_timing_mark(SR_T_PM_ADJ_GATHER, false, st);
     SR_HIP(hipGetLastError());

@@ -15,9 +15,14 @@ the transposed step:
     x'bar += A'(x')^T (dt/2 v'bar),  v_half bar = v'bar + dt x'bar,
     x bar  = x'bar + A'(x)^T (dt/2 v_half bar),  v bar = v_half bar.
 
-Every arithmetic step runs in the HIP library: the force and its adjoint
-(shortrange_accel / shortrange_accel_adjoint) and the elementwise updates
-(sr_axpy).  This module only sequences the calls and holds the checkpoints.
+With a PM handle (`pm`), a(x) is the whole TreePM force: the short-range tree
+force plus the PM long-range force of the same r_s and G, and each adjoint
+adds pm_accel_adjoint's position gradient.
+
+Every arithmetic step runs in the HIP library: the forces and their adjoints
+(shortrange_accel / shortrange_accel_adjoint, pm_accel / pm_accel_adjoint) and
+the elementwise updates (sr_axpy).  This module only sequences the calls and
+holds the checkpoints.
 """
 from __future__ import annotations
 
@@ -38,37 +43,48 @@ def _axpy(y: torch.Tensor, x: torch.Tensor, a: float):
                                       y.numel(), _lib.stream_handle()))
 
 
-def _accel(tree: Tree, x, mass, eps, params, box):
+def _accel(tree: Tree, x, mass, eps, params, box, pm=None):
     tree.build(x, mass, eps=eps, box=box)
     a, _ = shortrange_accel(tree, params, counts=False)
+    if pm is not None:
+        _axpy(a, pm.accel(x, mass, box=box, r_s=params["r_s"], G=params.get("G", 1.0)), 1.0)
     return a
 
 
+def _adjoint(tree: Tree, x, mass, params, w, box, pm=None):
+    g, _ = shortrange_accel_adjoint(tree, params, w)
+    if pm is not None:
+        gp, _ = pm.accel_adjoint(x, mass, w, box=box, r_s=params["r_s"], G=params.get("G", 1.0))
+        _axpy(g, gp, 1.0)
+    return g
+
+
 def kdk_rollout(pos, vel, mass, eps, params: dict, n_steps: int, dt: float, box: float = 1.0,
-                checkpoints: bool = False):
+                checkpoints: bool = False, pm=None):
     """Forward rollout.  Returns (x, v) after n_steps, plus the list of (x_k, v_k)
     checkpoints when `checkpoints` is set.  a(x_{k+1}) of one step's closing kick
-    is the next step's opening kick, so n_steps + 1 force evaluations are made."""
+    is the next step's opening kick, so n_steps + 1 force evaluations are made.
+    `pm`: a PM handle to add the long-range force (TreePM)."""
     x = pos.detach().to(torch.float64).contiguous().clone()
     v = vel.detach().to(torch.float64).contiguous().clone()
     tree = Tree()
     saved = []
-    a = _accel(tree, x, mass, eps, params, box)
+    a = _accel(tree, x, mass, eps, params, box, pm)
     for _ in range(n_steps):
         if checkpoints:
             saved.append((x.clone(), v.clone()))
         _axpy(v, a, 0.5 * dt)
         _axpy(x, v, dt)
-        a = _accel(tree, x, mass, eps, params, box)
+        a = _accel(tree, x, mass, eps, params, box, pm)
         _axpy(v, a, 0.5 * dt)
     return (x, v, saved) if checkpoints else (x, v)
 
 
 def kdk_rollout_grad(pos, vel, mass, eps, params: dict, n_steps: int, dt: float, wx, wv=None,
-                     box: float = 1.0):
+                     box: float = 1.0, pm=None):
     """Gradient of L = sum(wx . x_final) + sum(wv . v_final) with respect to the
     initial positions and velocities.  Returns (dL/dx0, dL/dv0, x_final, v_final)."""
-    x_fin, v_fin, saved = kdk_rollout(pos, vel, mass, eps, params, n_steps, dt, box, checkpoints=True)
+    x_fin, v_fin, saved = kdk_rollout(pos, vel, mass, eps, params, n_steps, dt, box, checkpoints=True, pm=pm)
     dev = x_fin.device
     wdt = torch.float32 if params.get("precision", "fp64") == "fp32" else torch.float64
     xb = wx.detach().to(torch.float64).contiguous().clone()
@@ -78,21 +94,19 @@ def kdk_rollout_grad(pos, vel, mass, eps, params: dict, n_steps: int, dt: float,
     for k in reversed(range(n_steps)):
         x0, v0 = saved[k]
         # recompute step k: trees and forward walks at x0 and x1
-        a0 = _accel(t0, x0, mass, eps, params, box)
+        a0 = _accel(t0, x0, mass, eps, params, box, pm)
         x1 = x0.clone()
         vh = v0.clone()
         _axpy(vh, a0, 0.5 * dt)
         _axpy(x1, vh, dt)
-        _accel(t1, x1, mass, eps, params, box)
+        _accel(t1, x1, mass, eps, params, box)  # the walk's lists at x1 (the PM needs none)
         # closing kick: v' = v_half + dt/2 a(x1)
         w.zero_()
         _axpy(w, vb, 0.5 * dt)
-        g1, _ = shortrange_accel_adjoint(t1, params, w)
-        _axpy(xb, g1, 1.0)                      # x1 bar
+        _axpy(xb, _adjoint(t1, x1, mass, params, w, box, pm), 1.0)     # x1 bar
         _axpy(vb, xb, dt)                       # v_half bar = v' bar + dt x1 bar
         # opening kick: v_half = v + dt/2 a(x0)
         w.zero_()
         _axpy(w, vb, 0.5 * dt)
-        g0, _ = shortrange_accel_adjoint(t0, params, w)
-        _axpy(xb, g0, 1.0)                      # x0 bar = x1 bar + A'(x0)^T w
+        _axpy(xb, _adjoint(t0, x0, mass, params, w, box, pm), 1.0)     # x0 bar = x1 bar + A'(x0)^T w
     return xb, vb, x_fin, v_fin

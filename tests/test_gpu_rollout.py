@@ -67,3 +67,24 @@ def test_zoom_rollout_fp32_close_to_fp64(rl, oracle):
     e32 = np.linalg.norm(v32.cpu().numpy() - vr, axis=1) / np.maximum(nr, 1e-6 * np.median(nr))
     print(f"   fp32 velocity error median {np.median(e32):.2e} p99.9 {np.quantile(e32, 0.999):.2e}", flush=True)
     assert np.median(e32) < 1e-5 and np.quantile(e32, 0.999) < 1e-4
+
+
+def test_treepm_rollout_and_gradient_fp64_match_oracle(rl, oracle):
+    # the whole TreePM force: short-range tree walk plus the PM force on the mesh
+    # that the workload's r_s = 1.25 L / n_mesh belongs to
+    import paper_2606_17145_amd as sg
+    from oracle import rollout as R
+    w, vel = _case(n=3000, seed=44)
+    p = w.params("fp64")
+    n_mesh = int(round(WL.ASMTH * 1.0 / w.r_s))
+    pm = sg.PM(n_mesh)
+    wx = np.random.default_rng(45).standard_normal((w.n, 3))
+    print(f"treepm rollout fp64: N={w.n}, mesh {n_mesh}^3, 2 steps", flush=True)
+    x, v = rl.kdk_rollout(_t(w.pos), _t(vel), _t(w.mass), _t(w.eps), p, 2, 1e-3, pm=pm)
+    xr, vr = R.rollout(w.pos, vel, w.mass, w.eps, p, 2, 1e-3, n_mesh=n_mesh)
+    assert np.allclose(x.cpu().numpy(), xr, rtol=0, atol=1e-14)
+    assert np.allclose(v.cpu().numpy(), vr, rtol=1e-11, atol=1e-11 * np.abs(vr).max())
+    gx, gv, _, _ = rl.kdk_rollout_grad(_t(w.pos), _t(vel), _t(w.mass), _t(w.eps), p, 2, 1e-3, _t(wx), pm=pm)
+    rx, rv = R.rollout_grad(w.pos, vel, w.mass, w.eps, p, 2, 1e-3, wx, n_mesh=n_mesh)
+    assert np.allclose(gx.cpu().numpy(), rx, rtol=1e-9, atol=1e-10 * np.abs(rx).max())
+    assert np.allclose(gv.cpu().numpy(), rv, rtol=1e-9, atol=1e-10 * np.abs(rv).max())
