@@ -189,6 +189,22 @@ def main():
     del pmh
     log(f"bench: pm 128^3 {pm_ms:.3f} ms {pm_phases}; adjoint {pm_adj_ms:.3f} ms")
 
+    # SPH density leg (not in the step): smoothing lengths and densities of the
+    # same particles on the step's tree, 64 neighbours
+    for _ in range(2):
+        sph_h, sph_rho, sph_bad = sg.sph_density(tree, 64.0)
+    torch.cuda.synchronize()
+    _lib.timing(True)
+    t_sph = time.perf_counter()
+    for _ in range(reps):
+        sph_h, sph_rho, sph_bad = sg.sph_density(tree, 64.0)
+    torch.cuda.synchronize()
+    sph_ms = (time.perf_counter() - t_sph) / reps * 1e3
+    it_ms, it_n = _lib.timing_read()["sph_iter"]
+    _lib.timing(False)
+    log(f"bench: sph density {sph_ms:.3f} ms per call, {it_n / reps:.1f} iterations, "
+        f"{it_ms / max(it_n, 1):.4f} ms per iteration, unconverged {sph_bad}")
+
     out = {
         "metric": METRIC,
         "value": inter / (ms_step * 1e-3),
@@ -218,6 +234,9 @@ def main():
     avg = {k: (ms / n if n else 0.0) for k, (ms, n) in phases.items()}
     out["kernel_ms_per_launch"] = avg
     out["walk_stats"] = stats
+    out["sph_density"] = {"n_ngb": 64, "ms_per_call": sph_ms, "iterations_per_call": it_n / reps,
+                          "ms_per_iteration": it_ms / max(it_n, 1), "particles_per_s": w.n / (sph_ms * 1e-3),
+                          "unconverged": sph_bad}
     out["pm_long_range"] = {"n_mesh": 128, "ms_per_call": pm_ms, "phases_ms_per_call": pm_phases,
                             "particles_per_s": w.n / (pm_ms * 1e-3), "adjoint_ms_per_call": pm_adj_ms,
                             "adjoint_phases_ms_per_call": pm_adj_phases}

@@ -187,7 +187,8 @@ enum {
     SR_T_PM_STENCIL = 11,  /* PM adjoint: transposed difference rule on one weight mesh */
     SR_T_PM_ADJ_GATHER = 12, /* PM adjoint: per-particle position and mass gradients */
     SR_T_PM_SORT = 13,     /* PM: particles sorted by mesh cell for the assignment */
-    SR_T_COUNT = 14
+    SR_T_SPH_ITER = 14,    /* SPH density: one iteration (neighbour walk, Newton step) */
+    SR_T_COUNT = 15
 };
 int srgrav_timing(int32_t enable);
 int srgrav_timing_read(double* ms, int64_t* calls);
@@ -291,6 +292,33 @@ int pm_accel_adjoint(sr_pm* pm, const double* pos, const double* mass, int64_t n
 
 /* pm_free -- waits for the device and releases the handle (NULL is ignored). */
 void pm_free(sr_pm* pm);
+
+/*
+ * sph_density -- SPH smoothing lengths and densities of the particles of a
+ * built tree (the paper's density module iterates each smoothing length to a
+ * fixed neighbour number, Sec. 2; the definitions are Gadget-2's):
+ *
+ *   W(r, h) = 8 / (pi h^3) w(r/h),  w(q) = 1 - 6q^2 + 6q^3 (q <= 1/2),
+ *             2 (1 - q)^3 (1/2 < q <= 1), 0 beyond      (cubic spline, support h)
+ *   rho_i(h) = sum_j m_j W(|x_j - x_i|, h)               (all j, self included,
+ *                                                         minimum image)
+ *   N_i(h)   = (4 pi / 3) h^3 rho_i(h) / m_i
+ *
+ * h_i is the root of N_i(h) = n_ngb (unique: N_i is strictly increasing once a
+ * neighbour lies within h), found by safeguarded Newton iterations to
+ * |N_i - n_ngb| <= 1e-13 n_ngb or a closed bracket; rho_i = rho_i(h_i).
+ *
+ *   tree         built by tree_build; its positions, masses and box are used
+ *   n_ngb        the neighbour number, finite and > 32/3 (the particle alone)
+ *   h, rho       DEVICE double[n] outputs, input order, overwritten
+ *   unconverged  HOST int64 (may be NULL): particles without a root below L/4
+ *                (or with mass <= 0), whose h is L/4 (or the last iterate)
+ *
+ * The host waits for the stream once per iteration (at most 100).  The
+ * workspace (about 36 bytes per particle) comes from the stream-ordered
+ * allocator and is released before the call returns.
+ */
+int sph_density(sr_tree* tree, double n_ngb, double* h, double* rho, int64_t* unconverged, void* stream);
 
 #ifdef __cplusplus
 }

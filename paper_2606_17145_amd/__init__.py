@@ -24,7 +24,7 @@ from . import _lib
 from ._lib import SrgravError  # noqa: F401
 
 __all__ = ["Tree", "tree_build", "shortrange_accel", "shortrange_accel_adjoint", "ShortRangeAccel",
-           "kdk_rollout", "SrgravError", "PM", "PMAccel", "pm_accel", "pm_accel_adjoint"]
+           "kdk_rollout", "SrgravError", "PM", "PMAccel", "pm_accel", "pm_accel_adjoint", "sph_density"]
 
 
 def _dev_f64(x, n=None, name="tensor"):
@@ -260,6 +260,21 @@ class PMAccel(torch.autograd.Function):
 def pm_accel(pos, mass, *, box: float, n_mesh: int, r_s: float, G: float = 1.0, pm: PM | None = None):
     """Long-range (PM) accelerations on an n_mesh^3 mesh (pass `pm` to reuse its plans)."""
     return _pm_handle(pm, n_mesh).accel(pos, mass, box=box, r_s=r_s, G=G)
+
+
+def sph_density(tree: Tree, n_ngb: float = 64.0):
+    """SPH smoothing lengths and densities (cubic spline; h the root of
+    (4 pi/3) h^3 rho / m = n_ngb) of the particles of a built tree.
+    Returns (h (N,), rho (N,), unconverged count), input order."""
+    if not tree._h:
+        raise ValueError("tree is not built")
+    h = torch.empty(tree.n, dtype=torch.float64, device=tree.device)
+    rho = torch.empty(tree.n, dtype=torch.float64, device=tree.device)
+    bad = C.c_int64(0)
+    with torch.cuda.device(tree.device):
+        _lib.check(_lib.lib().sph_density(tree._h, float(n_ngb), _lib.ptr(h), _lib.ptr(rho), C.byref(bad),
+                                          _lib.stream_handle()))
+    return h, rho, int(bad.value)
 
 
 def kdk_rollout(*args, **kwargs):

@@ -21,9 +21,9 @@ PRECISIONS = {"fp64": SR_FP64, "fp32": SR_FP32, "fp32_acc64": SR_FP32_ACC64}
 CRITERIA = {"bh": SR_OPEN_BH, "relative": SR_OPEN_RELATIVE}
 EXPORTED = ("tree_build", "shortrange_accel", "shortrange_accel_adjoint", "tree_node_count",
             "tree_export", "tree_free", "srgrav_last_error", "sr_axpy", "srgrav_timing",
-            "srgrav_timing_read", "tree_walk_stats", "pm_create", "pm_accel", "pm_accel_adjoint", "pm_free")
+            "srgrav_timing_read", "tree_walk_stats", "pm_create", "pm_accel", "pm_accel_adjoint", "pm_free", "sph_density")
 PHASES = ("tree_build", "traverse", "eval", "reduce", "adjoint_eval", "adjoint_reduce", "pushdown",
-          "pm_deposit", "pm_fft", "pm_green", "pm_interp", "pm_stencil", "pm_adj_gather", "pm_sort")
+          "pm_deposit", "pm_fft", "pm_green", "pm_interp", "pm_stencil", "pm_adj_gather", "pm_sort", "sph_iter")
 
 
 class SrgravError(RuntimeError):
@@ -77,6 +77,8 @@ def lib():
         L.pm_accel.restype = C.c_int
         L.pm_accel_adjoint.argtypes = [vp, vp, vp, i64, d, d, d, vp, vp, vp, vp]
         L.pm_accel_adjoint.restype = C.c_int
+        L.sph_density.argtypes = [vp, d, vp, vp, C.POINTER(i64), vp]
+        L.sph_density.restype = C.c_int
         L.pm_free.argtypes = [vp]
         L.pm_free.restype = None
         L.srgrav_last_error.restype = C.c_char_p

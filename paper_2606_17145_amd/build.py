@@ -8,7 +8,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB_PATH = os.path.join(PKG, "libsrgrav.so")
-SOURCES = ["api.hip", "build.hip", "walk.hip", "pm.hip"]
+SOURCES = ["api.hip", "build.hip", "walk.hip", "pm.hip", "sph.hip"]
 
 # -ffp-contract=off: the FP64 decisions and moment folds are reproduced bit for
 # bit, so nothing may be fused behind the source's back (FP32 code asks for FMA

@@ -1,0 +1,73 @@
+"""Parity of the SPH density (HIP path through the C ABI) with the SPH oracle.
+Both are FP64 and solve for the same unique root of the neighbour-number
+equation (the GPU by Newton iterations to |N - T| <= 1e-13 T, the oracle by
+bisection), so h and rho agree to 1e-10 relative."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import sph as OS
+from paper_2606_17145_amd import workloads as WL
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def sg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2606_17145_amd as sg
+    return sg
+
+
+def run(sg, pos, mass, box, n_ngb):
+    t = sg.tree_build(torch.tensor(pos, device=DEV), torch.tensor(mass, device=DEV), eps=1e-3 * box, box=box)
+    h, rho, bad = sg.sph_density(t, n_ngb)
+    return h.cpu().numpy(), rho.cpu().numpy(), bad
+
+
+def check(sg, pos, mass, box, n_ngb, tag, targets=None):
+    print(f"sph parity: {tag} N={len(pos)} n_ngb={n_ngb}", flush=True)
+    h, rho, bad = run(sg, pos, mass, box, n_ngb)
+    assert bad == 0
+    tg = np.arange(len(pos)) if targets is None else targets
+    hr, rr = OS.density(pos, mass, box, n_ngb, targets=tg)
+    eh = np.abs(h[tg] / hr - 1).max()
+    er = np.abs(rho[tg] / rr - 1).max()
+    print(f"   max relative error: h {eh:.2e}, rho {er:.2e}", flush=True)
+    assert eh <= 1e-10 and er <= 1e-10
+    return h, rho
+
+
+def test_sph_uniform_32k(sg):
+    w = WL.uniform_32k()
+    check(sg, w.pos, w.mass, w.box, 64.0, "uniform_32k")
+
+
+def test_sph_clustered_262k_sampled(sg):
+    # the full workload on the GPU; the oracle on 4,096 sampled particles, the
+    # densest sphere's core included
+    w = WL.clustered_262k()
+    tg = np.sort(np.random.default_rng(7).choice(w.n, 4096, replace=False))
+    check(sg, w.pos, w.mass, w.box, 64.0, "clustered_262k", targets=tg)
+
+
+def test_sph_unequal_masses_unwrapped_and_small(sg):
+    rng = np.random.default_rng(8)
+    pos = rng.uniform(-1.0, 2.0, (5000, 3)) * 2.0
+    mass = rng.uniform(0.2, 3.0, 5000)
+    check(sg, pos, mass, 2.0, 40.0, "unequal masses, box 2, unwrapped")
+    # a duplicated position (a level-30 bucket; two copies keep N(0+) = 64/3 below
+    # the target, so the root exists) and a tight clump
+    pos2 = np.vstack([rng.random((3000, 3)), np.full((2, 3), 0.3), 0.6 + 1e-4 * rng.standard_normal((500, 3))])
+    check(sg, pos2, np.ones(len(pos2)), 1.0, 32.0, "duplicates and a clump")
+
+
+def test_sph_failure_reporting(sg):
+    # 12 particles cannot hold 64 neighbours: every particle is reported
+    rng = np.random.default_rng(9)
+    h, rho, bad = run(sg, rng.random((12, 3)), np.ones(12), 1.0, 64.0)
+    assert bad == 12 and np.all(h == 0.25)
+    with pytest.raises(sg.SrgravError):
+        run(sg, rng.random((100, 3)), np.ones(100), 1.0, 5.0)      # below 32/3
