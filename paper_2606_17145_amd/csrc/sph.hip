@@ -8,13 +8,13 @@
 // (32/3) sum_j (m_j / m_i) w(r_ij / h), h_i is the root of N_i(h) = T.  N_i is
 // strictly increasing in h once a neighbour lies inside, so the root is unique.
 //
-// One thread per particle in Morton order (the lanes of a wave walk nearby
-// parts of the tree).  An iteration walks the pre-order node sequence without
-// a stack: a node whose cube meets the ball |x - x_i| < h (minimum image) is
-// entered (its direct particle children are summed, and the walk continues at
-// the next node in pre-order, its first child node or, if it has none, the
-// node after its subtree); any other node is skipped with n_skip.  The sums
-// give N(h) and dN/dh, and a safeguarded Newton step updates h inside the
+// One thread per particle in Morton order; the 64 lanes of a wave share one
+// walk of the pre-order node sequence without a stack: a node whose cube meets
+// any lane's ball |x - x_i| < h (minimum image) is entered (each lane sums the
+// direct particle children within its own h, and the walk continues at the
+// next node in pre-order, its first child node or, if it has none, the node
+// after its subtree); any other node is skipped with n_skip.  The sums give
+// N(h) and dN/dh, and a safeguarded Newton step in h^3 updates h inside the
 // bracket the iterations have found.
 #include <math.h>
 
@@ -45,7 +45,10 @@ __device__ inline void spline_w(double q, double& wq, double& qdw)
     }
 }
 
-__device__ inline double min_image(double d, double box) { return d - box * rint(d / box); }
+// Minimum image of a separation; inv_box = 1 / L (a product instead of an FP64
+// division; the image can differ from d / L rounding only at an exact half-box
+// tie, where both images are equally far).
+__device__ inline double min_image(double d, double box, double inv_box) { return d - box * rint(d * inv_box); }
 
 // Initial h: from the smallest ancestor of the particle's leaf that holds at
 // least T particles, the radius of a sphere with T particles at that node's
@@ -80,14 +83,21 @@ __global__ void k_sph_iterate(int64_t n, int64_t m, const WalkRec64* __restrict_
                               int32_t* __restrict__ active)
 {
     const int64_t s = blockIdx.x * (int64_t)SPH_TPB + threadIdx.x;
-    if (s >= n || state[s] != SPH_ACTIVE) return;
-    const Rec64 me = prec[s];
-    const double hh = h[s], h2 = hh * hh, inv_h = 1.0 / hh;
+    const bool act = s < n && state[s] == SPH_ACTIVE;
+    if (__ballot(act) == 0) return;         // the whole wave is done
+    Rec64 me{0.0, 0.0, 0.0, 0.0};
+    double hh = 0.0;
+    if (act) {
+        me = prec[s];
+        hh = h[s];
+    }
+    // an inactive lane has h2 = 0: it meets no node and no particle
+    const double h2 = hh * hh, inv_h = act ? 1.0 / hh : 0.0, inv_box = 1.0 / box;
     double A = 0.0, D = 0.0;       // sum m_j w(q_j), sum m_j q_j w'(q_j)
     auto pair = [&](int64_t j) {
         const Rec64 p = prec[j];
-        const double dx = min_image(p.x - me.x, box), dy = min_image(p.y - me.y, box),
-                     dz = min_image(p.z - me.z, box);
+        const double dx = min_image(p.x - me.x, box, inv_box), dy = min_image(p.y - me.y, box, inv_box),
+                     dz = min_image(p.z - me.z, box, inv_box);
         const double r2 = (dx * dx + dy * dy) + dz * dz;
         if (r2 < h2) {
             double wq, qdw;
@@ -97,16 +107,20 @@ __global__ void k_sph_iterate(int64_t n, int64_t m, const WalkRec64* __restrict_
         }
     };
     if (m == 0) {
-        pair(s);
+        if (act) pair(s);
     } else {
+        // The walk is shared by the wave: node k (the same on every lane) is
+        // entered when any lane's ball meets its cube; each lane then sums the
+        // node's particle children that lie within its own h.
         int64_t k = 0;
         while (k < m) {
             const WalkRec64* r = wrec + k;
+            const int64_t skip = n_skip[k];          // loaded with the record, not after the test
             const double half = 0.5 * r->l;
-            const double ex = fmax(fabs(min_image(me.x - r->cx, box)) - half, 0.0);
-            const double ey = fmax(fabs(min_image(me.y - r->cy, box)) - half, 0.0);
-            const double ez = fmax(fabs(min_image(me.z - r->cz, box)) - half, 0.0);
-            if ((ex * ex + ey * ey) + ez * ez < h2) {
+            const double ex = fmax(fabs(min_image(me.x - r->cx, box, inv_box)) - half, 0.0);
+            const double ey = fmax(fabs(min_image(me.y - r->cy, box, inv_box)) - half, 0.0);
+            const double ez = fmax(fabs(min_image(me.z - r->cz, box, inv_box)) - half, 0.0);
+            if (__ballot((ex * ex + ey * ey) + ez * ez < h2) != 0) {
                 const uint32_t meta = r->meta;
                 if (meta == META_BUCKET) {
                     const int64_t f = r->kids[0], c = r->kids[1];
@@ -119,10 +133,11 @@ __global__ void k_sph_iterate(int64_t n, int64_t m, const WalkRec64* __restrict_
                 }
                 ++k;
             } else {
-                k = n_skip[k];
+                k = skip;
             }
         }
     }
+    if (!act) return;
     const double mi = me.m;
     rho[s] = 8.0 / M_PI * inv_h * inv_h * inv_h * A;
     if (!(mi > 0.0)) {
@@ -144,8 +159,13 @@ __global__ void k_sph_iterate(int64_t n, int64_t m, const WalkRec64* __restrict_
         state[s] = SPH_DONE;
         return;
     }
+    // Newton in v = h^3, where N is close to linear: dN/dv = (dN/dh) / (3 h^2)
     const double dN = -32.0 / 3.0 * D / (mi * hh);
-    double hn = dN > 0.0 ? hh - f / dN : -1.0;
+    double hn = -1.0;
+    if (dN > 0.0) {
+        const double v = hh * hh * hh - f * 3.0 * hh * hh / dN;
+        if (v > 0.0) hn = cbrt(v);
+    }
     if (u < 0.0) {
         if (!(hn > hh)) hn = 2.0 * hh;
         hn = fmin(hn, 4.0 * hh);
