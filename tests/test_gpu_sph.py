@@ -71,3 +71,11 @@ def test_sph_failure_reporting(sg):
     assert bad == 12 and np.all(h == 0.25)
     with pytest.raises(sg.SrgravError):
         run(sg, rng.random((100, 3)), np.ones(100), 1.0, 5.0)      # below 32/3
+
+
+def test_sph_many_neighbours_walk_only(sg):
+    # 150 neighbours: within 1.15 h a particle has more than a neighbour list
+    # holds, so the iterations stay in walk mode to the end
+    rng = np.random.default_rng(10)
+    pos = rng.random((20000, 3))
+    check(sg, pos, np.full(20000, 1.0 / 20000), 1.0, 150.0, "150 neighbours", targets=np.arange(0, 20000, 7))
