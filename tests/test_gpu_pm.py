@@ -35,10 +35,14 @@ def check(sg, pos, mass, box, n_mesh, r_s, tag, scale=None):
     return acc, ref
 
 
-@pytest.mark.parametrize("case", ["uniform_32k", "clustered_262k"])
+MESH = {"uniform_32k": 64, "clustered_262k": 128, "clustered_2m_active": 256}
+
+
+@pytest.mark.parametrize("case", ["uniform_32k", "clustered_262k", "clustered_2m_active"])
 def test_pm_matches_oracle(sg, case):
+    # each workload on its own mesh, up to 2,097,152 particles on 256^3
     w = getattr(WL, case)()
-    n_mesh = 64 if case == "uniform_32k" else 128
+    n_mesh = MESH[case]
     r_s, _ = WL.split_scales(n_mesh, w.box)
     check(sg, w.pos, w.mass, w.box, n_mesh, r_s, case)
 

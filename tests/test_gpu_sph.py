@@ -53,6 +53,12 @@ def test_sph_clustered_262k_sampled(sg):
     check(sg, w.pos, w.mass, w.box, 64.0, "clustered_262k", targets=tg)
 
 
+def test_sph_clustered_2m_sampled(sg):
+    w = WL.clustered_2m_active()
+    tg = np.sort(np.random.default_rng(11).choice(w.n, 4096, replace=False))
+    check(sg, w.pos, w.mass, w.box, 64.0, "clustered_2m", targets=tg)
+
+
 def test_sph_unequal_masses_unwrapped_and_small(sg):
     rng = np.random.default_rng(8)
     pos = rng.uniform(-1.0, 2.0, (5000, 3)) * 2.0
