@@ -77,3 +77,23 @@ def test_host_side_argument_errors(libpath):
     n = ctypes.c_int64(0)
     assert L.tree_node_count(None, ctypes.byref(n)) == -4
     L.tree_free(None)
+
+
+def test_pm_and_sph_argument_errors(libpath):
+    """The PM and SPH entry points reject bad arguments before any device work."""
+    from paper_2606_17145_amd import _lib
+    L = _lib.lib()
+    dummy = ctypes.c_void_p(16)
+    h = ctypes.c_void_p(None)
+    # an odd or out-of-range mesh, and no output slot
+    assert L.pm_create(7, ctypes.byref(h)) == -1 and not h.value
+    assert b"n_mesh" in L.srgrav_last_error()
+    assert L.pm_create(4096, ctypes.byref(h)) == -1
+    assert L.pm_create(64, None) == -1
+    assert b"out is NULL" in L.srgrav_last_error()
+    # calls on a NULL handle
+    assert L.pm_accel(None, dummy, dummy, 4, 1.0, 0.1, 1.0, dummy, None) == -4
+    assert L.pm_accel_adjoint(None, dummy, dummy, 4, 1.0, 0.1, 1.0, dummy, dummy, dummy, None) == -4
+    L.pm_free(None)
+    bad = ctypes.c_int64(-1)
+    assert L.sph_density(None, 64.0, dummy, dummy, ctypes.byref(bad), None) == -4
