@@ -24,6 +24,8 @@ namespace {
 
 constexpr int SPH_TPB = 256;
 constexpr int SPH_MAX_ITER = 100;
+constexpr double SPH_INIT_FRACTION = 0.25;   // the initial density from the smallest ancestor with T/4 particles
+constexpr double SPH_GROW = 2.0;             // largest growth of h per step before an upper bound is known
 
 enum : int32_t { SPH_ACTIVE = 0, SPH_DONE = 1, SPH_FAILED = 2 };
 
@@ -51,8 +53,9 @@ __device__ inline void spline_w(double q, double& wq, double& qdw)
 __device__ inline double min_image(double d, double box, double inv_box) { return d - box * rint(d * inv_box); }
 
 // Initial h: from the smallest ancestor of the particle's leaf that holds at
-// least T particles, the radius of a sphere with T particles at that node's
-// mean density, l (3 T / (4 pi count))^(1/3), at most h_max.
+// least T/4 particles (a local density), the radius of a sphere with T
+// particles at that node's mean density, l (3 T / (4 pi count))^(1/3), at most
+// h_max.
 __global__ void k_sph_init(int64_t n, int64_t m, const int32_t* __restrict__ pparent,
                            const int32_t* __restrict__ n_parent, const int32_t* __restrict__ n_count,
                            const WalkRec64* __restrict__ wrec, double target, double box, double h_max,
@@ -63,7 +66,7 @@ __global__ void k_sph_init(int64_t n, int64_t m, const int32_t* __restrict__ ppa
     if (s >= n) return;
     double side = box, count = (double)n;
     int32_t nd = m > 0 ? pparent[s] : -1;
-    while (nd >= 0 && (double)n_count[nd] < target) nd = n_parent[nd];
+    while (nd >= 0 && (double)n_count[nd] < SPH_INIT_FRACTION * target) nd = n_parent[nd];
     if (nd >= 0) {
         side = wrec[nd].l;
         count = (double)n_count[nd];
@@ -167,8 +170,8 @@ __global__ void k_sph_iterate(int64_t n, int64_t m, const WalkRec64* __restrict_
         if (v > 0.0) hn = cbrt(v);
     }
     if (u < 0.0) {
-        if (!(hn > hh)) hn = 2.0 * hh;
-        hn = fmin(hn, 4.0 * hh);
+        if (!(hn > hh)) hn = SPH_GROW * hh;
+        hn = fmin(hn, SPH_GROW * hh);
         if (hn > h_max) {
             if (hh >= h_max) {              // N(h_max) < T: no root within h_max
                 state[s] = SPH_FAILED;
