@@ -24,6 +24,7 @@ namespace {
 
 constexpr int SPH_TPB = 256;
 constexpr int SPH_MAX_ITER = 100;
+constexpr double SPH_OVERFULL = 4.0;        // a partial neighbour number above 4 T ends a lane's walk
 constexpr double SPH_INIT_FRACTION = 0.25;   // the initial density from the smallest ancestor with T/4 particles
 constexpr double SPH_GROW = 2.0;             // largest growth of h per step before an upper bound is known
 
@@ -94,8 +95,13 @@ __global__ void k_sph_iterate(int64_t n, int64_t m, const WalkRec64* __restrict_
         me = prec[s];
         hh = h[s];
     }
-    // an inactive lane has h2 = 0: it meets no node and no particle
-    const double h2 = hh * hh, inv_h = act ? 1.0 / hh : 0.0, inv_box = 1.0 / box;
+    // an inactive lane has h2 = 0: it meets no node and no particle.  A lane
+    // whose partial sum already exceeds SPH_OVERFULL T neighbours (so h lies above
+    // the root) drops out of the walk the same way.
+    double h2 = hh * hh;
+    const double inv_h = act ? 1.0 / hh : 0.0, inv_box = 1.0 / box;
+    const double a_cut = SPH_OVERFULL * target * (3.0 / 32.0) * (act ? me.m : 0.0);
+    bool overfull = false;
     double A = 0.0, D = 0.0;       // sum m_j w(q_j), sum m_j q_j w'(q_j)
     auto pair = [&](int64_t j) {
         const Rec64 p = prec[j];
@@ -107,6 +113,10 @@ __global__ void k_sph_iterate(int64_t n, int64_t m, const WalkRec64* __restrict_
             spline_w(sqrt(r2) * inv_h, wq, qdw);
             A += p.m * wq;
             D += p.m * qdw;
+            if (A > a_cut && me.m > 0.0) {
+                overfull = true;
+                h2 = 0.0;
+            }
         }
     };
     if (m == 0) {
@@ -142,6 +152,15 @@ __global__ void k_sph_iterate(int64_t n, int64_t m, const WalkRec64* __restrict_
     }
     if (!act) return;
     const double mi = me.m;
+    if (overfull) {
+        // N(hh) > SPH_OVERFULL T: hh bounds the root from above; halve h, or
+        // bisect once a lower bound is known
+        const double l = lo[s];
+        hi[s] = hh;
+        h[s] = l > 0.0 ? 0.5 * (l + hh) : 0.5 * hh;
+        atomicAdd(active, 1);
+        return;
+    }
     rho[s] = 8.0 / M_PI * inv_h * inv_h * inv_h * A;
     if (!(mi > 0.0)) {
         state[s] = SPH_FAILED;
