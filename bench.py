@@ -109,7 +109,7 @@ def main():
         acc, cnt = sg.shortrange_accel(tree, p32)
         if ev:
             ev[2].record()
-        dx, dm = sg.shortrange_accel_adjoint(tree, p32, cot)
+        dx, dm = sg.shortrange_accel_adjoint(tree, p32, cot, list_token=tree.list_token)
         if ev:
             ev[3].record()
         return acc, cnt

@@ -115,6 +115,10 @@ int tree_build(const double* pos, const double* mass, const double* eps, double 
  *             (then float)
  *   counts    DEVICE int32[n_active*2] output (particle-particle, particle-node
  *             interactions per target), or NULL
+ *   list_token  HOST int64 output, or NULL: a positive token naming the
+ *             interaction lists this call made (0 when none were made, e.g.
+ *             n_active == 0 or a single particle).  Passing it to
+ *             shortrange_accel_adjoint differentiates exactly this call.
  *
  * Per-target semantics are those of a depth-first walk of one particle; the
  * group walk only shares the traversal.  The host waits once for the
@@ -125,18 +129,27 @@ int tree_build(const double* pos, const double* mass, const double* eps, double 
  * repeated within the call; the reservation is kept on the handle.
  */
 int shortrange_accel(sr_tree* tree, const sr_params* p, const int32_t* active, int64_t n_active,
-                     const double* a_old, void* acc, int32_t* counts, void* stream);
+                     const double* a_old, void* acc, int32_t* counts, int64_t* list_token, void* stream);
 
 /*
  * shortrange_accel_adjoint -- gradient of L = sum_t w_t . a_t.
  *
  * The tree topology, node membership, opening decisions and cutoff membership
  * are those of the forward pass and L is differentiated with all of them held
- * fixed: when the last shortrange_accel on this handle had the same parameters,
- * `active` and `a_old` pointers (and the tree was not rebuilt since), its
- * interaction lists are reused; otherwise the same deterministic walk is
- * repeated.  The caller must not change `active` or `a_old` in between.
+ * fixed.
  *
+ *   list_token  0: prepare the targets from `active` and repeat the forward's
+ *               deterministic walk (decisions from `a_old` for the relative
+ *               criterion).
+ *               > 0: a token returned by shortrange_accel on this handle; its
+ *               interaction lists and targets are reused and `active` and
+ *               `a_old` are not read (the gradient is that of the call that
+ *               issued the token, whatever the caller did to those arrays
+ *               since).  SR_ESTATE if the token no longer names the handle's
+ *               lists (a later shortrange_accel, an adjoint without a token or
+ *               a rebuild replaced them), SR_EINVAL if n_active or the decision
+ *               parameters (everything but the precision's accumulator) differ
+ *               from that call.
  *   w     DEVICE [n_active*3] cotangent, same element type as `acc`
  *   dLdx  DEVICE double[n*3]  output, input order (w.r.t. the wrapped positions,
  *                             which is the same as w.r.t. pos)
@@ -149,7 +162,7 @@ int shortrange_accel(sr_tree* tree, const sr_params* p, const int32_t* active, i
  */
 int shortrange_accel_adjoint(sr_tree* tree, const sr_params* p, const int32_t* active,
                              int64_t n_active, const double* a_old, const void* w, double* dLdx,
-                             double* dLdm, void* stream);
+                             double* dLdm, int64_t list_token, void* stream);
 
 /*
  * sr_axpy -- y[i] += a * x[i] for i < n, the elementwise update of a

@@ -8,7 +8,8 @@ binding: tensors in, tensors out, every step on the device.
 
     tree = tree_build(pos, mass, eps=eps, box=1.0)
     acc, counts = shortrange_accel(tree, params)              # params: dict
-    dLdx, dLdm = shortrange_accel_adjoint(tree, params, w)    # L = sum w . acc
+    dLdx, dLdm = shortrange_accel_adjoint(tree, params, w,    # L = sum w . acc, on the
+                                          list_token=tree.list_token)  # forward's lists
     acc = ShortRangeAccel.apply(pos, mass, eps, params)       # differentiable
 
 ``params`` keys: G, r_s, r_cut, theta, criterion ("bh" | "relative"), alpha,
@@ -42,6 +43,7 @@ class Tree:
         self.n = 0
         self.box = 1.0
         self.device = None
+        self.list_token = 0      # token of the interaction lists of the last shortrange_accel
 
     def __del__(self):
         try:
@@ -69,6 +71,7 @@ class Tree:
                                              float(eps_scalar or 0.0), n, float(box), 1,
                                              _lib.stream_handle(), C.byref(self._h)))
         self.n, self.box, self.device = n, float(box), pos.device
+        self.list_token = 0      # a rebuild replaces the lists
         return self
 
     def node_count(self) -> int:
@@ -127,14 +130,21 @@ def shortrange_accel(tree: Tree, params: dict, active=None, a_old=None, counts: 
     cnt = torch.empty((n_t, 2), dtype=torch.int32, device=tree.device) if counts else None
     ao = None if a_old is None else _dev_f64(torch.as_tensor(a_old, device=tree.device), name="a_old")
     p = _lib.make_params(params)
+    tok = C.c_int64(0)
     with torch.cuda.device(tree.device):
         _lib.check(_lib.lib().shortrange_accel(tree._h, C.byref(p), _lib.ptr(act), n_t, _lib.ptr(ao),
-                                               _lib.ptr(acc), _lib.ptr(cnt), _lib.stream_handle()))
+                                               _lib.ptr(acc), _lib.ptr(cnt), C.byref(tok),
+                                               _lib.stream_handle()))
+    tree.list_token = int(tok.value)
     return acc, cnt
 
 
-def shortrange_accel_adjoint(tree: Tree, params: dict, w, active=None, a_old=None):
-    """dL/dx (N, 3) and dL/dm (N) of L = sum_t w_t . a_t, decisions as in the forward."""
+def shortrange_accel_adjoint(tree: Tree, params: dict, w, active=None, a_old=None, list_token: int = 0):
+    """dL/dx (N, 3) and dL/dm (N) of L = sum_t w_t . a_t, decisions as in the forward.
+
+    list_token: 0 repeats the forward's walk for `active` / `a_old`; a token from
+    shortrange_accel (``tree.list_token`` right after it) differentiates that call on
+    its own lists and targets (`active` then only sets the length of `w`)."""
     prec = params.get("precision", "fp64")
     act, n_t = _targets(tree, active)
     dt = torch.float32 if prec == "fp32" else torch.float64
@@ -148,16 +158,21 @@ def shortrange_accel_adjoint(tree: Tree, params: dict, w, active=None, a_old=Non
     with torch.cuda.device(tree.device):
         _lib.check(_lib.lib().shortrange_accel_adjoint(tree._h, C.byref(p), _lib.ptr(act), n_t,
                                                        _lib.ptr(ao), _lib.ptr(w), _lib.ptr(dx),
-                                                       _lib.ptr(dm), _lib.stream_handle()))
+                                                       _lib.ptr(dm), int(list_token), _lib.stream_handle()))
+    if list_token == 0:
+        tree.list_token = 0      # the repeated walk replaced the handle's lists
     return dx, dm
 
 
 class ShortRangeAccel(torch.autograd.Function):
     """Differentiable short-range acceleration a(pos, mass).
 
-    The backward re-walks the tree built in the forward (kept on the context),
-    so topology, opening decisions and cutoff membership are those of the
-    forward pass.
+    ShortRangeAccel.apply(pos, mass, eps, params[, box, active, a_old]) returns
+    the accelerations of the targets (all particles, or `active`).  The backward
+    runs the adjoint on the tree and interaction lists of the forward (kept on the
+    context, named by their list token), so topology, opening decisions and
+    cutoff membership are those of the forward pass.  The gradient flows to `pos`
+    and, when it is a tensor, to `mass` (a 0-dimensional mass gets the sum).
     """
 
     @staticmethod
@@ -165,14 +180,21 @@ class ShortRangeAccel(torch.autograd.Function):
         tree = tree_build(pos, mass, eps=eps, box=box)
         acc, _ = shortrange_accel(tree, params, active=active, a_old=a_old, counts=False)
         ctx.tree, ctx.params, ctx.active, ctx.a_old = tree, params, active, a_old
-        ctx.pos_dtype, ctx.mass_dtype = pos.dtype, torch.as_tensor(mass).dtype
+        ctx.token = tree.list_token
+        ctx.pos_dtype = pos.dtype
+        ctx.mass_kind = (mass.dtype, mass.dim()) if isinstance(mass, torch.Tensor) else None
         return acc
 
     @staticmethod
     def backward(ctx, grad):
         dx, dm = shortrange_accel_adjoint(ctx.tree, ctx.params, grad.contiguous(), active=ctx.active,
-                                          a_old=ctx.a_old)
-        return dx.to(ctx.pos_dtype), dm.to(ctx.mass_dtype), None, None, None, None, None
+                                          a_old=ctx.a_old, list_token=ctx.token)
+        if ctx.mass_kind is None:
+            gm = None
+        else:
+            mdt, mdim = ctx.mass_kind
+            gm = (dm if mdim > 0 else dm.sum()).to(mdt)
+        return dx.to(ctx.pos_dtype), gm, None, None, None, None, None
 
 
 class PM:

@@ -57,8 +57,8 @@ def lib():
         L = C.CDLL(LIB_PATH)
         vp, i64, d = C.c_void_p, C.c_int64, C.c_double
         L.tree_build.argtypes = [vp, vp, vp, d, i64, d, C.c_int32, vp, C.POINTER(vp)]
-        L.shortrange_accel.argtypes = [vp, C.POINTER(SrParams), vp, i64, vp, vp, vp, vp]
-        L.shortrange_accel_adjoint.argtypes = [vp, C.POINTER(SrParams), vp, i64, vp, vp, vp, vp, vp]
+        L.shortrange_accel.argtypes = [vp, C.POINTER(SrParams), vp, i64, vp, vp, vp, C.POINTER(i64), vp]
+        L.shortrange_accel_adjoint.argtypes = [vp, C.POINTER(SrParams), vp, i64, vp, vp, vp, vp, i64, vp]
         L.tree_node_count.argtypes = [vp, C.POINTER(i64)]
         L.tree_export.argtypes = [vp, C.POINTER(SrTreeExport), vp]
         L.sr_axpy.argtypes = [vp, C.c_int32, vp, C.c_int32, d, i64, vp]

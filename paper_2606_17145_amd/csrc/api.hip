@@ -236,6 +236,10 @@ int check_params(const sr_tree* t, const sr_params* p)
 int check_call(sr_tree* t, const sr_params* p, const int32_t* active, int64_t n_active, const double* a_old)
 {
     if (!t || t->n <= 0) return sr_fail(SR_ESTATE, "tree handle is NULL or was never built");
+    int dev = -1;
+    SR_HIP(hipGetDevice(&dev));
+    if (dev != t->device)
+        return sr_fail(SR_ESTATE, "the tree was built on device %d, the current device is %d", t->device, dev);
     int rc = check_params(t, p);
     if (rc) return rc;
     if (!active && n_active != t->n)
@@ -380,27 +384,47 @@ int tree_build(const double* pos, const double* mass, const double* eps, double 
 }
 
 int shortrange_accel(sr_tree* t, const sr_params* p, const int32_t* active, int64_t n_active, const double* a_old,
-                     void* acc, int32_t* counts, void* stream)
+                     void* acc, int32_t* counts, int64_t* list_token, void* stream)
 {
     g_err[0] = 0;
+    if (list_token) *list_token = 0;
     int rc = check_call(t, p, active, n_active, a_old);
     if (rc) return rc;
     if (!acc) return sr_fail(SR_EINVAL, "acc is NULL");
     hipStream_t st = (hipStream_t)stream;
     if ((rc = sr_prepare_targets(t, active, n_active, st))) return rc;
-    return sr_walk_forward(t, p, n_active, active, a_old, acc, counts, st);
+    if ((rc = sr_walk_forward(t, p, n_active, active, a_old, acc, counts, st))) return rc;
+    if (list_token && t->lkey.valid) *list_token = t->lkey.token;
+    return SR_OK;
 }
 
 int shortrange_accel_adjoint(sr_tree* t, const sr_params* p, const int32_t* active, int64_t n_active,
-                             const double* a_old, const void* w, double* dLdx, double* dLdm, void* stream)
+                             const double* a_old, const void* w, double* dLdx, double* dLdm, int64_t list_token,
+                             void* stream)
 {
     g_err[0] = 0;
-    int rc = check_call(t, p, active, n_active, a_old);
-    if (rc) return rc;
+    if (list_token < 0) return sr_fail(SR_EINVAL, "list_token must be 0 or a token from shortrange_accel");
+    if (list_token > 0) {
+        // the targets and decisions come from the forward call that issued the token:
+        // active and a_old are not read
+        if (!t || t->n <= 0) return sr_fail(SR_ESTATE, "tree handle is NULL or was never built");
+        int dev = -1;
+        SR_HIP(hipGetDevice(&dev));
+        if (dev != t->device)
+            return sr_fail(SR_ESTATE, "the tree was built on device %d, the current device is %d", t->device, dev);
+        int rc = check_params(t, p);
+        if (rc) return rc;
+        if (n_active < 0 || n_active > t->n) return sr_fail(SR_EINVAL, "n_active must lie in [0, n]");
+        if ((rc = sr_check_list_token(t, p, n_active, list_token))) return rc;
+    } else {
+        int rc = check_call(t, p, active, n_active, a_old);
+        if (rc) return rc;
+    }
     if (!w || !dLdx || !dLdm) return sr_fail(SR_EINVAL, "w, dLdx and dLdm are required");
     hipStream_t st = (hipStream_t)stream;
-    if ((rc = sr_prepare_targets(t, active, n_active, st))) return rc;
-    return sr_walk_adjoint(t, p, n_active, active, a_old, w, dLdx, dLdm, st);
+    int rc = SR_OK;
+    if (list_token == 0 && (rc = sr_prepare_targets(t, active, n_active, st))) return rc;
+    return sr_walk_adjoint(t, p, n_active, active, a_old, w, dLdx, dLdm, list_token, st);
 }
 
 int tree_walk_stats(const sr_tree* t, int64_t* stats)

@@ -74,16 +74,18 @@ enum {
     ST_WORDS = ST_HIST + SR_MAX_DEPTH
 };
 
-// What a traversal's lists were made for; the adjoint reuses them only on a match.
+// What a traversal's lists were made for.  `token` names them: shortrange_accel
+// hands it to the caller, and the adjoint reuses these lists (and the targets they
+// were made for) only when it is given the same token and the same decision
+// parameters; any later target preparation or traversal invalidates it.
 struct ListKey {
     bool valid = false;
+    int64_t token = 0;
     int64_t gen = -1;
     int dec64 = 0;
     double G = 0, r_s = 0, r_cut = 0, theta = 0, alpha = 0;
     int criterion = 0;
     int64_t n_t = 0;
-    const void* active = nullptr;
-    const void* a_old = nullptr;
 };
 
 struct sr_tree {
@@ -156,6 +158,7 @@ struct sr_tree {
     int64_t n_units = 0, n_chunks = 0, n_tests = 0;
     int64_t unit_hint = 0;             // unit count expected from the previous traversal
     ListKey lkey;
+    int64_t list_serial = 0;           // last token issued on this handle
     int64_t build_gen = 0;
 
     // host mirrors
@@ -184,7 +187,10 @@ int sr_prepare_targets(sr_tree* t, const int32_t* active, int64_t n_active, hipS
 int sr_walk_forward(sr_tree* t, const sr_params* p, int64_t n_t, const int32_t* active, const double* a_old,
                     void* acc, int32_t* counts, hipStream_t st);
 int sr_walk_adjoint(sr_tree* t, const sr_params* p, int64_t n_t, const int32_t* active, const double* a_old,
-                    const void* w, double* dLdx, double* dLdm, hipStream_t st);
+                    const void* w, double* dLdx, double* dLdm, int64_t list_token, hipStream_t st);
+// walk.hip: SR_OK if `token` names the handle's current lists and they were made
+// with the decision parameters of `p` for n_t targets, else an error code
+int sr_check_list_token(const sr_tree* t, const sr_params* p, int64_t n_t, int64_t token);
 
 // walk.hip: elementwise y += a x
 int sr_axpy_device(void* y, int y_type, const void* x, int x_type, double a, int64_t n, hipStream_t st);

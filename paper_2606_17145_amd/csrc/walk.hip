@@ -1581,13 +1581,11 @@ ListArgs list_args(const sr_tree* t)
     return L;
 }
 
-bool same_lists(const sr_tree* t, const sr_params* p, int64_t n_t, const int32_t* active, const double* a_old)
+bool same_decisions(const ListKey& k, const sr_params* p)
 {
-    const ListKey& k = t->lkey;
     const int dec64 = p->precision == SR_FP64;
-    return k.valid && k.gen == t->build_gen && k.dec64 == dec64 && k.G == p->G && k.r_s == p->r_s &&
-           k.r_cut == p->r_cut && k.theta == p->theta && k.alpha == p->alpha && k.criterion == p->criterion &&
-           k.n_t == n_t && k.active == (const void*)active && k.a_old == (const void*)a_old;
+    return k.dec64 == dec64 && k.G == p->G && k.r_s == p->r_s && k.r_cut == p->r_cut && k.theta == p->theta &&
+           k.alpha == p->alpha && k.criterion == p->criterion;
 }
 
 // Phase 1, growing the list buffers (and the per-wave frontier) until everything fits.
@@ -1664,6 +1662,7 @@ int traverse_finish(sr_tree* t, const sr_params* p, int64_t n_t, const int32_t* 
     t->n_tests = tests;
     ListKey& k = t->lkey;
     k.valid = true;
+    k.token = ++t->list_serial;
     k.gen = t->build_gen;
     k.dec64 = p->precision == SR_FP64;
     k.G = p->G;
@@ -1673,8 +1672,6 @@ int traverse_finish(sr_tree* t, const sr_params* p, int64_t n_t, const int32_t* 
     k.alpha = p->alpha;
     k.criterion = p->criterion;
     k.n_t = n_t;
-    k.active = active;
-    k.a_old = a_old;
     return SR_OK;
 }
 
@@ -1742,9 +1739,24 @@ int eval_and_reduce(sr_tree* t, const sr_params* p, const WalkArgs& a, int64_t u
 
 }  // namespace
 
+int sr_check_list_token(const sr_tree* t, const sr_params* p, int64_t n_t, int64_t token)
+{
+    const ListKey& k = t->lkey;
+    if (!(k.valid && k.token == token && k.gen == t->build_gen))
+        return sr_fail(SR_ESTATE, "list token %lld does not name this handle's current interaction lists "
+                       "(another walk or a rebuild replaced them)", (long long)token);
+    if (k.n_t != n_t)
+        return sr_fail(SR_EINVAL, "n_active (%lld) differs from the forward call of this token (%lld)",
+                       (long long)n_t, (long long)k.n_t);
+    if (!same_decisions(k, p))
+        return sr_fail(SR_EINVAL, "parameters differ from the forward call of this token");
+    return SR_OK;
+}
+
 int sr_prepare_targets(sr_tree* t, const int32_t* active, int64_t n_active, hipStream_t st)
 {
     const int64_t n = t->n;
+    t->lkey.valid = false;   // the lists belong to the previous targets
     if (!active) {
         hipLaunchKernelGGL(k_targets_all, g256(n), dim3(256), 0, st, n, t->perm, t->tgt_sorted, t->tgt_slot);
         SR_HIP(hipGetLastError());
@@ -1822,14 +1834,15 @@ int sr_walk_forward(sr_tree* t, const sr_params* p, int64_t n_t, const int32_t* 
 }
 
 int sr_walk_adjoint(sr_tree* t, const sr_params* p, int64_t n_t, const int32_t* active, const double* a_old,
-                    const void* w, double* dLdx, double* dLdm, hipStream_t st)
+                    const void* w, double* dLdx, double* dLdm, int64_t list_token, hipStream_t st)
 {
     const int64_t n = t->n, m = t->n_nodes;
     hipLaunchKernelGGL(k_zero3_f64, g256(7 * n + 4 * m), dim3(256), 0, st, t->pbar, 4 * n, t->tbar, 3 * n, t->nbar,
                        4 * m);
     if (n_t > 0 && m > 0) {
-        // the forward's lists carry the frozen decisions; walk again only if they are not those of this call
-        if (!same_lists(t, p, n_t, active, a_old)) {
+        // the forward's lists (named by the token, checked by the caller) carry the frozen
+        // decisions; without a token the same deterministic walk is repeated
+        if (list_token == 0) {
             int rc = traverse(t, p, n_t, active, a_old, st);
             if (rc) return rc;
         }

@@ -52,7 +52,8 @@ def _accel(tree: Tree, x, mass, eps, params, box, pm=None):
 
 
 def _adjoint(tree: Tree, x, mass, params, w, box, pm=None):
-    g, _ = shortrange_accel_adjoint(tree, params, w)
+    # on the lists of the tree's last forward walk (its recomputation in this step)
+    g, _ = shortrange_accel_adjoint(tree, params, w, list_token=tree.list_token)
     if pm is not None:
         gp, _ = pm.accel_adjoint(x, mass, w, box=box, r_s=params["r_s"], G=params.get("G", 1.0))
         _axpy(g, gp, 1.0)

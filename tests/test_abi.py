@@ -73,7 +73,12 @@ def test_host_side_argument_errors(libpath):
     assert b"eps" in L.srgrav_last_error()
     # calls on a handle that was never built
     p = _lib.make_params(dict(r_s=0.01, r_cut=0.045))
-    assert L.shortrange_accel(None, ctypes.byref(p), None, 1, None, dummy, None, None) == -4
+    tok = ctypes.c_int64(7)
+    assert L.shortrange_accel(None, ctypes.byref(p), None, 1, None, dummy, None, ctypes.byref(tok), None) == -4
+    assert tok.value == 0
+    # adjoint: a negative token, and a token on a handle that was never built
+    assert L.shortrange_accel_adjoint(None, ctypes.byref(p), None, 1, None, dummy, dummy, dummy, -1, None) == -1
+    assert L.shortrange_accel_adjoint(None, ctypes.byref(p), None, 1, None, dummy, dummy, dummy, 3, None) == -4
     n = ctypes.c_int64(0)
     assert L.tree_node_count(None, ctypes.byref(n)) == -4
     L.tree_free(None)
