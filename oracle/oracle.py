@@ -37,6 +37,22 @@ def build(force: bool = True) -> str:
 _lib = None
 
 
+def use_native_build() -> str:
+    """Compile oracle.c with -O3 -march=native for the machine this runs on and route
+    every later call through that build (the same source and arithmetic: contraction
+    and fast-math stay off).  Used to time the oracle on the host it runs on."""
+    global _lib
+    path = os.path.join(HERE, "liboracle_native.so")
+    cmd = ["gcc", "-std=c99", "-O3", "-march=native", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+           "-fPIC", "-shared", "-Wall", "-o", path + ".tmp", os.path.join(HERE, "oracle.c"), "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(path + ".tmp", path)
+    L = C.CDLL(path)
+    _declare(L)
+    _lib = L
+    return path
+
+
 def lib():
     global _lib
     if _lib is None:
