@@ -66,6 +66,8 @@ typedef struct {
     const double* com;          /* n_nodes x 3 */
     const double* hmax;
     const double* hmin;
+    const double* half;         /* NULL for a built tree; after a drift: per-node half-side
+                                   of the cube the opening tests use (or_extents) */
 } or_tree;
 
 typedef struct {
@@ -307,8 +309,9 @@ void or_moments(or_tree* T, double* M, double* S, double* com, float* M32, uint3
         for (int k = 0; k < 3; ++k) {
             S[3 * nd + k] = s[k];
             com[3 * nd + k] = s[k] / m;
+            /* modulo 2^32: a drifted centre of mass may lie just outside [0, L) */
             double q = rint(com[3 * nd + k] / T->box * TWO32);
-            comX[3 * nd + k] = (uint32_t)(uint64_t)q;
+            comX[3 * nd + k] = (uint32_t)(int64_t)q;
         }
         M32[nd] = (float)m;
         double hx = -INFINITY, hn = INFINITY;
@@ -376,11 +379,39 @@ static double pair_dK(const or_params* P, double r, double h)
 /* node geometry and the opening decision                                    */
 /* ------------------------------------------------------------------------- */
 
-static double node_side(const or_tree* T, int64_t nd) { return ldexp(T->box, -T->level[nd]); }
+/* The side the opening tests use: the cell's side, or after a drift twice the
+ * node's half-side (or_extents). */
+static double node_side(const or_tree* T, int64_t nd)
+{
+    return T->half ? 2.0 * T->half[nd] : ldexp(T->box, -T->level[nd]);
+}
 
 static double node_centre(const or_tree* T, int64_t nd, int k)
 {
     return T->box * (ldexp((double)T->corner[3 * nd + k], -32) + ldexp(1.0, -T->level[nd] - 1));
+}
+
+/* Node drift (paper App. A: between rebuilds the tree nodes drift with their
+ * particles; the node lengths are then enlarged to keep them conservative).  The
+ * topology stays; T->xw holds the moved particles (the built positions plus the
+ * displacement, not wrapped again) and or_moments refolds the moments from them.
+ * The extent of node nd is the half-side of the cube about its cell centre c
+ * that holds all its particles:
+ *     half[nd] = max(l/2, max over members j and axes k of |x_jk - c_k|),
+ * so a node whose particles stayed in its cell keeps its side. */
+void or_extents(const or_tree* T, double* half)
+{
+    for (int64_t nd = 0; nd < T->n_nodes; ++nd) {
+        double h = 0.5 * ldexp(T->box, -T->level[nd]);
+        for (int64_t s = T->first[nd]; s < T->first[nd] + T->count[nd]; ++s) {
+            int64_t j = T->perm[s];
+            for (int k = 0; k < 3; ++k) {
+                double e = fabs(T->xw[3 * j + k] - node_centre(T, nd, k));
+                if (e > h) h = e;
+            }
+        }
+        half[nd] = h;
+    }
 }
 
 /* Prune (work only: every source of a pruned cube lies beyond r_cut), then the

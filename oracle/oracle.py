@@ -10,6 +10,7 @@ given as a plain dict with keys G, r_s, r_cut, theta, criterion ("bh" or
 """
 from __future__ import annotations
 
+import copy
 import ctypes as C
 import os
 import subprocess
@@ -72,7 +73,7 @@ class CTree(C.Structure):
     _fields_ = [("n", I64), ("box", D), ("xw", P), ("mass", P), ("hsml", P), ("X", P),
                 ("perm", P), ("pparent", P), ("n_nodes", I64), ("level", P), ("first", P),
                 ("count", P), ("parent", P), ("skip", P), ("corner", P), ("child_start", P),
-                ("child", P), ("M", P), ("com", P), ("hmax", P), ("hmin", P)]
+                ("child", P), ("M", P), ("com", P), ("hmax", P), ("hmin", P), ("half", P)]
 
 
 class CParams(C.Structure):
@@ -87,6 +88,7 @@ def _declare(L):
     L.or_build_topology.argtypes = [I64, P, P, P] + [P] * 9
     L.or_build_topology.restype = I64
     L.or_moments.argtypes = [C.POINTER(CTree)] + [P] * 7
+    L.or_extents.argtypes = [C.POINTER(CTree), P]
     L.or_walk.argtypes = [C.POINTER(CTree), C.POINTER(CParams), I64, P, P, P, P]
     L.or_direct.argtypes = [I64, P, P, P, D, C.POINTER(CParams), I64, P, P, P]
     L.or_adjoint.argtypes = [C.POINTER(CTree), C.POINTER(CParams), I64, P, P, P, P, P, P, P]
@@ -180,6 +182,7 @@ class Tree:
         self.comX = np.zeros((mm, 3), np.uint32)
         self.hmax = np.zeros(mm)
         self.hmin = np.zeros(mm)
+        self.half = None         # set by drift(): node half-sides of a drifted tree
         self.ct = self._struct()
         lib().or_moments(C.byref(self.ct), _p(self.M), _p(self.S), _p(self.com), _p(self.M32),
                          _p(self.comX), _p(self.hmax), _p(self.hmin))
@@ -189,15 +192,48 @@ class Tree:
                      _p(self.perm), _p(self.pparent), self.n_nodes, _p(self.level),
                      _p(self.first), _p(self.count), _p(self.parent), _p(self.skip),
                      _p(self.corner), _p(self.child_start), _p(self.child), _p(self.M),
-                     _p(self.com), _p(self.hmax), _p(self.hmin))
+                     _p(self.com), _p(self.hmax), _p(self.hmin),
+                     None if self.half is None else _p(self.half))
+
+    def drift(self, disp):
+        """The tree after its particles moved by `disp` (N x 3, input order) from where
+        it was built: the same nodes and node order, the particles at the built
+        (wrapped) positions plus disp (not wrapped again; their integer coordinates
+        are those of the moved positions), the moments refolded in the build's order,
+        and each node's cube grown to hold its particles (or_extents)."""
+        disp = np.ascontiguousarray(disp, dtype=np.float64)
+        assert disp.shape == (self.n, 3)
+        d = copy.copy(self)
+        base = self.xw if self.half is None else self.xw0
+        d.xw0 = base
+        d.xw = np.ascontiguousarray(base + disp)
+        d.X, _ = wrap_quantize(d.xw, self.box)
+        mm = max(self.n_nodes, 1)
+        d.M = np.zeros(mm)
+        d.S = np.zeros((mm, 3))
+        d.com = np.zeros((mm, 3))
+        d.M32 = np.zeros(mm, np.float32)
+        d.comX = np.zeros((mm, 3), np.uint32)
+        d.hmax = np.zeros(mm)
+        d.hmin = np.zeros(mm)
+        d.half = np.zeros(mm)
+        d.ct = d._struct()
+        lib().or_moments(C.byref(d.ct), _p(d.M), _p(d.S), _p(d.com), _p(d.M32), _p(d.comX),
+                         _p(d.hmax), _p(d.hmin))
+        if self.n_nodes > 0:
+            lib().or_extents(C.byref(d.ct), _p(d.half))
+        return d
 
     # node arrays trimmed to the node count
     def nodes(self) -> dict:
         m = self.n_nodes
-        return dict(level=self.level[:m], first=self.first[:m], count=self.count[:m],
-                    parent=self.parent[:m], skip=self.skip[:m], corner=self.corner[:m],
-                    M=self.M[:m], com=self.com[:m], M32=self.M32[:m], comX=self.comX[:m],
-                    hmax=self.hmax[:m], hmin=self.hmin[:m])
+        out = dict(level=self.level[:m], first=self.first[:m], count=self.count[:m],
+                   parent=self.parent[:m], skip=self.skip[:m], corner=self.corner[:m],
+                   M=self.M[:m], com=self.com[:m], M32=self.M32[:m], comX=self.comX[:m],
+                   hmax=self.hmax[:m], hmin=self.hmin[:m])
+        if self.half is not None:
+            out["half"] = self.half[:m]
+        return out
 
     def children(self, nd: int):
         """Children of node nd in digit order: ('node', k) or ('particle', sorted s)."""
