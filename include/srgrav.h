@@ -112,7 +112,7 @@ int tree_build(const double* pos, const double* mass, const double* eps, double 
  *   a_old     DEVICE double[n]  |a| of the previous step per particle (input
  *             order); read only for SR_OPEN_RELATIVE, else may be NULL
  *   acc       DEVICE [n_active*3] output, double unless p->precision == SR_FP32
- *             (then float)
+ *             (then float); may be NULL only when n_active == 0
  *   counts    DEVICE int32[n_active*2] output (particle-particle, particle-node
  *             interactions per target), or NULL
  *   list_token  HOST int64 output, or NULL: a positive token naming the
@@ -130,6 +130,34 @@ int tree_build(const double* pos, const double* mass, const double* eps, double 
  */
 int shortrange_accel(sr_tree* tree, const sr_params* p, const int32_t* active, int64_t n_active,
                      const double* a_old, void* acc, int32_t* counts, int64_t* list_token, void* stream);
+
+/*
+ * shortrange_accel_noalloc -- shortrange_accel for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, targets, decisions and results as
+ * shortrange_accel (bit for bit: the same kernels make the same lists), but the
+ * interaction lists, traversal frontier, list counters and per-unit partial sums
+ * live in one fixed device buffer of SR_NOALLOC_SCRATCH_BYTES that the library
+ * holds on each GPU it runs on until the process ends; the call allocates and
+ * frees nothing (with phase timing on, srgrav_timing may still create events).
+ * The tree handle must already have been built; its per-target workspace is
+ * reused.
+ *
+ *   n_active  at most SR_NOALLOC_MAX_TARGETS, else SR_EINVAL before any device work
+ *
+ * Lists that do not fit the buffer give SR_ENOMEM (acc and counts are then not
+ * valid): the list size depends on the clustering, not only on n_active.  No
+ * list token is issued (the adjoint repeats the walk for token 0), and a token
+ * from an earlier shortrange_accel on this handle is invalidated.  Every call
+ * on one GPU shares that GPU's buffer: calls that overlap on one GPU (on
+ * different streams or host threads) race and give wrong results; calls in
+ * stream order on one stream are safe.
+ */
+#define SR_NOALLOC_SCRATCH_BYTES (128ll << 20)
+#define SR_NOALLOC_MAX_TARGETS (1ll << 18)
+int shortrange_accel_noalloc(sr_tree* tree, const sr_params* p, const int32_t* active,
+                             int64_t n_active, const double* a_old, void* acc, int32_t* counts,
+                             void* stream);
 
 /*
  * shortrange_accel_adjoint -- gradient of L = sum_t w_t . a_t.

@@ -24,7 +24,7 @@ import torch
 from . import _lib
 from ._lib import SrgravError  # noqa: F401
 
-__all__ = ["Tree", "tree_build", "shortrange_accel", "shortrange_accel_adjoint", "ShortRangeAccel",
+__all__ = ["Tree", "tree_build", "shortrange_accel", "shortrange_accel_noalloc", "shortrange_accel_adjoint", "ShortRangeAccel",
            "kdk_rollout", "SrgravError", "PM", "PMAccel", "pm_accel", "pm_accel_adjoint", "sph_density"]
 
 
@@ -118,6 +118,9 @@ def _targets(tree: Tree, active):
     if active is None:
         return None, tree.n
     a = torch.as_tensor(active, device=tree.device).to(torch.int32).contiguous()
+    if a.numel() == 0:
+        # an empty subset still needs a non-NULL pointer (NULL means all particles)
+        return torch.zeros(1, dtype=torch.int32, device=tree.device), 0
     return a, a.shape[0]
 
 
@@ -137,6 +140,29 @@ def shortrange_accel(tree: Tree, params: dict, active=None, a_old=None, counts: 
                                                _lib.stream_handle()))
     tree.list_token = int(tok.value)
     return acc, cnt
+
+
+def shortrange_accel_noalloc(tree: Tree, params: dict, active=None, a_old=None, out=None, counts=None):
+    """shortrange_accel through the allocation-free entry point: the library's lists
+    live in its fixed per-GPU buffer.  `out` / `counts`: optional preallocated
+    outputs ((n_t, 3) and (n_t, 2) int32); missing ones are allocated here by torch."""
+    prec = params.get("precision", "fp64")
+    act, n_t = _targets(tree, active)
+    dt = torch.float32 if prec == "fp32" else torch.float64
+    acc = out if out is not None else torch.empty((n_t, 3), dtype=dt, device=tree.device)
+    if acc.shape != (n_t, 3) or acc.dtype != dt or not acc.is_contiguous():
+        raise ValueError(f"out must be a contiguous ({n_t}, 3) {dt} tensor")
+    if counts is not None and (counts.shape != (n_t, 2) or counts.dtype != torch.int32
+                               or not counts.is_contiguous()):
+        raise ValueError(f"counts must be a contiguous ({n_t}, 2) int32 tensor")
+    ao = None if a_old is None else _dev_f64(torch.as_tensor(a_old, device=tree.device), name="a_old")
+    p = _lib.make_params(params)
+    with torch.cuda.device(tree.device):
+        _lib.check(_lib.lib().shortrange_accel_noalloc(tree._h, C.byref(p), _lib.ptr(act), n_t,
+                                                       _lib.ptr(ao), _lib.ptr(acc), _lib.ptr(counts),
+                                                       _lib.stream_handle()))
+    tree.list_token = 0      # no token names these lists; the handle's earlier token is void
+    return acc, counts
 
 
 def shortrange_accel_adjoint(tree: Tree, params: dict, w, active=None, a_old=None, list_token: int = 0):

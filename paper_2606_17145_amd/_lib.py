@@ -19,7 +19,7 @@ SR_OPEN_BH, SR_OPEN_RELATIVE = 0, 1
 SR_FP64, SR_FP32, SR_FP32_ACC64 = 0, 1, 2
 PRECISIONS = {"fp64": SR_FP64, "fp32": SR_FP32, "fp32_acc64": SR_FP32_ACC64}
 CRITERIA = {"bh": SR_OPEN_BH, "relative": SR_OPEN_RELATIVE}
-EXPORTED = ("tree_build", "shortrange_accel", "shortrange_accel_adjoint", "tree_node_count",
+EXPORTED = ("tree_build", "shortrange_accel", "shortrange_accel_noalloc", "shortrange_accel_adjoint", "tree_node_count",
             "tree_export", "tree_free", "srgrav_last_error", "sr_axpy", "srgrav_timing",
             "srgrav_timing_read", "tree_walk_stats", "pm_create", "pm_accel", "pm_accel_adjoint", "pm_free", "sph_density")
 PHASES = ("tree_build", "traverse", "eval", "reduce", "adjoint_eval", "adjoint_reduce", "pushdown",
@@ -58,6 +58,7 @@ def lib():
         vp, i64, d = C.c_void_p, C.c_int64, C.c_double
         L.tree_build.argtypes = [vp, vp, vp, d, i64, d, C.c_int32, vp, C.POINTER(vp)]
         L.shortrange_accel.argtypes = [vp, C.POINTER(SrParams), vp, i64, vp, vp, vp, C.POINTER(i64), vp]
+        L.shortrange_accel_noalloc.argtypes = [vp, C.POINTER(SrParams), vp, i64, vp, vp, vp, vp]
         L.shortrange_accel_adjoint.argtypes = [vp, C.POINTER(SrParams), vp, i64, vp, vp, vp, vp, i64, vp]
         L.tree_node_count.argtypes = [vp, C.POINTER(i64)]
         L.tree_export.argtypes = [vp, C.POINTER(SrTreeExport), vp]
@@ -82,7 +83,7 @@ def lib():
         L.pm_free.argtypes = [vp]
         L.pm_free.restype = None
         L.srgrav_last_error.restype = C.c_char_p
-        for name in ("tree_build", "shortrange_accel", "shortrange_accel_adjoint", "tree_node_count",
+        for name in ("tree_build", "shortrange_accel", "shortrange_accel_noalloc", "shortrange_accel_adjoint", "tree_node_count",
                      "tree_export"):
             getattr(L, name).restype = C.c_int
         _lib = L

@@ -390,12 +390,27 @@ int shortrange_accel(sr_tree* t, const sr_params* p, const int32_t* active, int6
     if (list_token) *list_token = 0;
     int rc = check_call(t, p, active, n_active, a_old);
     if (rc) return rc;
-    if (!acc) return sr_fail(SR_EINVAL, "acc is NULL");
+    if (!acc && n_active > 0) return sr_fail(SR_EINVAL, "acc is NULL");
     hipStream_t st = (hipStream_t)stream;
     if ((rc = sr_prepare_targets(t, active, n_active, st))) return rc;
     if ((rc = sr_walk_forward(t, p, n_active, active, a_old, acc, counts, st))) return rc;
     if (list_token && t->lkey.valid) *list_token = t->lkey.token;
     return SR_OK;
+}
+
+int shortrange_accel_noalloc(sr_tree* t, const sr_params* p, const int32_t* active, int64_t n_active,
+                             const double* a_old, void* acc, int32_t* counts, void* stream)
+{
+    g_err[0] = 0;
+    int rc = check_call(t, p, active, n_active, a_old);
+    if (rc) return rc;
+    if (!acc && n_active > 0) return sr_fail(SR_EINVAL, "acc is NULL");
+    if (n_active > SR_NOALLOC_MAX_TARGETS)
+        return sr_fail(SR_EINVAL, "the allocation-free forward takes at most %lld targets (got %lld)",
+                       (long long)SR_NOALLOC_MAX_TARGETS, (long long)n_active);
+    hipStream_t st = (hipStream_t)stream;
+    if ((rc = sr_prepare_targets(t, active, n_active, st))) return rc;
+    return sr_walk_forward_noalloc(t, p, n_active, active, a_old, acc, counts, st);
 }
 
 int shortrange_accel_adjoint(sr_tree* t, const sr_params* p, const int32_t* active, int64_t n_active,

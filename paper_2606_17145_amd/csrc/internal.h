@@ -188,6 +188,9 @@ int sr_walk_forward(sr_tree* t, const sr_params* p, int64_t n_t, const int32_t* 
                     void* acc, int32_t* counts, hipStream_t st);
 int sr_walk_adjoint(sr_tree* t, const sr_params* p, int64_t n_t, const int32_t* active, const double* a_old,
                     const void* w, double* dLdx, double* dLdm, int64_t list_token, hipStream_t st);
+// walk.hip: the forward with its lists in the fixed scratch buffer (allocates nothing)
+int sr_walk_forward_noalloc(sr_tree* t, const sr_params* p, int64_t n_t, const int32_t* active, const double* a_old,
+                            void* acc, int32_t* counts, hipStream_t st);
 // walk.hip: SR_OK if `token` names the handle's current lists and they were made
 // with the decision parameters of `p` for n_t targets, else an error code
 int sr_check_list_token(const sr_tree* t, const sr_params* p, int64_t n_t, int64_t token);

@@ -12,6 +12,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <type_traits>
 
 #include "gpoly.h"
@@ -971,6 +972,23 @@ __device__ inline float stream_sum4(float x, float y, float z, float m, int lane
     }
 }
 
+// FP64 form of stream_sum4 for 16-lane streams (each exchange moves both 32-bit
+// halves): lane l ends with the row total of quantity (l mod 16) / 4.
+__device__ inline double stream_sum4_f64(double x, double y, double z, double m, int lane)
+{
+    const bool b3 = lane & 8, b2 = lane & 4;
+    double k0 = b3 ? z : x, k1 = b3 ? m : y;
+    const double s0 = b3 ? x : z, s1 = b3 ? y : m;
+    k0 += dpp_f64<0x140, 0xf, 0xf>(s0);
+    k1 += dpp_f64<0x140, 0xf, 0xf>(s1);
+    double k = b2 ? k1 : k0;
+    const double s = b2 ? k0 : k1;
+    k += dpp_f64<0x141, 0xf, 0xf>(s);
+    k += dpp_f64<0xb1, 0xf, 0xf>(k);
+    k += dpp_f64<0x4e, 0xf, 0xf>(k);
+    return k;
+}
+
 // FP32 evaluation of one unit, packed into streams.  A stream is a group of QL
 // lanes (QL Morton-consecutive targets).  For each chunk the entries whose mask
 // touches group k form stream k; step s evaluates entry stream_k[s] on the lanes
@@ -1183,22 +1201,6 @@ struct alignas(16) SrcLds64 {
     uint32_t pad[2];
 };
 
-// FP64 form of stream_sum4 for 16-lane streams (each exchange moves both 32-bit
-// halves): lane l ends with the row total of quantity (l mod 16) / 4.
-__device__ inline double stream_sum4_f64(double x, double y, double z, double m, int lane)
-{
-    const bool b3 = lane & 8, b2 = lane & 4;
-    double k0 = b3 ? z : x, k1 = b3 ? m : y;
-    const double s0 = b3 ? x : z, s1 = b3 ? y : m;
-    k0 += dpp_f64<0x140, 0xf, 0xf>(s0);
-    k1 += dpp_f64<0x140, 0xf, 0xf>(s1);
-    double k = b2 ? k1 : k0;
-    const double s = b2 ? k0 : k1;
-    k += dpp_f64<0x141, 0xf, 0xf>(s);
-    k += dpp_f64<0xb1, 0xf, 0xf>(k);
-    k += dpp_f64<0x4e, 0xf, 0xf>(k);
-    return k;
-}
 
 template <bool ADJ>
 __global__ __launch_bounds__(WAVE) void k_eval64(WalkArgs a, ListArgs L, char* __restrict__ partials)
@@ -1561,21 +1563,56 @@ WalkArgs make_args(const sr_tree* t, const sr_params* p, int64_t n_t, const doub
     return a;
 }
 
-ListArgs list_args(const sr_tree* t)
+// Where one traversal writes its lists, frontier and partial sums: the handle's
+// buffers (grown on demand) or the fixed buffer of the allocation-free forward.
+struct ListStore {
+    uint32_t* ent_src;
+    uint64_t* ent_mask;
+    int32_t *chunk_next, *chunk_cnt;
+    int32_t *unit_group, *unit_chunk, *unit_nch, *unit_next;
+    int32_t* group_head;
+    int32_t* counters;
+    char* partials;
+    uint32_t* frontier;
+    int64_t cap_chunks, cap_units, cap_front;
+};
+
+ListStore handle_store(const sr_tree* t)
+{
+    ListStore S{};
+    S.ent_src = t->ent_src;
+    S.ent_mask = t->ent_mask;
+    S.chunk_next = t->chunk_next;
+    S.chunk_cnt = t->chunk_cnt;
+    S.unit_group = t->unit_group;
+    S.unit_chunk = t->unit_chunk;
+    S.unit_nch = t->unit_nch;
+    S.unit_next = t->unit_next;
+    S.group_head = t->group_head;
+    S.counters = t->list_counters;
+    S.partials = t->partials;
+    S.frontier = t->frontier;
+    S.cap_chunks = t->cap_chunks;
+    S.cap_units = t->cap_units;
+    S.cap_front = t->cap_front;
+    return S;
+}
+
+ListArgs list_args(const ListStore& S)
 {
     ListArgs L{};
-    L.ent_src = t->ent_src;
-    L.ent_mask = t->ent_mask;
-    L.chunk_next = t->chunk_next;
-    L.chunk_cnt = t->chunk_cnt;
-    L.unit_group = t->unit_group;
-    L.unit_chunk = t->unit_chunk;
-    L.unit_nch = t->unit_nch;
-    L.unit_next = t->unit_next;
-    L.group_head = t->group_head;
-    L.counters = t->list_counters;
-    L.cap_chunks = t->cap_chunks;
-    L.cap_units = t->cap_units;
+    L.ent_src = S.ent_src;
+    L.ent_mask = S.ent_mask;
+    L.chunk_next = S.chunk_next;
+    L.chunk_cnt = S.chunk_cnt;
+    L.unit_group = S.unit_group;
+    L.unit_chunk = S.unit_chunk;
+    L.unit_nch = S.unit_nch;
+    L.unit_next = S.unit_next;
+    L.group_head = S.group_head;
+    L.counters = S.counters;
+    L.cap_chunks = S.cap_chunks;
+    L.cap_units = S.cap_units;
     L.unit_base = 0;
     L.unit_end = 0;
     return L;
@@ -1588,34 +1625,34 @@ bool same_decisions(const ListKey& k, const sr_params* p)
            k.alpha == p->alpha && k.criterion == p->criterion;
 }
 
-// Phase 1, growing the list buffers (and the per-wave frontier) until everything fits.
-// Phase 1 launch: reserve lists and frontier for `want` entries / `fcap` frontier
-// entries per wave, then the traversal.  No host synchronisation.
-int traverse_launch(sr_tree* t, const sr_params* p, int64_t n_t, const int32_t* active, const double* a_old,
-                    int64_t want, int64_t fcap, hipStream_t st)
+// Persistent traversal workgroups of TW waves for `groups` target groups: at
+// most `per_cu` per compute unit and one per group.
+int traversal_workgroups(int64_t groups, int64_t per_cu, int64_t& wgs)
 {
-    t->lkey.valid = false;
-    const int64_t groups = (n_t + WAVE - 1) / WAVE;
-    // persistent traversal workgroups of TW waves, at most one per group
     int dev = 0, cus = 0;
     SR_HIP(hipGetDevice(&dev));
     SR_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    const int64_t wgs = groups < SR_TRAV_WG_PER_CU * (int64_t)cus ? groups : SR_TRAV_WG_PER_CU * (int64_t)cus;
-    // every wave of a group may start a unit chain; each wave may leave a
-    // reserved batch of chunks and units unused
-    const int64_t chunks = (want + 63) / 64 + TW * wgs * (TRAV_CHUNK_BATCH + 2);
-    int rc = sr_list_reserve(t, groups, chunks, TW * groups + chunks / UCH + TW * wgs * TRAV_UNIT_BATCH + 1);
-    if (rc) return rc;
-    if ((rc = sr_front_reserve(t, wgs * TW, fcap))) return rc;
-    hipLaunchKernelGGL(k_fill_i32w, g256(groups), dim3(256), 0, st, t->group_head, groups, -1);
-    hipLaunchKernelGGL(k_fill_i32w, g256(8), dim3(256), 0, st, t->list_counters, (int64_t)8, 0);
+    wgs = groups < per_cu * (int64_t)cus ? groups : per_cu * (int64_t)cus;
+    if (wgs < 1) wgs = 1;
+    return SR_OK;
+}
+
+// The traversal into store S with `wgs` persistent workgroups (S holds a
+// frontier for that many), then the copy of its counters to pinned host memory.
+// No host synchronisation.
+int launch_traversal(sr_tree* t, const sr_params* p, int64_t n_t, const int32_t* active, const double* a_old,
+                     const ListStore& S, int64_t wgs, hipStream_t st)
+{
+    const int64_t groups = (n_t + WAVE - 1) / WAVE;
+    hipLaunchKernelGGL(k_fill_i32w, g256(groups), dim3(256), 0, st, S.group_head, groups, -1);
+    hipLaunchKernelGGL(k_fill_i32w, g256(8), dim3(256), 0, st, S.counters, (int64_t)8, 0);
     const WalkArgs a = make_args(t, p, n_t, a_old);
-    const ListArgs L = list_args(t);
+    const ListArgs L = list_args(S);
     FrontArgs F{};
-    F.buf = t->frontier;
-    F.cap = t->cap_front;
-    F.next_group = t->list_counters + 3;
-    F.overflow = t->list_counters + 2;
+    F.buf = S.frontier;
+    F.cap = S.cap_front;
+    F.next_group = S.counters + 3;
+    F.overflow = S.counters + 2;
     F.w32 = t->wrec32;
     F.w64 = t->wrec64;
     F.contig = active == nullptr;
@@ -1638,9 +1675,29 @@ int traverse_launch(sr_tree* t, const sr_params* p, int64_t n_t, const int32_t* 
     SR_HIP(hipGetLastError());
     // the counters go to pinned host memory right behind the traversal, so that the
     // check waits for the traversal only and not for the work queued after it
-    SR_HIP(hipMemcpyAsync(t->h_counters, t->list_counters, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    SR_HIP(hipMemcpyAsync(t->h_counters, S.counters, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     SR_HIP(hipEventRecord(t->ev_counters, st));
     return SR_OK;
+}
+
+// Phase 1 launch on the handle's lists: reserve lists and frontier for `want`
+// entries / `fcap` frontier entries per wave, then the traversal.  No host
+// synchronisation.
+int traverse_launch(sr_tree* t, const sr_params* p, int64_t n_t, const int32_t* active, const double* a_old,
+                    int64_t want, int64_t fcap, hipStream_t st)
+{
+    t->lkey.valid = false;
+    const int64_t groups = (n_t + WAVE - 1) / WAVE;
+    int64_t wgs = 1;
+    int rc = traversal_workgroups(groups, SR_TRAV_WG_PER_CU, wgs);
+    if (rc) return rc;
+    // every wave of a group may start a unit chain; each wave may leave a
+    // reserved batch of chunks and units unused
+    const int64_t chunks = (want + 63) / 64 + TW * wgs * (TRAV_CHUNK_BATCH + 2);
+    rc = sr_list_reserve(t, groups, chunks, TW * groups + chunks / UCH + TW * wgs * TRAV_UNIT_BATCH + 1);
+    if (rc) return rc;
+    if ((rc = sr_front_reserve(t, wgs * TW, fcap))) return rc;
+    return launch_traversal(t, p, n_t, active, a_old, handle_store(t), wgs, st);
 }
 
 // After a traversal: read its counters (the host waits until they have been
@@ -1704,10 +1761,10 @@ int traverse(sr_tree* t, const sr_params* p, int64_t n_t, const int32_t* active,
 // Phases 2 and 3: evaluate units [u0, u0 + nu) (units past the traversal's
 // count exit at once), then reduce every group.
 template <bool ADJ>
-int eval_and_reduce(sr_tree* t, const sr_params* p, const WalkArgs& a, int64_t u0, int64_t nu, hipStream_t st)
+int eval_and_reduce(const sr_params* p, const WalkArgs& a, const ListStore& S, int64_t u0, int64_t nu, hipStream_t st)
 {
     const int64_t groups = (a.n_t + WAVE - 1) / WAVE;
-    ListArgs L = list_args(t);
+    ListArgs L = list_args(S);
     L.unit_base = (int32_t)u0;
     L.unit_end = (int32_t)(u0 + nu);
     const dim3 gu((unsigned)(nu > 0 ? nu : 1)), gu32((unsigned)(nu > 0 ? (nu + EVAL_WAVES - 1) / EVAL_WAVES : 1)),
@@ -1716,21 +1773,21 @@ int eval_and_reduce(sr_tree* t, const sr_params* p, const WalkArgs& a, int64_t u
     if (nu > 0) {
         sr_timing_mark(ph_eval, true, st);
         switch (p->precision) {
-        case SR_FP64: hipLaunchKernelGGL((k_eval64<ADJ>), gu, dim3(WAVE), 0, st, a, L, t->partials); break;
+        case SR_FP64: hipLaunchKernelGGL((k_eval64<ADJ>), gu, dim3(WAVE), 0, st, a, L, S.partials); break;
         case SR_FP32:
-            hipLaunchKernelGGL((k_eval32<PR32, ADJ>), gu32, dim3(EVAL_WAVES * WAVE), 0, st, a, L, t->partials);
+            hipLaunchKernelGGL((k_eval32<PR32, ADJ>), gu32, dim3(EVAL_WAVES * WAVE), 0, st, a, L, S.partials);
             break;
         default:
-            hipLaunchKernelGGL((k_eval32<PR32A, ADJ>), gu32, dim3(EVAL_WAVES * WAVE), 0, st, a, L, t->partials);
+            hipLaunchKernelGGL((k_eval32<PR32A, ADJ>), gu32, dim3(EVAL_WAVES * WAVE), 0, st, a, L, S.partials);
             break;
         }
         sr_timing_mark(ph_eval, false, st);
     }
     sr_timing_mark(ph_red, true, st);
     switch (p->precision) {
-    case SR_FP64: hipLaunchKernelGGL((k_reduce<PR64, ADJ>), gg, dim3(WAVE), 0, st, a, L, t->partials); break;
-    case SR_FP32: hipLaunchKernelGGL((k_reduce<PR32, ADJ>), gg, dim3(WAVE), 0, st, a, L, t->partials); break;
-    default: hipLaunchKernelGGL((k_reduce<PR32A, ADJ>), gg, dim3(WAVE), 0, st, a, L, t->partials); break;
+    case SR_FP64: hipLaunchKernelGGL((k_reduce<PR64, ADJ>), gg, dim3(WAVE), 0, st, a, L, S.partials); break;
+    case SR_FP32: hipLaunchKernelGGL((k_reduce<PR32, ADJ>), gg, dim3(WAVE), 0, st, a, L, S.partials); break;
+    default: hipLaunchKernelGGL((k_reduce<PR32A, ADJ>), gg, dim3(WAVE), 0, st, a, L, S.partials); break;
     }
     sr_timing_mark(ph_red, false, st);
     SR_HIP(hipGetLastError());
@@ -1805,7 +1862,7 @@ int sr_walk_forward(sr_tree* t, const sr_params* p, int64_t n_t, const int32_t* 
         t->n_units = 0;
         t->lkey.valid = false;
         hipLaunchKernelGGL(k_fill_i32w, g256(groups), dim3(256), 0, st, t->group_head, groups, -1);
-        return eval_and_reduce<false>(t, p, a, 0, 0, st);
+        return eval_and_reduce<false>(p, a, handle_store(t), 0, 0, st);
     }
     // traversal, evaluation and reduction go to the stream back to back, the
     // evaluation sized by the previous unit count; the counters are checked once
@@ -1817,12 +1874,12 @@ int sr_walk_forward(sr_tree* t, const sr_params* p, int64_t n_t, const int32_t* 
         int rc = traverse_launch(t, p, n_t, active, a_old, want, fcap, st);
         if (rc) return rc;
         const int64_t guess = t->unit_hint > 0 && t->unit_hint < t->cap_units ? t->unit_hint : t->cap_units;
-        if ((rc = eval_and_reduce<false>(t, p, a, 0, guess, st))) return rc;
+        if ((rc = eval_and_reduce<false>(p, a, handle_store(t), 0, guess, st))) return rc;
         bool overflow = false;
         if ((rc = traverse_finish(t, p, n_t, active, a_old, st, overflow))) return rc;
         if (!overflow) {
             if (t->n_units > guess) {
-                if ((rc = eval_and_reduce<false>(t, p, a, guess, t->n_units - guess, st))) return rc;
+                if ((rc = eval_and_reduce<false>(p, a, handle_store(t), guess, t->n_units - guess, st))) return rc;
             }
             t->unit_hint = t->n_units + t->n_units / 8 + 64;
             return SR_OK;
@@ -1851,7 +1908,7 @@ int sr_walk_adjoint(sr_tree* t, const sr_params* p, int64_t n_t, const int32_t* 
         a.pbar = t->pbar;
         a.tbar = t->tbar;
         a.nbar = t->nbar;
-        int rc = eval_and_reduce<true>(t, p, a, 0, t->n_units, st);
+        int rc = eval_and_reduce<true>(p, a, handle_store(t), 0, t->n_units, st);
         if (rc) return rc;
     }
     double sx = 1.0, sm = 1.0;
@@ -1866,5 +1923,139 @@ int sr_walk_adjoint(sr_tree* t, const sr_params* p, int64_t n_t, const int32_t* 
                        t->nrec64, t->pbar, t->tbar, t->nbar, sx, sm, dLdx, dLdm);
     sr_timing_mark(SR_T_PUSHDOWN, false, st);
     SR_HIP(hipGetLastError());
+    return SR_OK;
+}
+
+// ----------------------------------------------------------------------------------
+// the allocation-free forward
+// ----------------------------------------------------------------------------------
+//
+// Everything the forward needs beyond the tree, the targets' workspace of the
+// handle and the outputs -- list counters, group heads, the traversal frontier,
+// chunks, units and partial sums -- lives in one fixed device buffer.  Each GPU
+// that runs the library holds its own copy until the process ends, and every
+// call on that GPU shares it.
+
+static __device__ __align__(256) char scratch[SR_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+constexpr int64_t NOALLOC_FRONT = 2048;   // frontier entries per wave and level
+std::mutex g_scratch_mu;
+char* g_scratch_addr[SCRATCH_MAX_DEVICES] = {};
+
+// Device address of the current device's copy of `scratch`, looked up once per
+// device with that device current.  Host code passes this address, never the
+// array's name, to kernels and copies.
+int scratch_address(char** out)
+{
+    int dev = -1;
+    SR_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= SCRATCH_MAX_DEVICES)
+        return sr_fail(SR_EUNSUPPORTED, "the allocation-free forward supports device ids below %d (current: %d)",
+                       SCRATCH_MAX_DEVICES, dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return sr_fail(SR_EHIP, "hipGetSymbolAddress of the scratch buffer failed on device %d: %s", dev,
+                           hipGetErrorString(e));
+        }
+        g_scratch_addr[dev] = (char*)ptr;
+    }
+    *out = g_scratch_addr[dev];
+    return SR_OK;
+}
+
+// Lays out a list store for n_t targets and `wgs` traversal workgroups in the
+// buffer at `base`: counters, group heads and the frontier first, then units
+// and chunks in the handle's proportion (UCH chunks per unit, plus the units
+// every wave may open or leave reserved).
+int carve_scratch(char* base, int64_t n_t, int64_t wgs, ListStore& S)
+{
+    auto up = [](int64_t b) { return (b + 255) & ~(int64_t)255; };
+    const int64_t groups = (n_t + WAVE - 1) / WAVE;
+    S = ListStore{};
+    int64_t off = 0;
+    S.counters = (int32_t*)(base + off);
+    off += up(8 * sizeof(int32_t));
+    S.group_head = (int32_t*)(base + off);
+    off += up(groups * (int64_t)sizeof(int32_t));
+    S.cap_front = NOALLOC_FRONT;
+    S.frontier = (uint32_t*)(base + off);
+    off += up(wgs * TW * S.cap_front * 6 * (int64_t)sizeof(uint32_t));
+    const int64_t per_chunk = 64 * 4 + 64 * 8 + 2 * 4;   // ent_src, ent_mask, next, count
+    const int64_t per_unit = 4 * 4 + PARTIAL_BYTES;       // group, chunk, nch, next, partials
+    const int64_t unit_fixed = TW * groups + TW * wgs * TRAV_UNIT_BATCH + 1;
+    const int64_t slack = 10 * 256;                       // alignment of the ten arrays below
+    const int64_t left = SR_NOALLOC_SCRATCH_BYTES - off - slack - unit_fixed * per_unit;
+    const int64_t chunks = left > 0 ? left * UCH / (UCH * per_chunk + per_unit) : 0;
+    const int64_t min_chunks = TW * wgs * (TRAV_CHUNK_BATCH + 2) + 1;
+    if (chunks < min_chunks)
+        return sr_fail(SR_EINVAL, "%lld targets leave no room for interaction lists in the %lld-byte scratch buffer",
+                       (long long)n_t, (long long)SR_NOALLOC_SCRATCH_BYTES);
+    const int64_t units = unit_fixed + chunks / UCH;
+    auto take = [&](int64_t bytes) {
+        char* q = base + off;
+        off += up(bytes);
+        return q;
+    };
+    S.ent_src = (uint32_t*)take(64 * chunks * 4);
+    S.ent_mask = (uint64_t*)take(64 * chunks * 8);
+    S.chunk_next = (int32_t*)take(chunks * 4);
+    S.chunk_cnt = (int32_t*)take(chunks * 4);
+    S.unit_group = (int32_t*)take(units * 4);
+    S.unit_chunk = (int32_t*)take(units * 4);
+    S.unit_nch = (int32_t*)take(units * 4);
+    S.unit_next = (int32_t*)take(units * 4);
+    S.partials = take(units * PARTIAL_BYTES);
+    if (off > SR_NOALLOC_SCRATCH_BYTES)
+        return sr_fail(SR_EINVAL, "internal: scratch layout of %lld bytes exceeds the buffer", (long long)off);
+    S.cap_chunks = chunks;
+    S.cap_units = units;
+    return SR_OK;
+}
+
+}  // namespace
+
+int sr_walk_forward_noalloc(sr_tree* t, const sr_params* p, int64_t n_t, const int32_t* active, const double* a_old,
+                            void* acc, int32_t* counts, hipStream_t st)
+{
+    t->lkey.valid = false;   // the targets changed; the handle's lists no longer match them
+    if (n_t == 0) return SR_OK;
+    if (n_t > SR_NOALLOC_MAX_TARGETS)
+        return sr_fail(SR_EINVAL, "the allocation-free forward takes at most %lld targets (got %lld)",
+                       (long long)SR_NOALLOC_MAX_TARGETS, (long long)n_t);
+    char* base = nullptr;
+    int rc = scratch_address(&base);
+    if (rc) return rc;
+    const int64_t groups = (n_t + WAVE - 1) / WAVE;
+    int64_t wgs = 1;
+    if ((rc = traversal_workgroups(groups, 1, wgs))) return rc;
+    ListStore S;
+    if ((rc = carve_scratch(base, n_t, wgs, S))) return rc;
+    WalkArgs a = make_args(t, p, n_t, a_old);
+    a.acc = acc;
+    a.counts = counts;
+    if (t->n_nodes == 0) {
+        // a single particle: no sources, every group list is empty
+        hipLaunchKernelGGL(k_fill_i32w, g256(groups), dim3(256), 0, st, S.group_head, groups, -1);
+        return eval_and_reduce<false>(p, a, S, 0, 0, st);
+    }
+    if ((rc = launch_traversal(t, p, n_t, active, a_old, S, wgs, st))) return rc;
+    const int64_t guess = t->unit_hint > 0 && t->unit_hint < S.cap_units ? t->unit_hint : S.cap_units;
+    if ((rc = eval_and_reduce<false>(p, a, S, 0, guess, st))) return rc;
+    bool overflow = false;
+    rc = traverse_finish(t, p, n_t, active, a_old, st, overflow);
+    t->lkey.valid = false;   // these lists are not the handle's: no token names them
+    if (rc) return rc;
+    if (overflow)
+        return sr_fail(SR_ENOMEM, "the interaction lists of %lld targets do not fit the %lld-byte scratch buffer "
+                       "of the allocation-free forward (acc and counts are not valid)",
+                       (long long)n_t, (long long)SR_NOALLOC_SCRATCH_BYTES);
+    if (t->n_units > guess) return eval_and_reduce<false>(p, a, S, guess, t->n_units - guess, st);
     return SR_OK;
 }
