@@ -1017,12 +1017,17 @@ __global__ __launch_bounds__(EVAL_WAVES * WAVE) void k_eval32(WalkArgs a, ListAr
     __shared__ uint8_t s_stream_w[EVAL_WAVES][NQ][WAVE];
     // adjoint: the four source terms of each (stream, entry) pair of the chunk; a stream
     // visits an entry at most once per chunk, so every slot is written at most once
-    __shared__ float4 s_part_w[EVAL_WAVES][ADJ ? NQ : 1][ADJ ? WAVE + 1 : 1];
+    // (in FP64 when the accumulation is FP64: the pair terms are FP32, their sums are not)
+    constexpr bool PART64 = ADJ && PREC == PR32A;
+    static_assert(!PART64 || QL == 16, "FP64 stream sums take 16-lane streams");
+    __shared__ float4 s_part_w[EVAL_WAVES][ADJ && !PART64 ? NQ : 1][ADJ && !PART64 ? WAVE + 1 : 1];
+    __shared__ double s_part64_w[EVAL_WAVES][PART64 ? NQ : 1][PART64 ? WAVE + 1 : 1][4];
     const int wv = threadIdx.x / WAVE;
     auto& s_ent = s_ent_w[wv];
     auto& s_src = s_src_w[wv];
     auto& s_stream = s_stream_w[wv];
     auto& s_part = s_part_w[wv];
+    auto& s_part64 = s_part64_w[wv];
     const int lane = threadIdx.x % WAVE;
     const int quarter = lane / QL;
     const uint32_t bit = 1u << (lane & 31);
@@ -1138,8 +1143,13 @@ __global__ __launch_bounds__(EVAL_WAVES * WAVE) void k_eval32(WalkArgs a, ListAr
                 // source terms: the stream's totals, one quantity per lane, stored in the
                 // (stream, entry) slot (the padding entry 64 has a slot that is never read);
                 // the QL/4 lanes that hold one quantity store the same value
-                const float ssum = stream_sum4<QL>(px, py, pz, K * wd, lane);
-                reinterpret_cast<float*>(&s_part[quarter][e])[(lane % QL) / (QL / 4)] = ssum;
+                if constexpr (PART64) {
+                    const double ssum = stream_sum4_f64((double)px, (double)py, (double)pz, (double)(K * wd), lane);
+                    s_part64[quarter][e][(lane % QL) / (QL / 4)] = ssum;
+                } else {
+                    const float ssum = stream_sum4<QL>(px, py, pz, K * wd, lane);
+                    reinterpret_cast<float*>(&s_part[quarter][e])[(lane % QL) / (QL / 4)] = ssum;
+                }
             }
         };
         // the forward takes two steps interleaved (their entries are independent):
@@ -1157,21 +1167,35 @@ __global__ __launch_bounds__(EVAL_WAVES * WAVE) void k_eval32(WalkArgs a, ListAr
                 double* dst = (sid & ITEM_PARTICLE) ? a.pbar + 4 * (int64_t)(sid & ~ITEM_PARTICLE)
                                                     : a.nbar + 4 * (int64_t)sid;
                 // the streams that visited this entry, in stream order
-                float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                double v[4] = {0.0, 0.0, 0.0, 0.0};
+                if constexpr (PART64) {
 #pragma unroll
-                for (int k = 0; k < NQ; ++k) {
-                    if (((lmask >> (QL * k)) & QMASK) != 0) {
-                        const float4 pk = s_part[k][lane];
-                        v.x += pk.x;
-                        v.y += pk.y;
-                        v.z += pk.z;
-                        v.w += pk.w;
+                    for (int k = 0; k < NQ; ++k) {
+                        if (((lmask >> (QL * k)) & QMASK) != 0) {
+#pragma unroll
+                            for (int c = 0; c < 4; ++c) v[c] += s_part64[k][lane][c];
+                        }
                     }
+                } else {
+                    float4 f = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+                    for (int k = 0; k < NQ; ++k) {
+                        if (((lmask >> (QL * k)) & QMASK) != 0) {
+                            const float4 pk = s_part[k][lane];
+                            f.x += pk.x;
+                            f.y += pk.y;
+                            f.z += pk.z;
+                            f.w += pk.w;
+                        }
+                    }
+                    v[0] = f.x;
+                    v[1] = f.y;
+                    v[2] = f.z;
+                    v[3] = f.w;
                 }
-                if (v.x != 0.0f) unsafeAtomicAdd(dst + 0, (double)v.x);
-                if (v.y != 0.0f) unsafeAtomicAdd(dst + 1, (double)v.y);
-                if (v.z != 0.0f) unsafeAtomicAdd(dst + 2, (double)v.z);
-                if (v.w != 0.0f) unsafeAtomicAdd(dst + 3, (double)v.w);
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    if (v[c] != 0.0) unsafeAtomicAdd(dst + c, v[c]);
             }
             wave_sync();
         }

@@ -296,8 +296,13 @@ def test_adjoint_fp32_close_to_oracle(sg, oracle, prec):
     gx, gm = oracle.adjoint(ref, w.params("fp64"), wt)
     ex = np.linalg.norm(dx.cpu().numpy() - gx, axis=1) / np.maximum(np.linalg.norm(gx, axis=1), 1e-6 * np.median(np.linalg.norm(gx, axis=1)))
     em = np.abs(dm.cpu().numpy() - gm) / np.maximum(np.abs(gm), 1e-6 * np.median(np.abs(gm)))
-    say(f"adjoint {prec}: dx median {np.median(ex):.3e} p99.9 {np.quantile(ex, 0.999):.3e}; dm median {np.median(em):.3e} p99.9 {np.quantile(em, 0.999):.3e}")
+    say(f"adjoint {prec}: dx median {np.median(ex):.3e} p99.9 {np.quantile(ex, 0.999):.3e}; "
+        f"dm median {np.median(em):.3e} p99 {np.quantile(em, 0.99):.3e} p99.9 {np.quantile(em, 0.999):.3e}")
     assert np.median(ex) <= 1e-4 and np.median(em) <= 1e-4
+    # dL/dx holds the forward's tail bar; the dL/dm tail is set by particles whose
+    # mass gradient nearly cancels (a sum of terms w . d of both signs), where the
+    # FP32 pair terms' own rounding dominates: its 99th percentile is held instead
+    assert np.quantile(ex, 0.999) <= 1e-4 and np.quantile(em, 0.99) <= 1e-4
 
 
 def test_error_paths(sg):
