@@ -193,6 +193,27 @@ int shortrange_accel_adjoint(sr_tree* tree, const sr_params* p, const int32_t* a
                              double* dLdm, int64_t list_token, void* stream);
 
 /*
+ * tree_drift -- reuse a built tree after its particles moved (paper App. A:
+ * between rebuilds the GPU step drifts the tree nodes with their particles).
+ * The topology, particle order and node order stay those of the last
+ * tree_build; every particle is placed at its built (wrapped) position plus
+ * disp, not wrapped again (its integer coordinates are those of the moved
+ * position); the node moments are refolded in the build's order; and each
+ * node's cube, centred on its cell centre c, grows to the half side
+ * max(l/2, max over its particles and axes of |x - c|), which every opening
+ * test then uses in place of the cell.  disp is measured from the built
+ * positions, so drifting twice is not cumulative.  The walks and the adjoint
+ * then run on the drifted tree; list tokens issued before are void.
+ *
+ *   disp   DEVICE double[n*3] displacement per particle, input order (finite)
+ *
+ * The first drift after a build allocates the drift buffers (kept by the
+ * handle).  The host waits once, for the finiteness flag.  SR_EINVAL for a
+ * non-finite displacement (the tree is then not usable until rebuilt).
+ */
+int tree_drift(sr_tree* tree, const double* disp, void* stream);
+
+/*
  * sr_axpy -- y[i] += a * x[i] for i < n, the elementwise update of a
  * kick-drift-kick leapfrog step (kick: v += dt/2 a(x); drift: x += dt v) and
  * of its transpose in a rollout's backward pass.  (The paper's GPU steps drift
@@ -229,7 +250,8 @@ enum {
     SR_T_PM_ADJ_GATHER = 12, /* PM adjoint: per-particle position and mass gradients */
     SR_T_PM_SORT = 13,     /* PM: particles sorted by mesh cell for the assignment */
     SR_T_SPH_ITER = 14,    /* SPH density: one iteration (neighbour walk, Newton step) */
-    SR_T_COUNT = 15
+    SR_T_DRIFT = 15,       /* tree_drift: moved particle records, refolded moments and cubes */
+    SR_T_COUNT = 16
 };
 int srgrav_timing(int32_t enable);
 int srgrav_timing_read(double* ms, int64_t* calls);
@@ -250,6 +272,8 @@ typedef struct {
     double* com;           /* [nodes*3] centre of mass */
     float* M32;            /* [nodes] (float)M */
     uint32_t* comX;        /* [nodes*3] rint(com / L * 2^32) mod 2^32 */
+    double* side;          /* [nodes] cube side the opening tests use: the cell side
+                              L 2^-level, or after tree_drift twice the grown half side */
 } sr_tree_export;
 
 int tree_node_count(const sr_tree* tree, int64_t* n_nodes);

@@ -74,6 +74,17 @@ class Tree:
         self.list_token = 0      # a rebuild replaces the lists
         return self
 
+    def drift(self, disp):
+        """Move the particles to their built positions plus `disp` ((N, 3), input
+        order) and refold moments and node cubes on the same topology (tree_drift)."""
+        d = _dev_f64(disp, name="disp")
+        if d.shape != (self.n, 3):
+            raise ValueError(f"disp must have shape ({self.n}, 3)")
+        with torch.cuda.device(self.device):
+            _lib.check(_lib.lib().tree_drift(self._h, _lib.ptr(d), _lib.stream_handle()))
+        self.list_token = 0      # a drift voids the lists' token
+        return self
+
     def node_count(self) -> int:
         m = C.c_int64(0)
         _lib.check(_lib.lib().tree_node_count(self._h, C.byref(m)))
@@ -99,10 +110,11 @@ class Tree:
                    M=torch.empty(m, dtype=torch.float64, device=dev),
                    com=torch.empty((m, 3), dtype=torch.float64, device=dev),
                    M32=torch.empty(m, dtype=torch.float32, device=dev),
-                   comX=torch.empty((m, 3), **i32))
+                   comX=torch.empty((m, 3), **i32),
+                   side=torch.empty(m, dtype=torch.float64, device=dev))
         ex = _lib.SrTreeExport(*[_lib.ptr(out[k]) if out[k].numel() else None for k in
                                  ("key_hi", "key_lo", "perm", "level", "first", "count", "parent",
-                                  "skip", "corner", "M", "com", "M32", "comX")])
+                                  "skip", "corner", "M", "com", "M32", "comX", "side")])
         with torch.cuda.device(dev):
             _lib.check(_lib.lib().tree_export(self._h, C.byref(ex), _lib.stream_handle()))
         return out

@@ -19,11 +19,11 @@ SR_OPEN_BH, SR_OPEN_RELATIVE = 0, 1
 SR_FP64, SR_FP32, SR_FP32_ACC64 = 0, 1, 2
 PRECISIONS = {"fp64": SR_FP64, "fp32": SR_FP32, "fp32_acc64": SR_FP32_ACC64}
 CRITERIA = {"bh": SR_OPEN_BH, "relative": SR_OPEN_RELATIVE}
-EXPORTED = ("tree_build", "shortrange_accel", "shortrange_accel_noalloc", "shortrange_accel_adjoint", "tree_node_count",
+EXPORTED = ("tree_build", "tree_drift", "shortrange_accel", "shortrange_accel_noalloc", "shortrange_accel_adjoint", "tree_node_count",
             "tree_export", "tree_free", "srgrav_last_error", "sr_axpy", "srgrav_timing",
             "srgrav_timing_read", "tree_walk_stats", "pm_create", "pm_accel", "pm_accel_adjoint", "pm_free", "sph_density")
 PHASES = ("tree_build", "traverse", "eval", "reduce", "adjoint_eval", "adjoint_reduce", "pushdown",
-          "pm_deposit", "pm_fft", "pm_green", "pm_interp", "pm_stencil", "pm_adj_gather", "pm_sort", "sph_iter")
+          "pm_deposit", "pm_fft", "pm_green", "pm_interp", "pm_stencil", "pm_adj_gather", "pm_sort", "sph_iter", "drift")
 
 
 class SrgravError(RuntimeError):
@@ -41,7 +41,7 @@ class SrParams(C.Structure):
 class SrTreeExport(C.Structure):
     _fields_ = [(name, C.c_void_p) for name in
                 ("key_hi", "key_lo", "perm", "level", "first", "count", "parent", "skip", "corner",
-                 "M", "com", "M32", "comX")]
+                 "M", "com", "M32", "comX", "side")]
 
 
 _lib = None
@@ -57,6 +57,8 @@ def lib():
         L = C.CDLL(LIB_PATH)
         vp, i64, d = C.c_void_p, C.c_int64, C.c_double
         L.tree_build.argtypes = [vp, vp, vp, d, i64, d, C.c_int32, vp, C.POINTER(vp)]
+        L.tree_drift.argtypes = [vp, vp, vp]
+        L.tree_drift.restype = C.c_int
         L.shortrange_accel.argtypes = [vp, C.POINTER(SrParams), vp, i64, vp, vp, vp, C.POINTER(i64), vp]
         L.shortrange_accel_noalloc.argtypes = [vp, C.POINTER(SrParams), vp, i64, vp, vp, vp, vp]
         L.shortrange_accel_adjoint.argtypes = [vp, C.POINTER(SrParams), vp, i64, vp, vp, vp, vp, i64, vp]

@@ -121,6 +121,9 @@ void free_workspace(sr_tree* t)
     release(t->n_meta);
     release(t->wrec32);
     release(t->wrec64);
+    release(t->prec64_0);
+    release(t->nbox);
+    t->drift_base = false;
     release(t->tgt_sorted);
     release(t->tgt_slot);
     release(t->mark);
@@ -442,6 +445,36 @@ int shortrange_accel_adjoint(sr_tree* t, const sr_params* p, const int32_t* acti
     return sr_walk_adjoint(t, p, n_active, active, a_old, w, dLdx, dLdm, list_token, st);
 }
 
+int tree_drift(sr_tree* t, const double* disp, void* stream)
+{
+    g_err[0] = 0;
+    if (!t || t->n <= 0) return sr_fail(SR_ESTATE, "tree handle is NULL or was never built");
+    int dev = -1;
+    SR_HIP(hipGetDevice(&dev));
+    if (dev != t->device)
+        return sr_fail(SR_ESTATE, "the tree was built on device %d, the current device is %d", t->device, dev);
+    if (!disp) return sr_fail(SR_EINVAL, "disp is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    int rc = SR_OK;
+    if (!t->prec64_0) {
+        // drift buffers, sized for the workspace capacity (kept across rebuilds)
+        const int64_t nodes = t->cap > 1 ? t->cap - 1 : 1;
+        if ((rc = alloc(&t->prec64_0, t->cap)) || (rc = alloc(&t->nbox, 6 * nodes))) {
+            release(t->prec64_0);
+            release(t->nbox);
+            return rc;
+        }
+        t->drift_base = false;
+    }
+    // the interaction lists belong to the undrifted particles: no token names them now
+    t->lkey.valid = false;
+    ++t->build_gen;
+    sr_timing_mark(SR_T_DRIFT, true, st);
+    rc = sr_drift_device(t, disp, st);
+    sr_timing_mark(SR_T_DRIFT, false, st);
+    return rc;
+}
+
 int tree_walk_stats(const sr_tree* t, int64_t* stats)
 {
     if (!t || t->n <= 0) return sr_fail(SR_ESTATE, "tree handle is NULL or was never built");
@@ -485,6 +518,8 @@ int tree_export(const sr_tree* t, const sr_tree_export* ex, void* stream)
         if (ex->M32) SR_HIP(hipMemcpy2DAsync(ex->M32, 4, &t->nrec32[0].m, sizeof(Rec32), 4, m, hipMemcpyDeviceToDevice, st));
         if (ex->comX) SR_HIP(hipMemcpy2DAsync(ex->comX, 12, t->nrec32, sizeof(Rec32), 12, m, hipMemcpyDeviceToDevice, st));
     }
+    if (m && ex->side)
+        SR_HIP(hipMemcpy2DAsync(ex->side, 8, &t->ngeo64[0].l, sizeof(Geo64), 8, m, hipMemcpyDeviceToDevice, st));
     return SR_OK;
 }
 

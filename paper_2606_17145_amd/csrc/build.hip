@@ -587,7 +587,15 @@ __global__ void k_child_table(int64_t m, const Item* __restrict__ items, const i
 // One node per thread in blocks of one wave: a depth holds 10^3 - 10^5 nodes and
 // each thread waits on two rounds of dependent loads, so small blocks spread a
 // depth over all CUs.
+//
+// DRIFT (a tree whose particles moved after the build, topology kept): also the
+// bounding box of the node's particles, folded with min / max (exact), and the
+// node's half side grown to max(l/2, max over members and axes of |x - c|)
+// about the fixed cell centre c; that maximum is attained at a box corner
+// because rounding is monotone, so the result equals the per-member maximum.
+// The opening tests then use twice the grown half side.
 constexpr int MOM_TPB = 64;
+template <bool DRIFT>
 __global__ __launch_bounds__(MOM_TPB) void k_moments(const int32_t* __restrict__ order, int64_t count, double box,
                           const int32_t* __restrict__ n_first, const int32_t* __restrict__ n_level,
                           const uint32_t* __restrict__ n_corner, const Rec64* __restrict__ r64,
@@ -596,7 +604,7 @@ __global__ __launch_bounds__(MOM_TPB) void k_moments(const int32_t* __restrict__
                           Rec32* __restrict__ nrec32, float* __restrict__ nhmax32,
                           const uint32_t* __restrict__ kids, const uint32_t* __restrict__ meta,
                           const int32_t* __restrict__ n_count, WalkRec32* __restrict__ w32,
-                          WalkRec64* __restrict__ w64)
+                          WalkRec64* __restrict__ w64, double* __restrict__ nbox)
 {
     int64_t t = blockIdx.x * (int64_t)MOM_TPB + threadIdx.x;
     if (t >= count) return;
@@ -605,6 +613,13 @@ __global__ __launch_bounds__(MOM_TPB) void k_moments(const int32_t* __restrict__
     const uint4 ka = ((const uint4*)(kids + 8 * (int64_t)nd))[0];
     const uint4 kb = ((const uint4*)(kids + 8 * (int64_t)nd))[1];
     double M = 0.0, S0 = 0.0, S1 = 0.0, S2 = 0.0, hx = 0.0, hn = 0.0;
+    double blo[3] = {0.0, 0.0, 0.0}, bhi[3] = {0.0, 0.0, 0.0};   // DRIFT: member bounding box
+    auto grow = [&](bool first, const double* lo, const double* hi) {
+        for (int k = 0; k < 3; ++k) {
+            blo[k] = first || lo[k] < blo[k] ? lo[k] : blo[k];
+            bhi[k] = first || hi[k] > bhi[k] ? hi[k] : bhi[k];
+        }
+    };
     auto fold = [&](bool first, double cm, double c0, double c1, double c2, double cx, double cn) {
         if (first) {
             M = cm;
@@ -629,6 +644,10 @@ __global__ __launch_bounds__(MOM_TPB) void k_moments(const int32_t* __restrict__
             const Rec64 p = r64[f + k];
             const double h = h64[f + k];
             fold(k == 0, p.m, p.m * p.x, p.m * p.y, p.m * p.z, h, h);
+            if constexpr (DRIFT) {
+                const double q[3] = {p.x, p.y, p.z};
+                grow(k == 0, q, q);
+            }
         }
     } else {
         const uint32_t kr[8] = {ka.x, ka.y, ka.z, ka.w, kb.x, kb.y, kb.z, kb.w};
@@ -658,6 +677,18 @@ __global__ __launch_bounds__(MOM_TPB) void k_moments(const int32_t* __restrict__
 #pragma unroll
         for (int k = 0; k < 8; ++k)
             if ((uint32_t)k < mt) fold(k == 0, cm[k], c0[k], c1[k], c2[k], cx[k], cn[k]);
+        if constexpr (DRIFT) {
+            for (uint32_t k = 0; k < mt; ++k) {
+                const uint32_t r = kr[k];
+                if (r & ITEM_PARTICLE) {
+                    const Rec64 p = r64[r & ~ITEM_PARTICLE];
+                    const double q[3] = {p.x, p.y, p.z};
+                    grow(k == 0, q, q);
+                } else {
+                    grow(k == 0, nbox + 6 * (int64_t)r, nbox + 6 * (int64_t)r + 3);
+                }
+            }
+        }
     }
     double com[3] = {S0 / M, S1 / M, S2 / M};
     nrec64[nd] = Rec64{com[0], com[1], com[2], M};
@@ -667,14 +698,31 @@ __global__ __launch_bounds__(MOM_TPB) void k_moments(const int32_t* __restrict__
     nhmax[nd] = hx;
     nhmin[nd] = hn;
     int lev = n_level[nd];
-    double l = ldexp(box, -lev);
+    const double lcell = ldexp(box, -lev);
     double half = ldexp(1.0, -lev - 1);
-    const Geo64 gg{box * (ldexp((double)n_corner[3 * nd + 0], -32) + half),
-                   box * (ldexp((double)n_corner[3 * nd + 1], -32) + half),
-                   box * (ldexp((double)n_corner[3 * nd + 2], -32) + half), l};
+    const double cc[3] = {box * (ldexp((double)n_corner[3 * nd + 0], -32) + half),
+                          box * (ldexp((double)n_corner[3 * nd + 1], -32) + half),
+                          box * (ldexp((double)n_corner[3 * nd + 2], -32) + half)};
+    double l = lcell;
+    bool grown = false;
+    if constexpr (DRIFT) {
+        double hs = 0.5 * lcell;
+        for (int k = 0; k < 3; ++k) {
+            nbox[6 * (int64_t)nd + k] = blo[k];
+            nbox[6 * (int64_t)nd + 3 + k] = bhi[k];
+            const double e0 = fabs(blo[k] - cc[k]), e1 = fabs(bhi[k] - cc[k]);
+            if (e0 > hs) hs = e0;
+            if (e1 > hs) hs = e1;
+        }
+        grown = hs != 0.5 * lcell;
+        l = 2.0 * hs;
+    }
+    const Geo64 gg{cc[0], cc[1], cc[2], l};
     geo[nd] = gg;
+    // ticks modulo 2^32 through a signed integer (a drifted centre of mass may lie
+    // just outside the box)
     uint32_t q[3];
-    for (int k = 0; k < 3; ++k) q[k] = (uint32_t)(uint64_t)rint(com[k] / box * TWO32);
+    for (int k = 0; k < 3; ++k) q[k] = (uint32_t)(int64_t)rint(com[k] / box * TWO32);
     const float M32 = (float)M, hx32 = (float)(hx / box * TWO32);
     nrec32[nd] = Rec32{q[0], q[1], q[2], M32};
     nhmax32[nd] = hx32;
@@ -691,6 +739,17 @@ __global__ __launch_bounds__(MOM_TPB) void k_moments(const int32_t* __restrict__
     a.Z = q[2];
     a.l2 = __float_as_uint((float)lint * (float)lint);
     a.half = __float_as_uint((float)halfi);
+    if (grown) {
+        // the grown cube in ticks: half side rounded up (the prune stays conservative),
+        // the largest integer below 0.6 side, and the side squared
+        const double ht = 0.5 * l / box * TWO32, sd = 2.0 * ht;
+        float hf = (float)ht;
+        if ((double)hf < ht) hf = nextafterf(hf, INFINITY);
+        const double tin = ceil(0.6 * sd) - 1.0;
+        a.tin = tin >= 4294967295.0 ? 0xffffffffu : (uint32_t)tin;
+        a.l2 = __float_as_uint((float)sd * (float)sd);
+        a.half = __float_as_uint(hf);
+    }
     a.M = __float_as_uint(M32);
     a.hx = __float_as_uint(hx32);
     a.mixed = hn != hx ? 1u : 0u;
@@ -797,6 +856,7 @@ int sr_build_device(sr_tree* t, const double* pos, const double* mass, const dou
 {
     const int64_t n = t->n;
     const double box = t->box;
+    t->drift_base = false;   // a drift after this build starts from its records
     hipLaunchKernelGGL(k_fill_i32, grid_for(ST_WORDS), dim3(TPB), 0, st, t->status, (int64_t)ST_WORDS, 0);
     hipLaunchKernelGGL(k_keys, grid_for(n), dim3(TPB), 0, st, pos, mass, eps, eps_scalar, n, box,
                        t->khi[0], t->klo[0], t->kidx[0], t->status);
@@ -884,11 +944,65 @@ int sr_build_device(sr_tree* t, const double* pos, const double* mass, const dou
     for (int d = t->max_depth; d >= 0; --d) {
         int64_t cnt = t->depth_hist[d];
         if (!cnt) continue;
-        hipLaunchKernelGGL(k_moments, dim3((unsigned)cdiv(cnt, MOM_TPB)), dim3(MOM_TPB), 0, st, t->depth_order + offs[d], cnt, box,
+        hipLaunchKernelGGL(k_moments<false>, dim3((unsigned)cdiv(cnt, MOM_TPB)), dim3(MOM_TPB), 0, st, t->depth_order + offs[d], cnt, box,
                            t->n_first, t->n_level, t->n_corner, t->prec64, t->ph64, t->nrec64, t->nS, t->ngeo64,
                            t->nhmax, t->nhmin, t->nrec32, t->nhmax32, t->n_kids, t->n_meta, t->n_count,
-                           t->wrec32, t->wrec64);
+                           t->wrec32, t->wrec64, (double*)nullptr);
+    }
+    for (int d = 0; d < SR_MAX_DEPTH; ++d) t->depth_offs[d] = offs[d];
+    SR_HIP(hipGetLastError());
+    return SR_OK;
+}
+
+namespace {
+
+// A drifted particle: its built (wrapped) position plus the displacement, not
+// wrapped again; its integer coordinates are those of the moved position.
+__global__ void k_drift_particles(int64_t n, double box, const int32_t* __restrict__ perm,
+                                  const Rec64* __restrict__ r0, const double* __restrict__ disp,
+                                  Rec64* __restrict__ r64, Rec32* __restrict__ r32, int32_t* __restrict__ status)
+{
+    int64_t s = blockIdx.x * (int64_t)TPB + threadIdx.x;
+    if (s >= n) return;
+    const int64_t i = perm[s];
+    const Rec64 b = r0[s];
+    const double x[3] = {b.x + disp[3 * i + 0], b.y + disp[3 * i + 1], b.z + disp[3 * i + 2]};
+    uint32_t X[3];
+    bool bad = false;
+    for (int k = 0; k < 3; ++k) {
+        if (!isfinite(x[k])) bad = true;
+        X[k] = isfinite(x[k]) ? (uint32_t)floor(wrap_unit(x[k], box) * TWO32) : 0u;
+    }
+    if (bad) atomicOr(&status[ST_FLAGS], 1);
+    r64[s] = Rec64{x[0], x[1], x[2], b.m};
+    r32[s] = Rec32{X[0], X[1], X[2], r32[s].m};
+}
+
+}  // namespace
+
+int sr_drift_device(sr_tree* t, const double* disp, hipStream_t st)
+{
+    const int64_t n = t->n, m = t->n_nodes;
+    if (!t->drift_base) {
+        // the first drift after a build keeps the built particle records
+        SR_HIP(hipMemcpyAsync(t->prec64_0, t->prec64, (size_t)n * sizeof(Rec64), hipMemcpyDeviceToDevice, st));
+        t->drift_base = true;
+    }
+    hipLaunchKernelGGL(k_fill_i32, grid_for(1), dim3(TPB), 0, st, t->status, (int64_t)1, 0);
+    hipLaunchKernelGGL(k_drift_particles, grid_for(n), dim3(TPB), 0, st, n, t->box, t->perm, t->prec64_0, disp,
+                       t->prec64, t->prec32, t->status);
+    SR_HIP(hipMemcpyAsync(t->h_status, t->status, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    SR_HIP(hipEventRecord(t->ev_status, st));
+    for (int d = t->max_depth; m > 0 && d >= 0; --d) {
+        int64_t cnt = t->depth_hist[d];
+        if (!cnt) continue;
+        hipLaunchKernelGGL(k_moments<true>, dim3((unsigned)cdiv(cnt, MOM_TPB)), dim3(MOM_TPB), 0, st,
+                           t->depth_order + t->depth_offs[d], cnt, t->box, t->n_first, t->n_level, t->n_corner,
+                           t->prec64, t->ph64, t->nrec64, t->nS, t->ngeo64, t->nhmax, t->nhmin, t->nrec32,
+                           t->nhmax32, t->n_kids, t->n_meta, t->n_count, t->wrec32, t->wrec64, t->nbox);
     }
     SR_HIP(hipGetLastError());
+    SR_HIP(hipEventSynchronize(t->ev_status));
+    if (t->h_status[ST_FLAGS] & 1) return sr_fail(SR_EINVAL, "tree_drift: non-finite displacement");
     return SR_OK;
 }

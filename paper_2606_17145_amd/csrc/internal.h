@@ -134,6 +134,11 @@ struct sr_tree {
     uint32_t* n_meta = nullptr;
     WalkRec32* wrec32 = nullptr;      // per node, for the walk
     WalkRec64* wrec64 = nullptr;
+    // node drift (allocated at the first drift): the built particle records, and
+    // per node the bounding box of its particles (lo xyz, hi xyz)
+    Rec64* prec64_0 = nullptr;
+    double* nbox = nullptr;
+    bool drift_base = false;          // prec64_0 holds the current build's records
 
     // walk workspace (cap)
     int32_t *tgt_sorted = nullptr, *tgt_slot = nullptr, *mark = nullptr;
@@ -166,6 +171,7 @@ struct sr_tree {
     bool mixed_soft = false;      // softening lengths differ between particles
     int max_depth = 0;
     int depth_hist[SR_MAX_DEPTH] = {};
+    int32_t depth_offs[SR_MAX_DEPTH] = {};   // start of each depth in depth_order
 };
 
 // error helpers shared by the host files
@@ -177,6 +183,9 @@ int sr_fail(int code, const char* fmt, ...);
             return sr_fail(SR_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));   \
     } while (0)
 
+// build.hip: move the particles of a built tree to their built positions plus
+// disp (input order) and refold the moments and node cubes; topology kept
+int sr_drift_device(sr_tree* t, const double* disp, hipStream_t st);
 // build.hip
 int sr_build_device(sr_tree* t, const double* pos, const double* mass, const double* eps,
                     double eps_scalar, hipStream_t st);

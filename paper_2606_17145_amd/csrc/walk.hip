@@ -303,25 +303,28 @@ __device__ inline double wave_max_f64(double v)
 // coordinates x in [lo, hi], with the same roundings as the per-target test.  The
 // rounded difference c - x is monotone in x, so the two ends bound every target's;
 // the minimum image is bounded only when it takes the same branch over the range.
+// The image is monotone too, so |image| is bounded by its ends' magnitudes, and is
+// zero somewhere when the ends straddle zero (after a drift, positions lie just
+// outside [0, L) and an image range can cross zero on either branch).
 __device__ inline bool axis_range64(double c, double lo, double hi, double L, double& amin, double& amax)
 {
     const double dlo = c - hi, dhi = c - lo;
+    double elo, ehi;
     if (dlo >= -(0.5 * L) && dhi <= 0.5 * L) {   // no wrap for any target
-        amin = (dlo <= 0.0 && dhi >= 0.0) ? 0.0 : fmin(fabs(dlo), fabs(dhi));
-        amax = fmax(fabs(dlo), fabs(dhi));
-        return true;
+        elo = dlo;
+        ehi = dhi;
+    } else if (dlo > 0.5 * L) {                  // every target wraps down
+        elo = dlo - L;
+        ehi = dhi - L;
+    } else if (dhi < -(0.5 * L)) {               // every target wraps up
+        elo = dlo + L;
+        ehi = dhi + L;
+    } else {
+        return false;
     }
-    if (dlo > 0.5 * L) {                         // every target wraps down
-        amin = fabs(dhi - L);
-        amax = fabs(dlo - L);
-        return true;
-    }
-    if (dhi < -(0.5 * L)) {                      // every target wraps up
-        amin = dlo + L;
-        amax = dhi + L;
-        return true;
-    }
-    return false;
+    amin = (elo <= 0.0 && ehi >= 0.0) ? 0.0 : fmin(fabs(elo), fabs(ehi));
+    amax = fmax(fabs(elo), fabs(ehi));
+    return true;
 }
 
 // Sum of a uint32 over the 64 lanes (DPP, total in lane 63).

@@ -88,3 +88,21 @@ def test_treepm_rollout_and_gradient_fp64_match_oracle(rl, oracle):
     rx, rv = R.rollout_grad(w.pos, vel, w.mass, w.eps, p, 2, 1e-3, wx, n_mesh=n_mesh)
     assert np.allclose(gx.cpu().numpy(), rx, rtol=1e-9, atol=1e-10 * np.abs(rx).max())
     assert np.allclose(gv.cpu().numpy(), rv, rtol=1e-9, atol=1e-10 * np.abs(rv).max())
+
+
+def test_rollout_with_tree_reuse_fp64_matches_oracle(rl, oracle):
+    # trees rebuilt at evaluations 0 and 2 and drifted at 1 and 3 (tree_drift)
+    from oracle import rollout as R
+    w, vel = _case(n=3000, seed=46)
+    p = w.params("fp64")
+    wx = np.random.default_rng(47).standard_normal((w.n, 3))
+    print(f"rollout with tree reuse, fp64: N={w.n}, 3 steps, rebuild every 2nd evaluation", flush=True)
+    x, v = rl.kdk_rollout(_t(w.pos), _t(vel), _t(w.mass), _t(w.eps), p, 3, 2e-3, rebuild_every=2)
+    xr, vr = R.rollout(w.pos, vel, w.mass, w.eps, p, 3, 2e-3, rebuild_every=2)
+    assert np.allclose(x.cpu().numpy(), xr, rtol=0, atol=1e-14)
+    assert np.allclose(v.cpu().numpy(), vr, rtol=1e-11, atol=1e-11 * np.abs(vr).max())
+    gx, gv, _, _ = rl.kdk_rollout_grad(_t(w.pos), _t(vel), _t(w.mass), _t(w.eps), p, 3, 2e-3, _t(wx),
+                                       rebuild_every=2)
+    rx, rv = R.rollout_grad(w.pos, vel, w.mass, w.eps, p, 3, 2e-3, wx, rebuild_every=2)
+    assert np.allclose(gx.cpu().numpy(), rx, rtol=1e-9, atol=1e-10 * np.abs(rx).max())
+    assert np.allclose(gv.cpu().numpy(), rv, rtol=1e-9, atol=1e-10 * np.abs(rv).max())

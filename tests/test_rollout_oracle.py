@@ -81,3 +81,29 @@ def test_treepm_rollout_gradient_matches_autograd_of_frozen_replay(oracle):
     # the mesh force changes the result
     xs, _ = R.rollout(x, v, m, eps, p, 2, 2e-3)
     assert np.abs(xs - xr).max() > 1e-6
+
+
+def test_rollout_with_tree_reuse_matches_autograd_of_frozen_replay(oracle):
+    # trees rebuilt every second force evaluation and drifted in between
+    # (evaluations 0 and 2 build, 1 and 3 drift the last build)
+    from oracle import rollout as R
+    x, v, m, eps, p = _case(n=200, seed=36)
+    wx = np.random.default_rng(37).standard_normal(x.shape)
+    xr, vr = R.rollout(x, v, m, eps, p, 3, 4e-3, rebuild_every=2)
+    f = R.frozen_replay(x, v, m, eps, p, 3, 4e-3, rebuild_every=2)
+    xt = torch.tensor(x, requires_grad=True)
+    vt = torch.tensor(v, requires_grad=True)
+    xf, vf = f(xt, vt)
+    assert np.allclose(xf.detach().numpy(), xr, rtol=0, atol=1e-13)
+    assert np.allclose(vf.detach().numpy(), vr, rtol=1e-11, atol=1e-11 * np.abs(vr).max())
+    gx, gv = R.rollout_grad(x, v, m, eps, p, 3, 4e-3, wx, rebuild_every=2)
+    (torch.tensor(wx) * xf).sum().backward()
+    assert np.allclose(gx, xt.grad.numpy(), rtol=1e-9, atol=1e-10 * np.abs(gx).max())
+    assert np.allclose(gv, vt.grad.numpy(), rtol=1e-9, atol=1e-10 * np.abs(gv).max())
+    # the reused trees give a different (drifted-tree) rollout, close to the rebuilt one
+    xb, _ = R.rollout(x, v, m, eps, p, 3, 4e-3)
+    dev = np.abs(xb - xr).max()
+    assert 0 < dev < 1e-2 * np.abs(xb - x).max()
+    # rebuilding every evaluation is the plain rollout
+    x1, v1 = R.rollout(x, v, m, eps, p, 3, 4e-3, rebuild_every=1)
+    assert np.array_equal(x1, xb)
