@@ -65,6 +65,105 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+BUILD_BYTES_PER_PARTICLE = 170     # algorithmic HBM bytes of the tree build (radix passes excluded)
+
+
+def timed_ms(torch, fn, reps):
+    """Median milliseconds of fn() over `reps` runs, HIP events on the current stream
+    (the stream every library call of this script is launched on)."""
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return float(np.median(ts))
+
+
+def flip_rate(c32, c64):
+    """Fraction of targets whose FP32 interaction counts differ from the FP64 ones."""
+    a, b = c32.cpu().numpy(), c64.cpu().numpy()
+    return float(np.mean(np.any(a != b, axis=1)))
+
+
+def other_configs(torch, sg, WL, dev, reps):
+    """The remaining workloads, each timed on its own: uniform_32k (FP64 reference
+    case), clustered_2m_active (relative criterion, 10% active subset) and the
+    zoom_6m 8-step FP32 rollout with and without tree reuse."""
+    out = {}
+    t = lambda a, **k: torch.tensor(a, device=dev, **k)   # noqa: E731
+
+    # uniform 32^3, FP64 (and FP32 beside it)
+    w = WL.uniform_32k()
+    pos, mass, eps = t(w.pos), t(w.mass), t(w.eps)
+    tree = sg.Tree()
+    b_ms = timed_ms(torch, lambda: sg.tree_build(pos, mass, eps=eps, tree=tree), reps)
+    res = {}
+    f64 = timed_ms(torch, lambda: res.__setitem__("64", sg.shortrange_accel(tree, w.params("fp64"))), reps)
+    f32 = timed_ms(torch, lambda: res.__setitem__("32", sg.shortrange_accel(tree, w.params("fp32"))), reps)
+    inter = int(res["64"][1].cpu().numpy().astype(np.int64).sum())
+    out["uniform_32k"] = {"n": w.n, "build_ms": b_ms, "walk_fp64_ms": f64, "walk_fp32_ms": f32,
+                          "interactions": inter, "walk_fp64_interactions_per_s": inter / (f64 * 1e-3),
+                          "walk_fp32_interactions_per_s": inter / (f32 * 1e-3),
+                          "particles_per_s_build_plus_fp64_walk": w.n / ((b_ms + f64) * 1e-3),
+                          "fp32_count_flip_rate": flip_rate(res["32"][1], res["64"][1])}
+    log(f"bench: uniform_32k build {b_ms:.3f} ms, fp64 walk {f64:.3f} ms, fp32 walk {f32:.3f} ms")
+    del tree
+
+    # clustered 128^3, relative criterion, 209,715 active targets; a_old = |a| of the
+    # FP64 Barnes-Hut walk of all particles (the same walk the oracle defines)
+    w = WL.clustered_2m_active()
+    pos, mass, eps = t(w.pos), t(w.mass), t(w.eps)
+    tree = sg.Tree()
+    b_ms = timed_ms(torch, lambda: sg.tree_build(pos, mass, eps=eps, tree=tree), reps)
+    a_bh, _ = sg.shortrange_accel(tree, dict(w.params("fp64"), criterion="bh", theta=0.5), counts=False)
+    a_old = a_bh.norm(dim=1).contiguous()
+    del a_bh
+    act = t(w.active)
+    res = {}
+    f32 = timed_ms(torch, lambda: res.__setitem__("32", sg.shortrange_accel(tree, w.params("fp32"), active=act,
+                                                                           a_old=a_old)), reps)
+    f64 = timed_ms(torch, lambda: res.__setitem__("64", sg.shortrange_accel(tree, w.params("fp64"), active=act,
+                                                                           a_old=a_old)), reps)
+    inter32 = int(res["32"][1].cpu().numpy().astype(np.int64).sum())
+    inter64 = int(res["64"][1].cpu().numpy().astype(np.int64).sum())
+    out["clustered_2m_active"] = {
+        "n": w.n, "targets": int(w.active.size), "criterion": "relative", "alpha": w.alpha, "theta": w.theta,
+        "build_ms": b_ms, "build_gbs_algorithmic": BUILD_BYTES_PER_PARTICLE * w.n / (b_ms * 1e-3) / 1e9,
+        "walk_fp32_ms": f32, "walk_fp64_ms": f64, "interactions_fp32": inter32, "interactions_fp64": inter64,
+        "walk_fp32_interactions_per_s": inter32 / (f32 * 1e-3),
+        "walk_fp64_interactions_per_s": inter64 / (f64 * 1e-3),
+        "fp32_over_fp64_walk_speedup": f64 / f32,
+        "fp32_count_flip_rate": flip_rate(res["32"][1], res["64"][1]),
+        "a_old": "|a| of the FP64 Barnes-Hut (theta 0.5) walk of all particles, on the device"}
+    log(f"bench: clustered_2m_active build {b_ms:.3f} ms, fp32 walk {f32:.3f} ms, fp64 walk {f64:.3f} ms")
+    del tree, res, a_old
+
+    # zoom-in, 6,291,456 particles: 8 KDK steps FP32, forward rollout and its
+    # gradient, rebuilding every evaluation and every second evaluation
+    from paper_2606_17145_amd import rollout as RL
+    w = WL.zoom_6m()
+    pos, mass, eps = t(w.pos), t(w.mass), t(w.eps)
+    vel, lw = t(w.extra["vel"]), t(w.extra["loss_w"])
+    ns, dt = w.extra["n_steps"], w.extra["dt"]
+    p = w.params("fp32")
+    z = {"n": w.n, "steps": ns, "dt": dt, "precision": "fp32"}
+    for k in (1, 2):
+        fwd = timed_ms(torch, lambda: RL.kdk_rollout(pos, vel, mass, eps, p, ns, dt, rebuild_every=k), 2)
+        grad = timed_ms(torch, lambda: RL.kdk_rollout_grad(pos, vel, mass, eps, p, ns, dt, lw, rebuild_every=k), 2)
+        z[f"rebuild_every_{k}"] = {"forward_ms": fwd, "forward_and_gradient_ms": grad}
+        log(f"bench: zoom_6m rollout rebuild_every={k}: forward {fwd:.1f} ms, gradient {grad:.1f} ms")
+    x1, _ = RL.kdk_rollout(pos, vel, mass, eps, p, ns, dt)
+    x2, _ = RL.kdk_rollout(pos, vel, mass, eps, p, ns, dt, rebuild_every=2)
+    moved = (x1 - pos).norm(dim=1)
+    z["reuse_position_difference_rel"] = float((x2 - x1).norm(dim=1).max() / moved.max())
+    z["tree_reuse_forward_time_saved"] = 1.0 - z["rebuild_every_2"]["forward_ms"] / z["rebuild_every_1"]["forward_ms"]
+    out["zoom_6m_rollout"] = z
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,6 +171,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-error-check", action="store_true")
+    ap.add_argument("--no-other-configs", action="store_true",
+                    help="skip the uniform_32k, clustered_2m_active and zoom_6m legs")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="copy a buffer of this size once before the run (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -157,6 +258,7 @@ def main():
         t64.append(e64[0].elapsed_time(e64[1]))
     fwd64_ms = float(np.mean(t64))
     inter64 = int(c64.cpu().numpy().astype(np.int64).sum())
+    flips = flip_rate(cnt, c64)
     log(f"bench: fwd64 {fwd64_ms:.3f} ms")
 
     # PM leg (not in the step): long-range force of the same particles on the 128^3 mesh
@@ -228,6 +330,7 @@ def main():
         "adjoint_fp32_interactions_per_s": inter / (adj_ms * 1e-3),
         "walk_fp64_interactions_per_s": inter64 / (fwd64_ms * 1e-3),
         "fp32_over_fp64_walk_speedup": fwd64_ms / fwd_ms,
+        "fp32_count_flip_rate": flips,
         "particles_per_s": w.n / (ms_step * 1e-3),
     }
     # per-kernel average launch durations from the library's events
@@ -261,6 +364,11 @@ def main():
                         "algorithmic_tflops": work[ph] / (avg[ph] * 1e-3) / 1e12}
     out["valu_counters"] = valu or None
 
+    if not args.no_other_configs:
+        del tree
+        torch.cuda.empty_cache()
+        out["configs"] = other_configs(torch, sg, WL, dev, reps=max(3, args.steps // 4))
+
     if not args.no_error_check:
         from oracle import oracle as O
         ref = O.Tree(w.pos, w.mass, w.eps)
@@ -278,6 +386,7 @@ def main():
     if not args.no_cpu_baseline:
         # the oracle on the host: the whole step (tree build, walk and adjoint of all targets) in FP64
         from oracle import oracle as O
+        O.use_native_build()     # -O3 -march=native for this host
         wt = WL.adjoint_weights(w.n)
         t0 = time.perf_counter()
         ref = O.Tree(w.pos, w.mass, w.eps)
@@ -287,7 +396,9 @@ def main():
         cpu_model = next((ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo")
                           if ln.startswith("model name")), "unknown") if os.path.exists("/proc/cpuinfo") else "unknown"
         out["cpu_baseline"] = {"value": float(cs.sum()) / cpu_s, "unit": "interactions/s",
-                               "cores": O.num_threads(), "kind": "oracle", "cpu_model": cpu_model,
+                               "cores": O.num_threads(), "host_cpus": os.cpu_count(),
+                               "build": "gcc -O3 -march=native -ffp-contract=off -fopenmp",
+                               "kind": "oracle", "cpu_model": cpu_model,
                                "sample": "the whole step on the same workload: FP64 oracle tree build of all "
                                          "262,144 particles, walk and adjoint of all 262,144 targets"}
         log(f"bench: oracle {cpu_s:.2f} s on {O.num_threads()} threads")
