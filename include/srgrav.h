@@ -256,6 +256,15 @@ enum {
 int srgrav_timing(int32_t enable);
 int srgrav_timing_read(double* ms, int64_t* calls);
 
+/*
+ * srgrav_inject_alloc_failure -- test hook for the out-of-memory paths: with
+ * after >= 0, the library's device allocation that follows the next `after`
+ * successful ones fails as if hipMalloc had (SR_ENOMEM), once; a negative
+ * value switches the injection off.  Process-wide; host-pinned buffers and
+ * hipFFT's own plan memory are not covered.  Always SR_OK.
+ */
+int srgrav_inject_alloc_failure(int64_t after);
+
 /* Internal arrays of a built tree, copied into caller buffers (DEVICE; any may
  * be NULL).  Node arrays need room for tree_node_count() entries. */
 typedef struct {

@@ -21,7 +21,7 @@ PRECISIONS = {"fp64": SR_FP64, "fp32": SR_FP32, "fp32_acc64": SR_FP32_ACC64}
 CRITERIA = {"bh": SR_OPEN_BH, "relative": SR_OPEN_RELATIVE}
 EXPORTED = ("tree_build", "tree_drift", "shortrange_accel", "shortrange_accel_noalloc", "shortrange_accel_adjoint", "tree_node_count",
             "tree_export", "tree_free", "srgrav_last_error", "sr_axpy", "srgrav_timing",
-            "srgrav_timing_read", "tree_walk_stats", "pm_create", "pm_accel", "pm_accel_adjoint", "pm_free", "sph_density")
+            "srgrav_timing_read", "srgrav_inject_alloc_failure", "tree_walk_stats", "pm_create", "pm_accel", "pm_accel_adjoint", "pm_free", "sph_density")
 PHASES = ("tree_build", "traverse", "eval", "reduce", "adjoint_eval", "adjoint_reduce", "pushdown",
           "pm_deposit", "pm_fft", "pm_green", "pm_interp", "pm_stencil", "pm_adj_gather", "pm_sort", "sph_iter", "drift")
 
@@ -70,6 +70,8 @@ def lib():
         L.srgrav_timing.restype = C.c_int
         L.srgrav_timing_read.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.srgrav_timing_read.restype = C.c_int
+        L.srgrav_inject_alloc_failure.argtypes = [C.c_int64]
+        L.srgrav_inject_alloc_failure.restype = C.c_int
         L.tree_walk_stats.argtypes = [vp, C.POINTER(C.c_int64)]
         L.tree_walk_stats.restype = C.c_int
         L.tree_free.argtypes = [vp]

@@ -6,6 +6,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <atomic>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -15,6 +16,10 @@
 
 namespace {
 thread_local char g_err[512] = "";
+
+// allocation-failure injection for tests: -1 off, k >= 0 fails the allocation
+// after the next k successful ones
+std::atomic<int64_t> g_alloc_fail_after{-1};
 
 // phase timing state (process-wide)
 struct TimedLaunch {
@@ -34,7 +39,7 @@ int alloc(T** p, int64_t count)
 {
     *p = nullptr;
     if (count <= 0) count = 1;
-    hipError_t e = hipMalloc((void**)p, sizeof(T) * (size_t)count);
+    hipError_t e = sr_device_malloc((void**)p, sizeof(T) * (size_t)count);
     if (e != hipSuccess) {
         *p = nullptr;
         (void)hipGetLastError();
@@ -255,10 +260,20 @@ int check_call(sr_tree* t, const sr_params* p, const int32_t* active, int64_t n_
 }
 }  // namespace
 
-int sr_front_reserve(sr_tree* t, int64_t waves, int64_t cap)
+hipError_t sr_device_malloc(void** p, size_t bytes)
+{
+    if (g_alloc_fail_after.load() >= 0 && g_alloc_fail_after.fetch_sub(1) == 0) {
+        *p = nullptr;
+        return hipErrorOutOfMemory;
+    }
+    return hipMalloc(p, bytes);
+}
+
+int sr_front_reserve(sr_tree* t, int64_t waves, int64_t cap, hipStream_t st)
 {
     if (waves <= t->n_front_waves && cap <= t->cap_front) return SR_OK;
-    SR_HIP(hipDeviceSynchronize());
+    // the old frontier may still be read by work queued on the call's stream
+    SR_HIP(hipStreamSynchronize(st));
     release(t->frontier);
     // per wave: two levels of node ids (u32) and masks (u64)
     int rc = alloc(&t->frontier, waves * cap * 6);
@@ -271,11 +286,11 @@ int sr_front_reserve(sr_tree* t, int64_t waves, int64_t cap)
     return SR_OK;
 }
 
-int sr_list_reserve(sr_tree* t, int64_t groups, int64_t chunks, int64_t units)
+int sr_list_reserve(sr_tree* t, int64_t groups, int64_t chunks, int64_t units, hipStream_t st)
 {
     if (groups <= t->cap_groups && chunks <= t->cap_chunks && units <= t->cap_units) return SR_OK;
-    // the old lists may still be read by queued work
-    SR_HIP(hipDeviceSynchronize());
+    // the old lists may still be read by work queued on the call's stream
+    SR_HIP(hipStreamSynchronize(st));
     free_lists(t);
     int rc = SR_OK;
 #define A(ptr, count)                              \
@@ -364,7 +379,9 @@ int tree_build(const double* pos, const double* mass, const double* eps, double 
         free_workspace(t);
         int rc = allocate_workspace(t, n);
         if (rc) {
+            // the old tree is gone with its workspace: the handle reads as never built
             if (fresh) delete t;
+            else t->n = 0;
             return rc;
         }
     }
@@ -532,6 +549,12 @@ int sr_axpy(void* y, int32_t y_type, const void* x, int32_t x_type, double a, in
     if ((y_type != SR_F64 && y_type != SR_F32) || (x_type != SR_F64 && x_type != SR_F32))
         return sr_fail(SR_EINVAL, "element types must be SR_F64 or SR_F32");
     return sr_axpy_device(y, y_type, x, x_type, a, n, (hipStream_t)stream);
+}
+
+int srgrav_inject_alloc_failure(int64_t after)
+{
+    g_alloc_fail_after.store(after < 0 ? -1 : after);
+    return SR_OK;
 }
 
 int srgrav_timing(int32_t enable)

@@ -211,7 +211,11 @@ int sr_axpy_device(void* y, int y_type, const void* x, int x_type, double a, int
 bool sr_timing_on();
 void sr_timing_mark(int phase, bool start, hipStream_t st);
 
-// api.hip: make room for the lists of `groups` target groups, `chunks` chunks and `units` units
-int sr_list_reserve(sr_tree* t, int64_t groups, int64_t chunks, int64_t units);
+// api.hip: make room for the lists of `groups` target groups, `chunks` chunks and `units`
+// units (waits for stream st before it frees smaller lists)
+int sr_list_reserve(sr_tree* t, int64_t groups, int64_t chunks, int64_t units, hipStream_t st);
 // api.hip: frontier scratch of `waves` persistent traversal waves, `cap` entries per level
-int sr_front_reserve(sr_tree* t, int64_t waves, int64_t cap);
+int sr_front_reserve(sr_tree* t, int64_t waves, int64_t cap, hipStream_t st);
+// api.hip: every device allocation of the library (hipMalloc, or the injected failure
+// of srgrav_inject_alloc_failure)
+hipError_t sr_device_malloc(void** p, size_t bytes);

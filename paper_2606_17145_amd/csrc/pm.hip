@@ -351,9 +351,9 @@ int pm_create(int32_t n_mesh, sr_pm** out)
     m->n = n_mesh;
     m->device = dev;
     const int64_t n3 = (int64_t)n_mesh * n_mesh * n_mesh, nc = (int64_t)n_mesh * n_mesh * (n_mesh / 2 + 1);
-    const bool ok = hipMalloc((void**)&m->mesh, sizeof(double) * n3) == hipSuccess &&
-                    hipMalloc((void**)&m->spec, sizeof(hipfftDoubleComplex) * nc) == hipSuccess &&
-                    hipMalloc((void**)&m->axis, sizeof(double) * n_mesh) == hipSuccess;
+    const bool ok = sr_device_malloc((void**)&m->mesh, sizeof(double) * n3) == hipSuccess &&
+                    sr_device_malloc((void**)&m->spec, sizeof(hipfftDoubleComplex) * nc) == hipSuccess &&
+                    sr_device_malloc((void**)&m->axis, sizeof(double) * n_mesh) == hipSuccess;
     if (!ok) {
         pm_release(m);
         delete m;
@@ -419,11 +419,11 @@ int pm_convolve(sr_pm* m, double* src, double* dst, double box, double r_s, doub
 }
 
 // Particle workspace for n particles; a larger n frees and reallocates it (the
-// free waits for the device).
-int pm_reserve(sr_pm* m, int64_t n, const char* fn)
+// free waits for the call's stream).
+int pm_reserve(sr_pm* m, int64_t n, const char* fn, hipStream_t st)
 {
     if (n <= m->cap) return SR_OK;
-    if (m->cap > 0) SR_HIP(hipDeviceSynchronize());     // earlier calls may still use the buffers
+    if (m->cap > 0) SR_HIP(hipStreamSynchronize(st));   // earlier calls may still use the buffers
     for (int b = 0; b < 2; ++b) {
         (void)hipFree(m->key[b]);
         (void)hipFree(m->idx[b]);
@@ -433,10 +433,10 @@ int pm_reserve(sr_pm* m, int64_t n, const char* fn)
     (void)hipFree(m->hist);
     m->hist = nullptr;
     m->cap = 0;
-    bool ok = hipMalloc((void**)&m->hist, sizeof(uint32_t) * sr_sort_hist_words(n)) == hipSuccess;
+    bool ok = sr_device_malloc((void**)&m->hist, sizeof(uint32_t) * sr_sort_hist_words(n)) == hipSuccess;
     for (int b = 0; b < 2 && ok; ++b)
-        ok = hipMalloc((void**)&m->key[b], sizeof(uint64_t) * n) == hipSuccess &&
-             hipMalloc((void**)&m->idx[b], sizeof(uint32_t) * n) == hipSuccess;
+        ok = sr_device_malloc((void**)&m->key[b], sizeof(uint64_t) * n) == hipSuccess &&
+             sr_device_malloc((void**)&m->idx[b], sizeof(uint32_t) * n) == hipSuccess;
     if (!ok) return sr_fail(SR_ENOMEM, "%s: device allocation for %lld particles failed", fn, (long long)n);
     m->cap = n;
     return SR_OK;
@@ -463,7 +463,7 @@ int pm_potential(sr_pm* m, const double* pos, const double* mass, int64_t n, dou
 {
     const int N = m->n;
     const double h = box / N;
-    PM_TRY(pm_reserve(m, n, fn));
+    PM_TRY(pm_reserve(m, n, fn, st));
     const uint64_t n3 = (uint64_t)N * N * N;
     int bits = 1;
     while (bits < 64 && (n3 - 1) >> bits) ++bits;
@@ -510,8 +510,8 @@ int pm_accel_adjoint(sr_pm* m, const double* pos, const double* mass, int64_t n,
     const int N = m->n;
     const int64_t n3 = (int64_t)N * N * N;
     if (!m->work) {
-        if (hipMalloc((void**)&m->work, sizeof(double) * n3) != hipSuccess ||
-            hipMalloc((void**)&m->chi, sizeof(double) * n3) != hipSuccess) {
+        if (sr_device_malloc((void**)&m->work, sizeof(double) * n3) != hipSuccess ||
+            sr_device_malloc((void**)&m->chi, sizeof(double) * n3) != hipSuccess) {
             (void)hipFree(m->work);
             m->work = nullptr;
             m->chi = nullptr;

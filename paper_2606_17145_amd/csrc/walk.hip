@@ -1721,9 +1721,9 @@ int traverse_launch(sr_tree* t, const sr_params* p, int64_t n_t, const int32_t* 
     // every wave of a group may start a unit chain; each wave may leave a
     // reserved batch of chunks and units unused
     const int64_t chunks = (want + 63) / 64 + TW * wgs * (TRAV_CHUNK_BATCH + 2);
-    rc = sr_list_reserve(t, groups, chunks, TW * groups + chunks / UCH + TW * wgs * TRAV_UNIT_BATCH + 1);
+    rc = sr_list_reserve(t, groups, chunks, TW * groups + chunks / UCH + TW * wgs * TRAV_UNIT_BATCH + 1, st);
     if (rc) return rc;
-    if ((rc = sr_front_reserve(t, wgs * TW, fcap))) return rc;
+    if ((rc = sr_front_reserve(t, wgs * TW, fcap, st))) return rc;
     return launch_traversal(t, p, n_t, active, a_old, handle_store(t), wgs, st);
 }
 
@@ -1884,7 +1884,7 @@ int sr_walk_forward(sr_tree* t, const sr_params* p, int64_t n_t, const int32_t* 
     if (t->n_nodes == 0) {
         // a single particle: no sources, every group list is empty
         const int64_t groups = (n_t + WAVE - 1) / WAVE;
-        int rc = sr_list_reserve(t, groups, 1, 1);
+        int rc = sr_list_reserve(t, groups, 1, 1, st);
         if (rc) return rc;
         t->n_units = 0;
         t->lkey.valid = false;
