@@ -260,8 +260,9 @@ int srgrav_timing_read(double* ms, int64_t* calls);
  * srgrav_inject_alloc_failure -- test hook for the out-of-memory paths: with
  * after >= 0, the library's device allocation that follows the next `after`
  * successful ones fails as if hipMalloc had (SR_ENOMEM), once; a negative
- * value switches the injection off.  Process-wide; host-pinned buffers and
- * hipFFT's own plan memory are not covered.  Always SR_OK.
+ * value switches the injection off.  Process-wide; host-pinned buffers,
+ * hipFFT's own plan memory and sph_density's stream-ordered workspace are not
+ * covered.  Always SR_OK.
  */
 int srgrav_inject_alloc_failure(int64_t after);
 
@@ -388,9 +389,12 @@ void pm_free(sr_pm* pm);
  *   unconverged  HOST int64 (may be NULL): particles without a root below L/4
  *                (or with mass <= 0), whose h is L/4 (or the last iterate)
  *
- * The host waits for the stream once per iteration (at most 100).  The
- * workspace (about 36 bytes per particle) comes from the stream-ordered
- * allocator and is released before the call returns.
+ * Neighbours are gathered per group of 64 Morton-consecutive particles into
+ * candidate lists that are kept across iterations while the group's smoothing
+ * lengths stay within the gathered radius.  The host waits for the stream once
+ * per iteration (at most 100).  The workspace (about 36 bytes per particle plus
+ * the candidate lists, grown on demand) comes from the stream-ordered allocator
+ * and is released before the call returns; the sums are deterministic.
  */
 int sph_density(sr_tree* tree, double n_ngb, double* h, double* rho, int64_t* unconverged, void* stream);
 

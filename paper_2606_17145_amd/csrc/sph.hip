@@ -1,34 +1,48 @@
 // SPH density with an iterated smoothing length, on the tree of tree_build.
 //
 // The paper's density module iterates each particle's smoothing length until
-// its kernel sphere holds a fixed number of neighbours (Sec. 2).  With Gadget-2's
-// cubic spline of support h, W(r, h) = 8 / (pi h^3) w(r / h), the density
-// rho_i(h) = sum_j m_j W(r_ij, h) (self included, minimum image) and the
-// mass-weighted neighbour number N_i(h) = (4 pi / 3) h^3 rho_i(h) / m_i =
-// (32/3) sum_j (m_j / m_i) w(r_ij / h), h_i is the root of N_i(h) = T.  N_i is
-// strictly increasing in h once a neighbour lies inside, so the root is unique.
+// its kernel sphere holds a fixed number of neighbours (Sec. 2), gathering the
+// neighbours of a group of particles first and evaluating them after, in
+// chunks (its GPU-porting subsection).  With Gadget-2's cubic spline of support
+// h, W(r, h) = 8 / (pi h^3) w(r / h), the density rho_i(h) = sum_j m_j
+// W(r_ij, h) (self included, minimum image) and the mass-weighted neighbour
+// number N_i(h) = (4 pi / 3) h^3 rho_i(h) / m_i = (32/3) sum_j (m_j / m_i)
+// w(r_ij / h), h_i is the root of N_i(h) = T.  N_i is strictly increasing in h
+// once a neighbour lies inside, so the root is unique.
 //
-// One thread per particle in Morton order; the 64 lanes of a wave share one
-// walk of the pre-order node sequence without a stack: a node whose cube meets
-// any lane's ball |x - x_i| < h (minimum image) is entered (each lane sums the
-// direct particle children within its own h, and the walk continues at the
-// next node in pre-order, its first child node or, if it has none, the node
-// after its subtree); any other node is skipped with n_skip.  The sums give
-// N(h) and dN/dh, and a safeguarded Newton step in h^3 updates h inside the
-// bracket the iterations have found.
+// Groups are 64 Morton-consecutive particles (lane l = sorted particle 64 g +
+// l).  Three kernels per iteration:
+//   gather  (only when some h left its group's gathered radius): one wave per
+//           group walks the tree breadth-first, lane-parallel over the level's
+//           nodes, and lists every particle within R of the box of the
+//           group's active particles, R = a margin times their largest h; the
+//           candidates go to chunks of 64, UCH chunks to a unit;
+//   eval    one wave per unit: the unit's candidates are staged in LDS and
+//           every lane sums m_j w and m_j q w' over those inside its own h;
+//   update  one wave per group: the units' sums in order, then a safeguarded
+//           Newton step in h^3 inside the bracket found so far.
+// The candidates are kept across iterations while every active h stays within
+// the gathered radius (and above half of it, so that the lists do not stay far
+// larger than the balls).
 #include <math.h>
 
 #include "internal.h"
 
 namespace {
 
+constexpr int WAVE = 64;
 constexpr int SPH_TPB = 256;
 constexpr int SPH_MAX_ITER = 100;
-constexpr double SPH_OVERFULL = 4.0;        // a partial neighbour number above 4 T ends a lane's walk
 constexpr double SPH_INIT_FRACTION = 0.25;   // the initial density from the smallest ancestor with T/4 particles
 constexpr double SPH_GROW = 2.0;             // largest growth of h per step before an upper bound is known
+constexpr double SPH_MARGIN = 1.3;           // gathered radius / largest active h of the group
+constexpr int SPH_UCH = 8;                   // chunks per evaluation unit
+constexpr int SPH_GATHER_WG_PER_CU = 4;      // persistent gather waves per compute unit
 
 enum : int32_t { SPH_ACTIVE = 0, SPH_DONE = 1, SPH_FAILED = 2 };
+// list counters: chunks taken, units taken, overflow, next group, active particles,
+// regather request
+enum { SC_CHUNKS = 0, SC_UNITS = 1, SC_OVERFLOW = 2, SC_GROUP = 3, SC_ACTIVE = 4, SC_REGATHER = 5, SC_WORDS = 8 };
 
 inline dim3 sph_grid(int64_t n) { return dim3((unsigned)((n + SPH_TPB - 1) / SPH_TPB)); }
 
@@ -52,6 +66,38 @@ __device__ inline void spline_w(double q, double& wq, double& qdw)
 // division; the image can differ from d / L rounding only at an exact half-box
 // tie, where both images are equally far).
 __device__ inline double min_image(double d, double box, double inv_box) { return d - box * rint(d * inv_box); }
+
+__device__ inline double wave_max_d(double v)
+{
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) v = fmax(v, __shfl_xor(v, o, WAVE));
+    return v;
+}
+__device__ inline double wave_min_d(double v)
+{
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) v = fmin(v, __shfl_xor(v, o, WAVE));
+    return v;
+}
+
+struct SphLists {
+    uint64_t* ent;          // candidate range: first sorted particle | count (1..64) << 32; 64 per chunk
+    int32_t* chunk_next;
+    int32_t* chunk_cnt;
+    int32_t* unit_group;
+    int32_t* unit_chunk;
+    int32_t* unit_nch;
+    int32_t* unit_next;
+    int32_t* group_head;    // first unit of each group, -1 for none
+    double* rad;            // gathered radius of each group (0: no list)
+    int32_t* need;          // 1: the group needs new candidates
+    double* gbox;           // per group: centre of its active particles' box (3), and 1 if the box
+                            // spans more than half the period on some axis
+    int32_t* counters;      // SC_WORDS
+    uint32_t* front;        // per gather wave: two levels of cap_front node ids
+    double* partials;       // per unit: A[64], D[64]
+    int64_t cap_chunks, cap_units, cap_front;
+};
 
 // Initial h: from the smallest ancestor of the particle's leaf that holds at
 // least T/4 particles (a local density), the radius of a sphere with T
@@ -80,135 +126,492 @@ __global__ void k_sph_init(int64_t n, int64_t m, const int32_t* __restrict__ ppa
     state[s] = SPH_ACTIVE;
 }
 
-__global__ void k_sph_iterate(int64_t n, int64_t m, const WalkRec64* __restrict__ wrec,
-                              const int32_t* __restrict__ n_skip, const Rec64* __restrict__ prec, double box,
-                              double target, double h_max, double* __restrict__ h, double* __restrict__ lo,
-                              double* __restrict__ hi, int32_t* __restrict__ state, double* __restrict__ rho,
-                              int32_t* __restrict__ active)
+// Candidate gather, one wave per group that needs new candidates (persistent
+// waves take groups from a counter).  Node cubes (cell centre, side l; grown
+// after a drift) are tested against the box of the group's active particles
+// grown by R along each axis's minimum image: a node farther than R is pruned;
+// a node within R as a whole, a small node and a bucket of identical keys give
+// all their particles (a contiguous range of the sorted order, no record read);
+// any other node is opened, and its particle children within R are listed.
+// The candidates are thus a superset of the particles within R of the box (the
+// evaluation applies each lane's exact r < h).  The group's previous units are
+// marked empty first.
+constexpr uint32_t SPH_WHOLE = 8;    // nodes of at most this many particles are listed whole
+constexpr uint32_t SPH_PIECE = 32;   // largest candidate count of one list entry
+constexpr uint32_t SPH_CHUNK_CAND = 256;    // a chunk closes at this many candidates
+constexpr uint32_t SPH_UNIT_CAND = 1024;    // a unit closes at this many candidates
+constexpr int SPH_CHUNK_BATCH = 16;  // chunk indices a wave reserves per atomic
+constexpr int SPH_UNIT_BATCH = 2;    // unit indices a wave reserves per atomic
+
+__global__ __launch_bounds__(WAVE) void k_sph_gather(int64_t n, int64_t m, int64_t groups,
+                                                     const WalkRec64* __restrict__ wrec,
+                                                     const int32_t* __restrict__ n_first,
+                                                     const int32_t* __restrict__ n_count,
+                                                     const Rec64* __restrict__ prec, double box,
+                                                     const int32_t* __restrict__ state,
+                                                     const double* __restrict__ hs, SphLists S)
 {
-    const int64_t s = blockIdx.x * (int64_t)SPH_TPB + threadIdx.x;
+    const int lane = threadIdx.x;
+    const uint64_t below = (1ull << lane) - 1ull;
+    const double inv_box = 1.0 / box;
+    uint32_t* cur_ids = S.front + (int64_t)blockIdx.x * 2 * S.cap_front;
+    uint32_t* nxt_ids = cur_ids + S.cap_front;
+    // chunk and unit indices reserved in batches (one atomic per batch on the shared
+    // counters) and handed out in order; reserved units never used stay empty
+    int32_t c_next = 0, c_end = 0, u_next = 0, u_end = 0;
+    auto take_chunk = [&]() __attribute__((always_inline)) -> int32_t {
+        if (c_next == c_end) {
+            int32_t b = 0;
+            if (lane == 0) b = atomicAdd(&S.counters[SC_CHUNKS], SPH_CHUNK_BATCH);
+            c_next = __builtin_amdgcn_readfirstlane(b);
+            c_end = c_next + SPH_CHUNK_BATCH;
+        }
+        return c_next++;
+    };
+    auto take_unit = [&]() __attribute__((always_inline)) -> int32_t {
+        if (u_next == u_end) {
+            int32_t b = 0;
+            if (lane == 0) b = atomicAdd(&S.counters[SC_UNITS], SPH_UNIT_BATCH);
+            u_next = __builtin_amdgcn_readfirstlane(b);
+            u_end = u_next + SPH_UNIT_BATCH;
+            // a reserved unit is empty until it is filled
+            if ((uint32_t)lane < (uint32_t)SPH_UNIT_BATCH && u_next + lane < S.cap_units) S.unit_nch[u_next + lane] = 0;
+        }
+        return u_next++;
+    };
+    for (;;) {
+        int32_t gi = 0;
+        if (lane == 0) gi = atomicAdd(&S.counters[SC_GROUP], 1);
+        const int64_t g = __builtin_amdgcn_readfirstlane(gi);
+        if (g >= groups) break;
+        if (S.need[g] == 0) continue;
+        // the group's previous units hold no work from now on
+        if (lane == 0)
+            for (int32_t u = S.group_head[g]; u >= 0; u = S.unit_next[u]) S.unit_nch[u] = 0;
+        const int64_t s = g * WAVE + lane;
+        const bool act = s < n && state[s] == SPH_ACTIVE;
+        Rec64 me{0.0, 0.0, 0.0, 0.0};
+        if (act) me = prec[s];
+        const double hmax = wave_max_d(act ? hs[s] : 0.0);
+        if (!(hmax > 0.0)) {
+            if (lane == 0) {
+                S.group_head[g] = -1;
+                S.rad[g] = 0.0;
+                S.need[g] = 0;
+            }
+            continue;
+        }
+        const double R = SPH_MARGIN * hmax;
+        const double R2 = R * R * (1.0 + 1e-6);
+        // the box of the active particles: centre and half-width per axis (an axis
+        // wider than half the box passes every test)
+        double mid[3], hw[3];
+        bool wide = false;
+        const double xs[3] = {me.x, me.y, me.z};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double l = wave_min_d(act ? xs[k] : INFINITY), u = wave_max_d(act ? xs[k] : -INFINITY);
+            mid[k] = 0.5 * (l + u);
+            wide = wide || u - l > 0.5 * box;
+            hw[k] = u - l > 0.5 * box ? box : 0.5 * (u - l);
+        }
+        // squared distances from the box to the nearest and to the farthest point of
+        // the cube of half side e about c
+        auto dist2 = [&](const WalkRec64& r, double& near2, double& far2) __attribute__((always_inline)) {
+            const double c[3] = {r.cx, r.cy, r.cz}, e = 0.5 * r.l;
+            near2 = 0.0;
+            far2 = 0.0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const double a = fabs(min_image(c[k] - mid[k], box, inv_box));
+                const double t0 = fmax(a - hw[k] - e, 0.0), t1 = fmax(a - hw[k] + e, 0.0);
+                near2 += t0 * t0;
+                far2 += t1 * t1;
+            }
+        };
+
+        // ---- the group's list, chunk by chunk ----
+        bool overflow = false;
+        int32_t cc = -1, prev_chunk = -1, cur_unit = -1, prev_unit = -1, first_unit = -1;
+        uint32_t nl = 0, unit_nch = 0;
+        // chunks close at 64 entries or SPH_CHUNK_CAND candidates, units at SPH_UCH
+        // chunks or SPH_UNIT_CAND candidates, so that no unit holds much more work
+        // than another
+        uint32_t ncand = 0, ucand = 0;   // candidates in the current chunk / unit
+        auto new_chunk = [&]() __attribute__((always_inline)) -> bool {
+            const int32_t c = take_chunk();
+            if (c >= S.cap_chunks) return false;
+            if (unit_nch == 0 || unit_nch == SPH_UCH || ucand >= SPH_UNIT_CAND) {
+                const int32_t u = take_unit();
+                if (u >= S.cap_units) return false;
+                if (lane == 0) {
+                    if (cur_unit >= 0) S.unit_nch[cur_unit] = (int32_t)unit_nch;
+                    S.unit_group[u] = (int32_t)g;
+                    S.unit_chunk[u] = c;
+                    S.unit_next[u] = -1;
+                    S.unit_nch[u] = 0;
+                    if (prev_unit >= 0) S.unit_next[prev_unit] = u;
+                }
+                if (first_unit < 0) first_unit = u;
+                prev_unit = u;
+                cur_unit = u;
+                unit_nch = 0;
+                ucand = 0;
+            } else if (lane == 0) {
+                S.chunk_next[prev_chunk] = c;
+            }
+            if (lane == 0) S.chunk_next[c] = -1;
+            ++unit_nch;
+            prev_chunk = c;
+            cc = c;
+            nl = 0;
+            ncand = 0;
+            return true;
+        };
+        auto close_chunk = [&]() __attribute__((always_inline)) {
+            if (lane == 0 && cc >= 0) S.chunk_cnt[cc] = (int32_t)nl;
+        };
+        auto room = [&]() __attribute__((always_inline)) -> bool {
+            if (cc < 0 || nl == (uint32_t)WAVE || ncand >= SPH_CHUNK_CAND) {
+                close_chunk();
+                if (!new_chunk()) {
+                    overflow = true;
+                    return false;
+                }
+            }
+            return true;
+        };
+        // list the range entry p (k candidates) of every lane set in b, in lane order:
+        // each pass takes the lanes whose entry starts within the chunk's room
+        auto append = [&](uint64_t b, uint64_t p, uint32_t k) __attribute__((always_inline)) {
+            while (b && room()) {
+                const uint32_t mine = (b >> lane) & 1 ? k : 0u;
+                uint32_t incl = mine;
+#pragma unroll
+                for (int o = 1; o < WAVE; o <<= 1) {
+                    const uint32_t y = (uint32_t)__shfl_up((int)incl, o, WAVE);
+                    if (lane >= o) incl += y;
+                }
+                const uint32_t rank = (uint32_t)__popcll(b & below);
+                const bool fits = (b >> lane) & 1 && rank < (uint32_t)WAVE - nl && incl - mine < SPH_CHUNK_CAND - ncand;
+                const uint64_t take = __ballot(fits);
+                if (fits) S.ent[64 * (int64_t)cc + nl + rank] = p;
+                // the candidates taken: the prefix at the last lane taken
+                const int last = 63 - __builtin_clzll(take);
+                const uint32_t added = (uint32_t)__shfl((int)incl, last, WAVE);
+                nl += (uint32_t)__popcll(take);
+                ncand += added;
+                ucand += added;
+                b &= ~take;
+            }
+        };
+        // list the sorted particles f .. f + c - 1 of every lane with c > 0, as
+        // entries of at most SPH_PIECE particles
+        auto append_ranges = [&](uint32_t f, uint32_t c) __attribute__((always_inline)) {
+            for (;;) {
+                const uint64_t b = __ballot(c > 0);
+                if (!b || overflow) break;
+                const uint32_t k = c < SPH_PIECE ? c : SPH_PIECE;
+                append(b, (uint64_t)f | ((uint64_t)k << 32), k);
+                f += k;
+                c -= k;
+            }
+        };
+
+        if (m == 0) {
+            append_ranges(0u, lane == 0 ? 1u : 0u);   // a single particle: its own candidate
+        } else {
+            uint32_t na = 1;
+            if (lane == 0) cur_ids[0] = 0u;
+            __syncthreads();   // (one wave: orders the frontier's global stores before its loads)
+            while (na > 0 && !overflow) {
+                uint32_t nb = 0;
+                for (uint32_t b0 = 0; b0 < na && !overflow; b0 += WAVE) {
+                    const bool has = b0 + lane < na;
+                    WalkRec64 r{};
+                    uint32_t nd = 0;
+                    bool keep = false, whole = false;
+                    if (has) {
+                        nd = cur_ids[b0 + lane];
+                        r = wrec[nd];
+                        double near2, far2;
+                        dist2(r, near2, far2);
+                        keep = near2 <= R2;
+                        whole = keep && (far2 <= R2 || r.meta == META_BUCKET || (uint32_t)n_count[nd] <= SPH_WHOLE);
+                    }
+                    // nodes listed whole: their particle ranges
+                    append_ranges(whole ? (uint32_t)n_first[nd] : 0u, whole ? (uint32_t)n_count[nd] : 0u);
+                    // opened nodes: node children to the next level, particle children listed
+                    const bool open = keep && !whole;
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        const bool kid = open && (uint32_t)k < r.meta;
+                        const uint32_t ch = kid ? r.kids[k] : 0u;
+                        const bool isnode = kid && !(ch & ITEM_PARTICLE);
+                        const uint64_t bn = __ballot(isnode);
+                        if (bn) {
+                            const uint32_t cnt = (uint32_t)__popcll(bn);
+                            if (nb + cnt > S.cap_front) {
+                                overflow = true;
+                            } else {
+                                if (isnode) nxt_ids[nb + __popcll(bn & below)] = ch;
+                                nb += cnt;
+                            }
+                        }
+                        bool near = false;
+                        if (kid && (ch & ITEM_PARTICLE)) {
+                            const Rec64 p = prec[ch & ~ITEM_PARTICLE];
+                            const double xp[3] = {p.x, p.y, p.z};
+                            double d2 = 0.0;
+#pragma unroll
+                            for (int a = 0; a < 3; ++a) {
+                                const double t = fmax(fabs(min_image(xp[a] - mid[a], box, inv_box)) - hw[a], 0.0);
+                                d2 += t * t;
+                            }
+                            near = d2 <= R2;
+                        }
+                        append(__ballot(near), (uint64_t)(ch & ~ITEM_PARTICLE) | (1ull << 32), 1u);
+                    }
+                }
+                // the next level becomes the current one
+                uint32_t* t = cur_ids;
+                cur_ids = nxt_ids;
+                nxt_ids = t;
+                na = nb;
+                __syncthreads();
+            }
+        }
+        if (overflow) {
+            if (lane == 0) atomicOr(&S.counters[SC_OVERFLOW], 1);
+            break;
+        }
+        close_chunk();
+        if (lane == 0) {
+            if (cur_unit >= 0) S.unit_nch[cur_unit] = (int32_t)unit_nch;
+            S.group_head[g] = first_unit;
+            S.rad[g] = R;
+            S.need[g] = 0;
+            S.gbox[4 * g + 0] = mid[0];
+            S.gbox[4 * g + 1] = mid[1];
+            S.gbox[4 * g + 2] = mid[2];
+            S.gbox[4 * g + 3] = wide ? 1.0 : 0.0;
+        }
+    }
+}
+
+// need[g] = 1 for every group with an active particle (a full gather).
+__global__ void k_sph_need_all(int64_t n, int64_t groups, const int32_t* __restrict__ state, SphLists S)
+{
+    const int64_t g = blockIdx.x * (int64_t)(SPH_TPB / WAVE) + threadIdx.x / WAVE;
+    const int lane = threadIdx.x % WAVE;
+    if (g >= groups) return;
+    const int64_t s = g * WAVE + lane;
+    const uint64_t a = __ballot(s < n && state[s] == SPH_ACTIVE);
+    if (lane == 0) {
+        S.need[g] = a != 0;
+        S.group_head[g] = -1;   // the pool is reset: no earlier unit is referenced
+    }
+}
+
+// Sums over one unit's candidates: lane l (sorted particle 64 g + l) adds
+// m_j w(r/h) and m_j q w'(q) of every candidate within its h.
+__global__ __launch_bounds__(WAVE) void k_sph_eval(int64_t n, const Rec64* __restrict__ prec, double box,
+                                                   const int32_t* __restrict__ state,
+                                                   const double* __restrict__ hs, SphLists S)
+{
+    __shared__ Rec64 s_c[WAVE];
+    __shared__ uint32_t s_off[WAVE], s_first[WAVE];
+    const int lane = threadIdx.x;
+    const int32_t u = (int32_t)blockIdx.x;
+    if (u >= S.counters[SC_UNITS] || S.counters[SC_OVERFLOW] != 0) return;
+    const int32_t nch = S.unit_nch[u];
+    if (nch == 0) return;
+    const int64_t g = S.unit_group[u];
+    const int64_t s = g * WAVE + lane;
     const bool act = s < n && state[s] == SPH_ACTIVE;
-    if (__ballot(act) == 0) return;         // the whole wave is done
     Rec64 me{0.0, 0.0, 0.0, 0.0};
     double hh = 0.0;
     if (act) {
         me = prec[s];
-        hh = h[s];
+        hh = hs[s];
     }
-    // an inactive lane has h2 = 0: it meets no node and no particle.  A lane
-    // whose partial sum already exceeds SPH_OVERFULL T neighbours (so h lies above
-    // the root) drops out of the walk the same way.
-    double h2 = hh * hh;
-    const double inv_h = act ? 1.0 / hh : 0.0, inv_box = 1.0 / box;
-    const double a_cut = SPH_OVERFULL * target * (3.0 / 32.0) * (act ? me.m : 0.0);
-    bool overfull = false;
+    const double h2 = hh * hh, inv_h = act ? 1.0 / hh : 0.0, inv_box = 1.0 / box;
+    // positions as minimum-image offsets from the centre of the group's box: for a
+    // box narrower than half the period on every axis, the separations are the
+    // offsets' differences; otherwise their minimum image
+    const double cx = S.gbox[4 * g + 0], cy = S.gbox[4 * g + 1], cz = S.gbox[4 * g + 2];
+    const bool wide = S.gbox[4 * g + 3] != 0.0;
+    const double ox = min_image(me.x - cx, box, inv_box), oy = min_image(me.y - cy, box, inv_box),
+                 oz = min_image(me.z - cz, box, inv_box);
     double A = 0.0, D = 0.0;       // sum m_j w(q_j), sum m_j q_j w'(q_j)
-    auto pair = [&](int64_t j) {
-        const Rec64 p = prec[j];
-        const double dx = min_image(p.x - me.x, box, inv_box), dy = min_image(p.y - me.y, box, inv_box),
-                     dz = min_image(p.z - me.z, box, inv_box);
-        const double r2 = (dx * dx + dy * dy) + dz * dz;
-        if (r2 < h2) {
-            double wq, qdw;
-            spline_w(sqrt(r2) * inv_h, wq, qdw);
-            A += p.m * wq;
-            D += p.m * qdw;
-            if (A > a_cut && me.m > 0.0) {
-                overfull = true;
-                h2 = 0.0;
-            }
+    int32_t c = S.unit_chunk[u];
+    for (int32_t q = 0; q < nch; ++q) {
+        // the chunk's entries (ranges of sorted particles) and their offsets in the
+        // chunk's particle sequence
+        const int32_t ne = S.chunk_cnt[c];
+        const int32_t cnext = S.chunk_next[c];
+        uint32_t first = 0, count = 0;
+        if (lane < ne) {
+            const uint64_t v = S.ent[64 * (int64_t)c + lane];
+            first = (uint32_t)v;
+            count = (uint32_t)(v >> 32);
         }
-    };
-    if (m == 0) {
-        if (act) pair(s);
-    } else {
-        // The walk is shared by the wave: node k (the same on every lane) is
-        // entered when any lane's ball meets its cube; each lane then sums the
-        // node's particle children that lie within its own h.
-        int64_t k = 0;
-        while (k < m) {
-            const WalkRec64* r = wrec + k;
-            const int64_t skip = n_skip[k];          // loaded with the record, not after the test
-            const double half = 0.5 * r->l;
-            const double ex = fmax(fabs(min_image(me.x - r->cx, box, inv_box)) - half, 0.0);
-            const double ey = fmax(fabs(min_image(me.y - r->cy, box, inv_box)) - half, 0.0);
-            const double ez = fmax(fabs(min_image(me.z - r->cz, box, inv_box)) - half, 0.0);
-            if (__ballot((ex * ex + ey * ey) + ez * ez < h2) != 0) {
-                const uint32_t meta = r->meta;
-                if (meta == META_BUCKET) {
-                    const int64_t f = r->kids[0], c = r->kids[1];
-                    for (int64_t j = f; j < f + c; ++j) pair(j);
-                } else {
-                    for (uint32_t c = 0; c < meta; ++c) {
-                        const uint32_t kid = r->kids[c];
-                        if (kid & ITEM_PARTICLE) pair(kid & ~ITEM_PARTICLE);
-                    }
+        uint32_t incl = count;
+#pragma unroll
+        for (int o = 1; o < WAVE; o <<= 1) {
+            const uint32_t y = (uint32_t)__shfl_up((int)incl, o, WAVE);
+            if (lane >= o) incl += y;
+        }
+        s_off[lane] = incl - count;
+        s_first[lane] = first;
+        const uint32_t total = (uint32_t)__shfl((int)incl, WAVE - 1, WAVE);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (uint32_t base = 0; base < total; base += WAVE) {
+            // candidate base + lane: the last entry whose offset is at most its index
+            const uint32_t idx = base + (uint32_t)lane;
+            if (idx < total) {
+                uint32_t e = 0;
+#pragma unroll
+                for (uint32_t step = 32; step; step >>= 1)
+                    if (e + step < (uint32_t)ne && s_off[e + step] <= idx) e += step;
+                const Rec64 p = prec[s_first[e] + (idx - s_off[e])];
+                s_c[lane] = Rec64{min_image(p.x - cx, box, inv_box), min_image(p.y - cy, box, inv_box),
+                                  min_image(p.z - cz, box, inv_box), p.m};
+            }
+            const int32_t cnt = total - base < (uint32_t)WAVE ? (int32_t)(total - base) : WAVE;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            auto candidate = [&](const Rec64& p, double dx, double dy, double dz) __attribute__((always_inline)) {
+                const double r2 = (dx * dx + dy * dy) + dz * dz;
+                if (r2 < h2) {
+                    double wq, qdw;
+                    spline_w(sqrt(r2) * inv_h, wq, qdw);
+                    A += p.m * wq;
+                    D += p.m * qdw;
                 }
-                ++k;
+            };
+            if (!wide) {
+                for (int32_t e = 0; e < cnt; ++e) {
+                    const Rec64 p = s_c[e];
+                    candidate(p, p.x - ox, p.y - oy, p.z - oz);
+                }
             } else {
-                k = skip;
+                for (int32_t e = 0; e < cnt; ++e) {
+                    const Rec64 p = s_c[e];
+                    candidate(p, min_image(p.x - ox, box, inv_box), min_image(p.y - oy, box, inv_box),
+                              min_image(p.z - oz, box, inv_box));
+                }
             }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
+        c = cnext;
     }
-    if (!act) return;
-    const double mi = me.m;
-    if (overfull) {
-        // N(hh) > SPH_OVERFULL T: hh bounds the root from above; halve h, or
-        // bisect once a lower bound is known
-        const double l = lo[s];
-        hi[s] = hh;
-        h[s] = l > 0.0 ? 0.5 * (l + hh) : 0.5 * hh;
-        atomicAdd(active, 1);
-        return;
-    }
-    rho[s] = 8.0 / M_PI * inv_h * inv_h * inv_h * A;
-    if (!(mi > 0.0)) {
-        state[s] = SPH_FAILED;
-        return;
-    }
-    const double N = 32.0 / 3.0 * A / mi;
-    const double f = N - target;
-    double l = lo[s], u = hi[s];
-    if (fabs(f) <= 1e-13 * target) {
-        state[s] = SPH_DONE;
-        return;
-    }
-    if (f < 0.0)
-        l = hh;
-    else
-        u = hh;
-    if (u > 0.0 && u - l <= 4e-16 * u) {     // the bracket has closed
-        state[s] = SPH_DONE;
-        return;
-    }
-    // Newton in v = h^3, where N is close to linear: dN/dv = (dN/dh) / (3 h^2)
-    const double dN = -32.0 / 3.0 * D / (mi * hh);
-    double hn = -1.0;
-    if (dN > 0.0) {
-        const double v = hh * hh * hh - f * 3.0 * hh * hh / dN;
-        if (v > 0.0) hn = cbrt(v);
-    }
-    if (u < 0.0) {
-        if (!(hn > hh)) hn = SPH_GROW * hh;
-        hn = fmin(hn, SPH_GROW * hh);
-        if (hn > h_max) {
-            if (hh >= h_max) {              // N(h_max) < T: no root within h_max
-                state[s] = SPH_FAILED;
-                return;
-            }
-            hn = h_max;
-        }
-    } else if (!(hn > l && hn < u)) {
-        hn = 0.5 * (l + u);
-    }
-    lo[s] = l;
-    hi[s] = u;
-    h[s] = hn;
-    atomicAdd(active, 1);
+    S.partials[(int64_t)u * 2 * WAVE + lane] = A;
+    S.partials[(int64_t)u * 2 * WAVE + WAVE + lane] = D;
 }
 
-// Launched with one thread; the lane-indexed address keeps it a vector store.
-__global__ void k_sph_zero(int32_t* p) { p[threadIdx.x] = 0; }
+// One group per wave: its units' sums in unit order, then the Newton step.
+__global__ __launch_bounds__(WAVE) void k_sph_update(int64_t n, const Rec64* __restrict__ prec, double target,
+                                                     double h_max, double* __restrict__ h, double* __restrict__ lo,
+                                                     double* __restrict__ hi, int32_t* __restrict__ state,
+                                                     double* __restrict__ rho, SphLists S)
+{
+    const int lane = threadIdx.x;
+    const int64_t g = blockIdx.x;
+    if (S.counters[SC_OVERFLOW] != 0) return;   // the lists are incomplete: the iteration is repeated
+    const int64_t s = g * WAVE + lane;
+    const bool act = s < n && state[s] == SPH_ACTIVE;
+    const double R = S.rad[g];
+    double A = 0.0, D = 0.0;
+    for (int32_t u = S.group_head[g]; u >= 0; u = S.unit_next[u]) {
+        A += S.partials[(int64_t)u * 2 * WAVE + lane];
+        D += S.partials[(int64_t)u * 2 * WAVE + WAVE + lane];
+    }
+    bool still = false;
+    double hn = 0.0;
+    if (act) {
+        const double hh = h[s];
+        const double mi = prec[s].m;
+        const double inv_h = 1.0 / hh;
+        rho[s] = 8.0 / M_PI * inv_h * inv_h * inv_h * A;
+        const double N = 32.0 / 3.0 * A / mi;
+        const double f = N - target;
+        double l = lo[s], u = hi[s];
+        if (!(mi > 0.0)) {
+            state[s] = SPH_FAILED;
+        } else if (fabs(f) <= 1e-13 * target) {
+            state[s] = SPH_DONE;
+        } else {
+            if (f < 0.0)
+                l = hh;
+            else
+                u = hh;
+            if (u > 0.0 && u - l <= 4e-16 * u) {     // the bracket has closed
+                state[s] = SPH_DONE;
+            } else {
+                // Newton in v = h^3, where N is close to linear: dN/dv = (dN/dh) / (3 h^2)
+                const double dN = -32.0 / 3.0 * D / (mi * hh);
+                hn = -1.0;
+                if (dN > 0.0) {
+                    const double v = hh * hh * hh - f * 3.0 * hh * hh / dN;
+                    if (v > 0.0) hn = cbrt(v);
+                }
+                bool failed = false;
+                if (u < 0.0) {
+                    if (!(hn > hh)) hn = SPH_GROW * hh;
+                    hn = fmin(hn, SPH_GROW * hh);
+                    if (hn > h_max) {
+                        if (hh >= h_max) {              // N(h_max) < T: no root within h_max
+                            state[s] = SPH_FAILED;
+                            failed = true;
+                        } else {
+                            hn = h_max;
+                        }
+                    }
+                } else if (!(hn > l && hn < u)) {
+                    hn = 0.5 * (l + u);
+                }
+                if (!failed) {
+                    lo[s] = l;
+                    hi[s] = u;
+                    h[s] = hn;
+                    still = true;
+                }
+            }
+        }
+    }
+    // one count per wave; a regather when an active h left the gathered radius or
+    // every active h fell below half of it
+    // per group: new candidates when an active h left the gathered radius or every
+    // active h fell below half of it; a group with no active particle left drops
+    // its units.  One count per wave.
+    const uint64_t live = __ballot(still);
+    const uint64_t outside = __ballot(still && hn > R);
+    const double hmax = wave_max_d(still ? hn : 0.0);
+    if (lane == 0) {
+        if (live) {
+            atomicAdd(&S.counters[SC_ACTIVE], (int32_t)__popcll(live));
+            const bool renew = outside || hmax < 0.5 * R;
+            S.need[g] = renew ? 1 : 0;
+            if (renew) atomicOr(&S.counters[SC_REGATHER], 1);
+        } else {
+            for (int32_t u = S.group_head[g]; u >= 0; u = S.unit_next[u]) S.unit_nch[u] = 0;
+            S.group_head[g] = -1;
+            S.need[g] = 0;
+        }
+    }
+}
+
+__global__ void k_sph_clear(int32_t* p, int32_t k0, int32_t k1)
+{
+    const int k = (int)threadIdx.x;
+    if (k >= k0 && k < k1) p[k] = 0;
+}
 
 __global__ void k_sph_out(int64_t n, const int32_t* __restrict__ perm, const double* __restrict__ hs,
                           const double* __restrict__ rs, const int32_t* __restrict__ state,
@@ -222,6 +625,57 @@ __global__ void k_sph_out(int64_t n, const int32_t* __restrict__ perm, const dou
     if (state[s] != SPH_DONE) atomicAdd(failed, 1);
 }
 
+// Workspace of one call, from the stream-ordered allocator: per particle h, lo,
+// hi, rho and state; per group the list heads and radii; the lists, frontier and
+// partials sized by the capacities.
+struct SphWork {
+    double* buf = nullptr;      // 4 n doubles
+    int32_t* ibuf = nullptr;    // n + SC_WORDS + 1 ints
+    void* lists = nullptr;
+    int64_t lists_bytes = 0;
+};
+
+int lists_alloc(SphWork& W, SphLists& S, int64_t groups, int64_t waves, int64_t chunks, int64_t units,
+                int64_t front, int32_t* counters, hipStream_t st)
+{
+    if (W.lists) (void)hipFreeAsync(W.lists, st);
+    W.lists = nullptr;
+    auto up = [](int64_t b) { return (b + 255) & ~(int64_t)255; };
+    const int64_t bytes = up(64 * chunks * 8) + 2 * up(chunks * 4) + 4 * up(units * 4) + 2 * up(groups * 4) +
+                          up(groups * 8) + up(groups * 32) + up(waves * 2 * front * 4) + up(units * 2 * WAVE * 8);
+    if (hipMallocAsync(&W.lists, (size_t)bytes, st) != hipSuccess) {
+        W.lists = nullptr;
+        (void)hipGetLastError();
+        return sr_fail(SR_ENOMEM, "sph_density: %lld bytes of candidate lists could not be allocated",
+                       (long long)bytes);
+    }
+    W.lists_bytes = bytes;
+    char* p = (char*)W.lists;
+    auto take = [&](int64_t b) {
+        char* q = p;
+        p += up(b);
+        return q;
+    };
+    S.ent = (uint64_t*)take(64 * chunks * 8);
+    S.chunk_next = (int32_t*)take(chunks * 4);
+    S.chunk_cnt = (int32_t*)take(chunks * 4);
+    S.unit_group = (int32_t*)take(units * 4);
+    S.unit_chunk = (int32_t*)take(units * 4);
+    S.unit_nch = (int32_t*)take(units * 4);
+    S.unit_next = (int32_t*)take(units * 4);
+    S.group_head = (int32_t*)take(groups * 4);
+    S.rad = (double*)take(groups * 8);
+    S.need = (int32_t*)take(groups * 4);
+    S.gbox = (double*)take(groups * 32);
+    S.front = (uint32_t*)take(waves * 2 * front * 4);
+    S.partials = (double*)take(units * 2 * WAVE * 8);
+    S.counters = counters;
+    S.cap_chunks = chunks;
+    S.cap_units = units;
+    S.cap_front = front;
+    return SR_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -233,42 +687,84 @@ int sph_density(sr_tree* t, double n_ngb, double* h, double* rho, int64_t* uncon
     if (!(n_ngb > 32.0 / 3.0) || !isfinite(n_ngb))
         return sr_fail(SR_EINVAL, "sph_density: n_ngb must be finite and above 32/3 (got %g)", n_ngb);
     if (!h || !rho) return sr_fail(SR_EINVAL, "sph_density: h and rho are required");
-    int dev = 0;
+    int dev = 0, cus = 0;
     SR_HIP(hipGetDevice(&dev));
     if (dev != t->device) return sr_fail(SR_ESTATE, "sph_density: tree belongs to device %d, current is %d", t->device, dev);
+    SR_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     hipStream_t st = (hipStream_t)stream;
     const int64_t n = t->n, m = t->n_nodes;
+    const int64_t groups = (n + WAVE - 1) / WAVE;
+    const int64_t waves = groups < (int64_t)SPH_GATHER_WG_PER_CU * cus ? groups : (int64_t)SPH_GATHER_WG_PER_CU * cus;
     const double box = t->box, h_max = 0.25 * box;
-    // workspace (stream-ordered): h, lo, hi, rho in sorted order; state; two counters
-    double* buf = nullptr;
-    int32_t* ibuf = nullptr;
-    if (hipMallocAsync((void**)&buf, sizeof(double) * 4 * n, st) != hipSuccess ||
-        hipMallocAsync((void**)&ibuf, sizeof(int32_t) * (n + 2), st) != hipSuccess) {
-        if (buf) (void)hipFreeAsync(buf, st);
+    SphWork W;
+    if (hipMallocAsync((void**)&W.buf, sizeof(double) * 4 * n, st) != hipSuccess ||
+        hipMallocAsync((void**)&W.ibuf, sizeof(int32_t) * (n + SC_WORDS + 1), st) != hipSuccess) {
+        if (W.buf) (void)hipFreeAsync(W.buf, st);
+        (void)hipGetLastError();
         return sr_fail(SR_ENOMEM, "sph_density: workspace allocation for %lld particles failed", (long long)n);
     }
-    double *hs = buf, *lo = buf + n, *hi = buf + 2 * n, *rs = buf + 3 * n;
-    int32_t *state = ibuf, *active = ibuf + n, *failed = ibuf + n + 1;
-    int32_t count = 0;
-    int rc = SR_OK;
+    double *hs = W.buf, *lo = W.buf + n, *hi = W.buf + 2 * n, *rs = W.buf + 3 * n;
+    int32_t *state = W.ibuf, *ctr = W.ibuf + n, *failed = W.ibuf + n + SC_WORDS;
+    // list capacities: 32 chunks per group to start, doubled when a full gather overflows
+    int64_t chunks = 32 * groups + 1024, units = chunks / 2 + 2 * groups + 2 * waves + 64, front = 4096;
+    SphLists S{};
+    int rc = lists_alloc(W, S, groups, waves, chunks, units, front, ctr, st);
+    int32_t hc[SC_WORDS];
     hipLaunchKernelGGL(k_sph_init, sph_grid(n), dim3(SPH_TPB), 0, st, n, m, t->pparent, t->n_parent, t->n_count,
                        t->wrec64, n_ngb, box, h_max, hs, lo, hi, state);
-    for (int it = 0; it < SPH_MAX_ITER; ++it) {
-        hipLaunchKernelGGL(k_sph_zero, dim3(1), dim3(1), 0, st, active);
+    // The first gather is a full one (the pool reset, every group with an active
+    // particle); later ones renew only the groups that asked, appending to the pool,
+    // until one overflows (then a full gather; a full gather that overflows grows
+    // the pool).
+    // The host reads the counters once per iteration.  An overflowing gather sets a
+    // flag that makes the evaluation and the update of that iteration do nothing;
+    // the iteration is then repeated with a full gather, or with a grown pool if
+    // the full gather overflowed.
+    bool gather = true, full = true;
+    for (int it = 0; rc == SR_OK && it < SPH_MAX_ITER;) {
         sr_timing_mark(SR_T_SPH_ITER, true, st);
-        hipLaunchKernelGGL(k_sph_iterate, sph_grid(n), dim3(SPH_TPB), 0, st, n, m, t->wrec64, t->n_skip, t->prec64,
-                           box, n_ngb, h_max, hs, lo, hi, state, rs, active);
+        const bool gathered_full = gather && full;
+        if (gather) {
+            if (full) {
+                hipLaunchKernelGGL(k_sph_clear, dim3(1), dim3(SC_WORDS), 0, st, ctr, 0, SC_WORDS);
+                hipLaunchKernelGGL(k_sph_need_all, dim3((unsigned)((groups + SPH_TPB / WAVE - 1) / (SPH_TPB / WAVE))),
+                                   dim3(SPH_TPB), 0, st, n, groups, state, S);
+            } else {
+                hipLaunchKernelGGL(k_sph_clear, dim3(1), dim3(SC_WORDS), 0, st, ctr, SC_OVERFLOW, SC_GROUP + 1);
+            }
+            hipLaunchKernelGGL(k_sph_gather, dim3((unsigned)waves), dim3(WAVE), 0, st, n, m, groups, t->wrec64,
+                               t->n_first, t->n_count, t->prec64, box, state, hs, S);
+        }
+        hipLaunchKernelGGL(k_sph_clear, dim3(1), dim3(SC_WORDS), 0, st, ctr, SC_ACTIVE, SC_REGATHER + 1);
+        hipLaunchKernelGGL(k_sph_eval, dim3((unsigned)S.cap_units), dim3(WAVE), 0, st, n, t->prec64, box, state, hs, S);
+        hipLaunchKernelGGL(k_sph_update, dim3((unsigned)groups), dim3(WAVE), 0, st, n, t->prec64, n_ngb, h_max, hs,
+                           lo, hi, state, rs, S);
         sr_timing_mark(SR_T_SPH_ITER, false, st);
         if (hipGetLastError() != hipSuccess ||
-            hipMemcpyAsync(&count, active, sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipMemcpyAsync(hc, ctr, sizeof(hc), hipMemcpyDeviceToHost, st) != hipSuccess ||
             hipStreamSynchronize(st) != hipSuccess) {
             rc = sr_fail(SR_EHIP, "sph_density: iteration %d failed", it);
             break;
         }
-        if (count == 0) break;
+        if (hc[SC_OVERFLOW]) {
+            if (gathered_full) {
+                // the lists or a level of the walk did not fit: grow both
+                chunks *= 2;
+                units = chunks / 2 + 2 * groups + 2 * waves + 64;
+                front *= 2;
+                if ((rc = lists_alloc(W, S, groups, waves, chunks, units, front, ctr, st))) break;
+            }
+            gather = full = true;
+            continue;
+        }
+        ++it;
+        full = false;
+        if (hc[SC_ACTIVE] == 0) break;
+        gather = hc[SC_REGATHER] != 0;
     }
     if (rc == SR_OK) {
-        hipLaunchKernelGGL(k_sph_zero, dim3(1), dim3(1), 0, st, failed);
+        int32_t count = 0;
+        hipLaunchKernelGGL(k_sph_clear, dim3(1), dim3(1), 0, st, failed, 0, 1);
         hipLaunchKernelGGL(k_sph_out, sph_grid(n), dim3(SPH_TPB), 0, st, n, t->perm, hs, rs, state, h, rho, failed);
         if (hipGetLastError() != hipSuccess ||
             hipMemcpyAsync(&count, failed, sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -277,8 +773,9 @@ int sph_density(sr_tree* t, double n_ngb, double* h, double* rho, int64_t* uncon
         else if (unconverged)
             *unconverged = count;
     }
-    (void)hipFreeAsync(buf, st);
-    (void)hipFreeAsync(ibuf, st);
+    if (W.lists) (void)hipFreeAsync(W.lists, st);
+    (void)hipFreeAsync(W.buf, st);
+    (void)hipFreeAsync(W.ibuf, st);
     return rc;
 }
 
