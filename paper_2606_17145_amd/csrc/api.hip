@@ -98,8 +98,6 @@ void free_workspace(sr_tree* t)
     if (t->ev_counters) (void)hipEventDestroy(t->ev_counters);
     t->h_status = t->h_counters = nullptr;
     t->ev_status = t->ev_counters = nullptr;
-    release(t->depth_order);
-    release(t->depth_cursor);
     release(t->perm);
     release(t->invperm);
     release(t->pparent);
@@ -179,8 +177,6 @@ int allocate_workspace(sr_tree* t, int64_t cap)
         free_workspace(t);
         return sr_fail(SR_ENOMEM, "pinned host read-back buffers or their events could not be created");
     }
-    A(t->depth_order, nodes);
-    A(t->depth_cursor, SR_MAX_DEPTH);
     A(t->perm, cap);
     A(t->invperm, cap);
     A(t->pparent, cap);

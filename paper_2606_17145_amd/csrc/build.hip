@@ -477,10 +477,8 @@ __global__ void k_node_depth(const int32_t* __restrict__ m_dev, const int32_t* _
                              int32_t* __restrict__ n_depth, Item* __restrict__ items,
                              int32_t* __restrict__ status)
 {
-    // per-block depth histogram in LDS, one global atomic per non-empty bin
-    __shared__ int32_t h[SR_MAX_DEPTH];
+    // the deepest depth of the block in LDS, one global atomic per block
     __shared__ int32_t dmax;
-    if (threadIdx.x < SR_MAX_DEPTH) h[threadIdx.x] = 0;
     if (threadIdx.x == 0) dmax = 0;
     __syncthreads();
     const int64_t m = *m_dev;
@@ -491,11 +489,9 @@ __global__ void k_node_depth(const int32_t* __restrict__ m_dev, const int32_t* _
         n_depth[nd] = d;
         int32_t f = n_first[nd], c = n_count[nd];
         items[f + nd] = Item{(uint32_t)nd, (uint32_t)(f + c + base[f + c]), (uint32_t)d, 0u};
-        atomicAdd(&h[d < SR_MAX_DEPTH ? d : SR_MAX_DEPTH - 1], 1);
         atomicMax(&dmax, d);
     }
     __syncthreads();
-    if (threadIdx.x < SR_MAX_DEPTH && h[threadIdx.x]) atomicAdd(&status[ST_HIST + threadIdx.x], h[threadIdx.x]);
     if (threadIdx.x == 0) atomicMax(&status[ST_MAXDEPTH], dmax);
 }
 
@@ -520,48 +516,20 @@ __global__ void k_particle_items(int64_t n, const int32_t* __restrict__ leaf_bpa
 }
 
 // ------------------------------------------------------------------------------------
-// node moments, one depth at a time (deepest first)
+// node moments, bottom-up in one launch
 // ------------------------------------------------------------------------------------
 
-__global__ void k_depth_scatter(int64_t m, const int32_t* __restrict__ n_depth,
-                                const int32_t* __restrict__ hist, int32_t* __restrict__ cursor,
-                                int32_t* __restrict__ order)
-{
-    // ranks within the block from LDS counters; one global reservation per depth and block;
-    // depth d starts at the sum of the node counts of the depths above it
-    __shared__ int32_t cnt[SR_MAX_DEPTH], off[SR_MAX_DEPTH], base[SR_MAX_DEPTH];
-    if (threadIdx.x < SR_MAX_DEPTH) {
-        cnt[threadIdx.x] = 0;
-        int32_t b = 0;
-        for (int k = 0; k < (int)threadIdx.x; ++k) b += hist[k];
-        base[threadIdx.x] = b;
-    }
-    __syncthreads();
-    int64_t nd = blockIdx.x * (int64_t)TPB + threadIdx.x;
-    int d = -1, r = 0;
-    if (nd < m) {
-        d = n_depth[nd];
-        r = atomicAdd(&cnt[d], 1);
-    }
-    __syncthreads();
-    if (threadIdx.x < SR_MAX_DEPTH && cnt[threadIdx.x])
-        off[threadIdx.x] = atomicAdd(&cursor[threadIdx.x], cnt[threadIdx.x]);
-    __syncthreads();
-    if (d >= 0) order[base[d] + off[d] + r] = (int32_t)nd;
-}
-
-// Fold the children of every node of one depth, left to right in digit order:
-// M <- c1, M <- M + c2, ...; S likewise with a particle contributing m x;
-// COM = S / M.  Also the FP32-path node record and the FP64 decision geometry.
 // Child table of every node: its children in digit order, at most 8 (node
 // index, or sorted particle index | ITEM_PARTICLE); a level-30 bucket keeps its
-// particle range (first, count) with META_BUCKET.
-__global__ void k_child_table(int64_t m, const Item* __restrict__ items, const int32_t* __restrict__ n_first,
-                              const int32_t* __restrict__ n_level, const int32_t* __restrict__ n_count,
-                              uint32_t* __restrict__ kids, uint32_t* __restrict__ meta)
+// particle range (first, count) with META_BUCKET.  Launched for the N - 1 node
+// bound; the node count is read on the device.
+__global__ void k_child_table(const int32_t* __restrict__ m_dev, const Item* __restrict__ items,
+                              const int32_t* __restrict__ n_first, const int32_t* __restrict__ n_level,
+                              const int32_t* __restrict__ n_count, uint32_t* __restrict__ kids,
+                              uint32_t* __restrict__ meta)
 {
     const int64_t nd = blockIdx.x * (int64_t)TPB + threadIdx.x;
-    if (nd >= m) return;
+    if (nd >= *m_dev) return;
     if (n_level[nd] == 30) {
         kids[8 * nd + 0] = (uint32_t)n_first[nd];
         kids[8 * nd + 1] = (uint32_t)n_count[nd];
@@ -580,13 +548,10 @@ __global__ void k_child_table(int64_t m, const Item* __restrict__ items, const i
     meta[nd] = nk;
 }
 
-// Moments of the nodes of one depth (children done): M, S = sum m x, COM = S / M,
+// Moments of one node whose children are done: M, S = sum m x, COM = S / M,
 // folded left to right over the children in digit order without FMA, the
 // support range, the cube geometry and the FP32 record.  All children's data
 // are loaded before the fold.
-// One node per thread in blocks of one wave: a depth holds 10^3 - 10^5 nodes and
-// each thread waits on two rounds of dependent loads, so small blocks spread a
-// depth over all CUs.
 //
 // DRIFT (a tree whose particles moved after the build, topology kept): also the
 // bounding box of the node's particles, folded with min / max (exact), and the
@@ -594,102 +559,54 @@ __global__ void k_child_table(int64_t m, const Item* __restrict__ items, const i
 // about the fixed cell centre c; that maximum is attained at a box corner
 // because rounding is monotone, so the result equals the per-member maximum.
 // The opening tests then use twice the grown half side.
-constexpr int MOM_TPB = 64;
+struct MomArgs {
+    double box;
+    const int32_t *n_first, *n_level, *n_count, *n_parent;
+    const uint32_t *n_corner, *kids, *meta;
+    const Rec64* r64;
+    const double* h64;
+    Rec64* nrec64;
+    double* nS;
+    Geo64* geo;
+    double *nhmax, *nhmin;
+    Rec32* nrec32;
+    float* nhmax32;
+    WalkRec32* w32;
+    WalkRec64* w64;
+    double* nbox;
+};
+
+// A node's fold of its children: M, S = sum m x, the support range and (DRIFT)
+// the bounding box of its particles.
+struct NodeFold {
+    double M, S0, S1, S2, hx, hn;
+    double blo[3], bhi[3];
+};
+
+// Everything stored for a folded node: COM = S / M, the cube geometry (grown
+// with DRIFT), the FP32-path record and the walk's records.
 template <bool DRIFT>
-__global__ __launch_bounds__(MOM_TPB) void k_moments(const int32_t* __restrict__ order, int64_t count, double box,
-                          const int32_t* __restrict__ n_first, const int32_t* __restrict__ n_level,
-                          const uint32_t* __restrict__ n_corner, const Rec64* __restrict__ r64,
-                          const double* __restrict__ h64, Rec64* __restrict__ nrec64, double* __restrict__ nS,
-                          Geo64* __restrict__ geo, double* __restrict__ nhmax, double* __restrict__ nhmin,
-                          Rec32* __restrict__ nrec32, float* __restrict__ nhmax32,
-                          const uint32_t* __restrict__ kids, const uint32_t* __restrict__ meta,
-                          const int32_t* __restrict__ n_count, WalkRec32* __restrict__ w32,
-                          WalkRec64* __restrict__ w64, double* __restrict__ nbox)
+__device__ void node_store(const MomArgs& A, int32_t nd, const NodeFold& f)
 {
-    int64_t t = blockIdx.x * (int64_t)MOM_TPB + threadIdx.x;
-    if (t >= count) return;
-    const int32_t nd = order[t];
-    const uint32_t mt = meta[nd];
-    const uint4 ka = ((const uint4*)(kids + 8 * (int64_t)nd))[0];
-    const uint4 kb = ((const uint4*)(kids + 8 * (int64_t)nd))[1];
-    double M = 0.0, S0 = 0.0, S1 = 0.0, S2 = 0.0, hx = 0.0, hn = 0.0;
-    double blo[3] = {0.0, 0.0, 0.0}, bhi[3] = {0.0, 0.0, 0.0};   // DRIFT: member bounding box
-    auto grow = [&](bool first, const double* lo, const double* hi) {
-        for (int k = 0; k < 3; ++k) {
-            blo[k] = first || lo[k] < blo[k] ? lo[k] : blo[k];
-            bhi[k] = first || hi[k] > bhi[k] ? hi[k] : bhi[k];
-        }
-    };
-    auto fold = [&](bool first, double cm, double c0, double c1, double c2, double cx, double cn) {
-        if (first) {
-            M = cm;
-            S0 = c0;
-            S1 = c1;
-            S2 = c2;
-            hx = cx;
-            hn = cn;
-        } else {
-            M = M + cm;
-            S0 = S0 + c0;
-            S1 = S1 + c1;
-            S2 = S2 + c2;
-            hx = cx > hx ? cx : hx;
-            hn = cn < hn ? cn : hn;
-        }
-    };
-    if (mt == META_BUCKET) {
-        // identical keys: the particles first .. first + count - 1
-        const uint32_t f = (uint32_t)n_first[nd], c = (uint32_t)n_count[nd];
-        for (uint32_t k = 0; k < c; ++k) {
-            const Rec64 p = r64[f + k];
-            const double h = h64[f + k];
-            fold(k == 0, p.m, p.m * p.x, p.m * p.y, p.m * p.z, h, h);
-            if constexpr (DRIFT) {
-                const double q[3] = {p.x, p.y, p.z};
-                grow(k == 0, q, q);
-            }
-        }
-    } else {
-        const uint32_t kr[8] = {ka.x, ka.y, ka.z, ka.w, kb.x, kb.y, kb.z, kb.w};
-        double cm[8], c0[8], c1[8], c2[8], cx[8], cn[8];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            cm[k] = c0[k] = c1[k] = c2[k] = cx[k] = cn[k] = 0.0;
-            if ((uint32_t)k < mt) {
-                const uint32_t r = kr[k];
-                if (r & ITEM_PARTICLE) {
-                    const Rec64 p = r64[r & ~ITEM_PARTICLE];
-                    cm[k] = p.m;
-                    c0[k] = p.m * p.x;
-                    c1[k] = p.m * p.y;
-                    c2[k] = p.m * p.z;
-                    cx[k] = cn[k] = h64[r & ~ITEM_PARTICLE];
-                } else {
-                    cm[k] = nrec64[r].m;
-                    c0[k] = nS[3 * r + 0];
-                    c1[k] = nS[3 * r + 1];
-                    c2[k] = nS[3 * r + 2];
-                    cx[k] = nhmax[r];
-                    cn[k] = nhmin[r];
-                }
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < 8; ++k)
-            if ((uint32_t)k < mt) fold(k == 0, cm[k], c0[k], c1[k], c2[k], cx[k], cn[k]);
-        if constexpr (DRIFT) {
-            for (uint32_t k = 0; k < mt; ++k) {
-                const uint32_t r = kr[k];
-                if (r & ITEM_PARTICLE) {
-                    const Rec64 p = r64[r & ~ITEM_PARTICLE];
-                    const double q[3] = {p.x, p.y, p.z};
-                    grow(k == 0, q, q);
-                } else {
-                    grow(k == 0, nbox + 6 * (int64_t)r, nbox + 6 * (int64_t)r + 3);
-                }
-            }
-        }
-    }
+    const double box = A.box;
+    const int32_t* n_level = A.n_level;
+    const uint32_t* n_corner = A.n_corner;
+    Rec64* nrec64 = A.nrec64;
+    double* nS = A.nS;
+    Geo64* geo = A.geo;
+    double* nhmax = A.nhmax;
+    double* nhmin = A.nhmin;
+    Rec32* nrec32 = A.nrec32;
+    float* nhmax32 = A.nhmax32;
+    WalkRec32* w32 = A.w32;
+    WalkRec64* w64 = A.w64;
+    double* nbox = A.nbox;
+    const uint32_t mt = A.meta[nd];
+    const uint4 ka = ((const uint4*)(A.kids + 8 * (int64_t)nd))[0];
+    const uint4 kb = ((const uint4*)(A.kids + 8 * (int64_t)nd))[1];
+    const double M = f.M, S0 = f.S0, S1 = f.S1, S2 = f.S2, hx = f.hx, hn = f.hn;
+    const double* blo = f.blo;
+    const double* bhi = f.bhi;
     double com[3] = {S0 / M, S1 / M, S2 / M};
     nrec64[nd] = Rec64{com[0], com[1], com[2], M};
     nS[3 * nd + 0] = S0;
@@ -777,6 +694,443 @@ __global__ __launch_bounds__(MOM_TPB) void k_moments(const int32_t* __restrict__
     b.meta = mt;
     for (int k = 0; k < 8; ++k) b.kids[k] = a.kids[k];
     w64[nd] = b;
+}
+
+// A node that reaches past the end of the particle partition its first particle
+// lies in (partitions of P sorted particles).
+__device__ inline bool crosses(const MomArgs& A, int32_t nd, int64_t P)
+{
+    const int64_t f = A.n_first[nd];
+    return (f + A.n_count[nd] - 1) / P != f / P;
+}
+
+// All node moments, deepest depth first, in a few launches and without
+// device-wide waits.  Every node is folded exactly once, after all of its
+// children, with the fold above (same order, same operations), so the result
+// is that of a depth-by-depth fold.
+//
+// First pass (k_moments_leaves): block b owns the sorted particles
+// [bP1, (b+1)P1) and the nodes whose first particle lies there, the pre-order
+// run [base[bP1], base[(b+1)P1]) of at most P1 + 30 nodes (a forest of nodes
+// with two or more children each, plus the chain of nodes that reach past the
+// partition's end).  The nodes that stay inside the partition only have
+// children inside it: the block stages the partition's particles and those
+// nodes' child tables in LDS and folds the nodes one depth at a time, their sums
+// kept in LDS, a block barrier between depths, then stores them.  The nodes that
+// reach past the end contain its last particle and the next one: they are
+// ancestors of one node, at consecutive depths, at most 31, and go to the
+// block's slots of a list in depth order, which is pre-order.
+//
+// Later passes (k_moments_list), partitions growing by MP_FAN: block w takes
+// the listed nodes of its MP_FAN sub-partitions (pre-order, with their child
+// tables, in LDS), folds those that stay inside its own partition one depth at
+// a time, a block barrier between depths, and lists the others for the next
+// pass the same way.  A child of a folded node is either listed in this block
+// (its sums in LDS; `slot` maps it there) or was folded by an earlier pass
+// (global memory).  The pass whose partition holds all N particles lists
+// nothing.
+constexpr int MP_P1 = 512;                               // particles per block of the first pass
+constexpr int MP_TPB = 256;
+constexpr int MP_NODES = MP_P1 + 32;                     // nodes whose first particle is in a partition
+constexpr int MP_OWN = (MP_NODES + MP_TPB - 1) / MP_TPB;
+constexpr int MP_SLOTS = 32;                             // list slots per partition (at most 31 used)
+constexpr int MP_FAN = 32;                               // sub-partitions per partition of a later pass
+constexpr int ML_TPB = 512;
+constexpr int ML_CAND = MP_FAN * MP_SLOTS;
+
+struct MomList {
+    int32_t* nodes;    // MP_SLOTS per partition
+    int32_t* count;    // per partition
+};
+
+// One child's terms: M, S (= m x for a particle), hmax, hmin.
+struct ChildTerms {
+    double cm, c0, c1, c2, cx, cn;
+};
+
+__device__ inline void fold_child(NodeFold& f, bool first, const ChildTerms& c)
+{
+    if (first) {
+        f.M = c.cm;
+        f.S0 = c.c0;
+        f.S1 = c.c1;
+        f.S2 = c.c2;
+        f.hx = c.cx;
+        f.hn = c.cn;
+    } else {
+        f.M = f.M + c.cm;
+        f.S0 = f.S0 + c.c0;
+        f.S1 = f.S1 + c.c1;
+        f.S2 = f.S2 + c.c2;
+        f.hx = c.cx > f.hx ? c.cx : f.hx;
+        f.hn = c.cn < f.hn ? c.cn : f.hn;
+    }
+}
+
+// DRIFT: a child's member box (a particle's position for both corners).
+__device__ inline void grow_child(NodeFold& f, bool first, const double* lo, const double* hi)
+{
+    for (int e = 0; e < 3; ++e) {
+        f.blo[e] = first || lo[e] < f.blo[e] ? lo[e] : f.blo[e];
+        f.bhi[e] = first || hi[e] > f.bhi[e] ? hi[e] : f.bhi[e];
+    }
+}
+
+__device__ inline ChildTerms particle_terms(double m, double x, double y, double z, double h)
+{
+    return ChildTerms{m, m * x, m * y, m * z, h, h};
+}
+
+// Terms of child r from its raw data: a particle's m, x, y, z, h or a node's sums.
+__device__ inline ChildTerms child_terms(uint32_t r, const double* raw)
+{
+    if (r & ITEM_PARTICLE) return particle_terms(raw[0], raw[1], raw[2], raw[3], raw[4]);
+    return ChildTerms{raw[0], raw[1], raw[2], raw[3], raw[4], raw[5]};
+}
+
+// LDS sums of the nodes a block folds: M, S0, S1, S2, hmax, hmin, then with
+// DRIFT the box lo xyz, hi xyz.
+template <bool DRIFT, int CAP>
+struct NodeSums {
+    double v[DRIFT ? 12 : 6][CAP];
+    __device__ void put(int j, const NodeFold& f)
+    {
+        v[0][j] = f.M;
+        v[1][j] = f.S0;
+        v[2][j] = f.S1;
+        v[3][j] = f.S2;
+        v[4][j] = f.hx;
+        v[5][j] = f.hn;
+        if constexpr (DRIFT)
+            for (int e = 0; e < 3; ++e) {
+                v[6 + e][j] = f.blo[e];
+                v[9 + e][j] = f.bhi[e];
+            }
+    }
+    __device__ ChildTerms terms(int j) const { return ChildTerms{v[0][j], v[1][j], v[2][j], v[3][j], v[4][j], v[5][j]}; }
+    __device__ void box(int j, double* lo, double* hi) const
+    {
+        for (int e = 0; e < 3; ++e) {
+            lo[e] = v[6 + e][j];
+            hi[e] = v[9 + e][j];
+        }
+    }
+    __device__ NodeFold fold(int j) const
+    {
+        NodeFold f{v[0][j], v[1][j], v[2][j], v[3][j], v[4][j], v[5][j], {}, {}};
+        if constexpr (DRIFT) box(j, f.blo, f.bhi);
+        return f;
+    }
+};
+
+template <bool DRIFT>
+__global__ __launch_bounds__(MP_TPB) void k_moments_leaves(MomArgs A, const int32_t* __restrict__ base,
+                                                          const int32_t* __restrict__ depth, int64_t n,
+                                                          MomList out)
+{
+    __shared__ double s_p[5][MP_P1];                    // m, x, y, z, h
+    __shared__ NodeSums<DRIFT, MP_NODES> s_n;
+    __shared__ uint32_t s_meta[MP_NODES];
+    __shared__ uint4 s_kids[MP_NODES][2];
+    __shared__ int32_t s_dmin, s_dmax, s_cmin, s_out;
+    const int64_t s0 = blockIdx.x * (int64_t)MP_P1, s1 = s0 + MP_P1 < n ? s0 + MP_P1 : n;
+    const int32_t nb = base[s0], ne = base[s1];
+    if (threadIdx.x == 0) {
+        s_dmin = s_cmin = 1 << 30;
+        s_dmax = -1;
+        s_out = 0;
+    }
+    for (int64_t k = threadIdx.x; k < s1 - s0; k += MP_TPB) {
+        const Rec64 q = A.r64[s0 + k];
+        s_p[0][k] = q.m;
+        s_p[1][k] = q.x;
+        s_p[2][k] = q.y;
+        s_p[3][k] = q.z;
+        s_p[4][k] = A.h64[s0 + k];
+    }
+    __syncthreads();
+    // own nodes nb + tid + k MP_TPB: depth, or -1 when outside / reaching past the end
+    int32_t dep[MP_OWN];
+    bool cross[MP_OWN];
+    int32_t lmin = 1 << 30, lmax = -1, cmin = 1 << 30;
+#pragma unroll
+    for (int k = 0; k < MP_OWN; ++k) {
+        const int32_t i = nb + (int32_t)threadIdx.x + k * MP_TPB;
+        dep[k] = -1;
+        cross[k] = false;
+        if (i < ne) {
+            const int32_t d = depth[i];
+            if (crosses(A, i, MP_P1)) {
+                cross[k] = true;
+                dep[k] = d;
+                cmin = d < cmin ? d : cmin;
+            } else {
+                dep[k] = d;
+                lmin = d < lmin ? d : lmin;
+                lmax = d > lmax ? d : lmax;
+                const int j = i - nb;
+                s_meta[j] = A.meta[i];
+                s_kids[j][0] = ((const uint4*)(A.kids + 8 * (int64_t)i))[0];
+                s_kids[j][1] = ((const uint4*)(A.kids + 8 * (int64_t)i))[1];
+            }
+        }
+    }
+    if (lmax >= 0) {
+        atomicMin(&s_dmin, lmin);
+        atomicMax(&s_dmax, lmax);
+    }
+    if (cmin < (1 << 30)) atomicMin(&s_cmin, cmin);
+    __syncthreads();
+    const int32_t dmin = s_dmin, dmax = s_dmax, dtop = s_cmin;
+#pragma unroll
+    for (int k = 0; k < MP_OWN; ++k)
+        if (cross[k]) {
+            out.nodes[blockIdx.x * (int64_t)MP_SLOTS + dep[k] - dtop] = nb + (int32_t)threadIdx.x + k * MP_TPB;
+            atomicAdd(&s_out, 1);
+        }
+    for (int32_t d = dmax; d >= dmin; --d) {
+#pragma unroll
+        for (int k = 0; k < MP_OWN; ++k) {
+            if (cross[k] || dep[k] != d) continue;
+            const int j = (int)threadIdx.x + k * MP_TPB;
+            const uint32_t mt = s_meta[j];
+            const uint4 ka = s_kids[j][0], kb = s_kids[j][1];
+            const uint32_t kr[8] = {ka.x, ka.y, ka.z, ka.w, kb.x, kb.y, kb.z, kb.w};
+            NodeFold f{};
+            if (mt == META_BUCKET) {
+                for (uint32_t c = 0; c < kr[1]; ++c) {
+                    const int64_t q = (int64_t)(kr[0] + c) - s0;
+                    fold_child(f, c == 0, particle_terms(s_p[0][q], s_p[1][q], s_p[2][q], s_p[3][q], s_p[4][q]));
+                    if constexpr (DRIFT) {
+                        const double x[3] = {s_p[1][q], s_p[2][q], s_p[3][q]};
+                        grow_child(f, c == 0, x, x);
+                    }
+                }
+            } else {
+                // all children's data read before the fold (a particle: m, x, y, z, h;
+                // a node: its sums), the products formed in the fold
+                // (the read addresses are selected, not the data, and slots past the
+                // last child read the partition's first particle, so that no read waits
+                // for another)
+                double raw[8][6];
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    const uint32_t r = (uint32_t)c < mt ? kr[c] : (uint32_t)s0 | ITEM_PARTICLE;
+                    const bool pt = (r & ITEM_PARTICLE) != 0;
+                    const int q = pt ? (int)((int64_t)(r & ~ITEM_PARTICLE) - s0) : 0;
+                    const int j = pt ? 0 : (int)r - nb;
+#pragma unroll
+                    for (int e = 0; e < 6; ++e) raw[c][e] = *(pt ? &s_p[e < 5 ? e : 4][q] : &s_n.v[e][j]);
+                }
+#pragma unroll
+                for (int c = 0; c < 8; ++c)
+                    if ((uint32_t)c < mt) fold_child(f, c == 0, child_terms(kr[c], raw[c]));
+                if constexpr (DRIFT) {
+                    for (uint32_t c = 0; c < mt; ++c) {
+                        const uint32_t r = kr[c];
+                        double lo[3], hi[3];
+                        if (r & ITEM_PARTICLE) {
+                            const int64_t q = (int64_t)(r & ~ITEM_PARTICLE) - s0;
+                            lo[0] = hi[0] = s_p[1][q];
+                            lo[1] = hi[1] = s_p[2][q];
+                            lo[2] = hi[2] = s_p[3][q];
+                        } else {
+                            s_n.box((int)r - nb, lo, hi);
+                        }
+                        grow_child(f, c == 0, lo, hi);
+                    }
+                }
+            }
+            s_n.put(j, f);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < MP_OWN; ++k)
+        if (!cross[k] && dep[k] >= 0) {
+            const int j = (int)threadIdx.x + k * MP_TPB;
+            node_store<DRIFT>(A, nb + j, s_n.fold(j));
+        }
+    if (threadIdx.x == 0) out.count[blockIdx.x] = s_out;
+}
+
+template <bool DRIFT>
+__global__ __launch_bounds__(ML_TPB) void k_moments_list(MomArgs A, const int32_t* __restrict__ depth,
+                                                        int32_t* __restrict__ slot, int64_t P, int64_t n_sub,
+                                                        MomList in, MomList out)
+{
+    __shared__ NodeSums<DRIFT, ML_CAND> s_n;
+    __shared__ int32_t s_nd[ML_CAND], s_dp[ML_CAND];
+    __shared__ uint32_t s_meta[ML_CAND];
+    __shared__ uint4 s_kids[ML_CAND][2];
+    __shared__ int32_t s_off[MP_FAN + 1];
+    __shared__ int32_t s_dmin, s_dmax, s_cmin, s_out;
+    if (threadIdx.x == 0) {
+        // candidate offsets: the sub-partitions' lists concatenated (pre-order)
+        int32_t o = 0;
+        for (int q = 0; q < MP_FAN; ++q) {
+            s_off[q] = o;
+            const int64_t sub = blockIdx.x * (int64_t)MP_FAN + q;
+            o += sub < n_sub ? in.count[sub] : 0;
+        }
+        s_off[MP_FAN] = o;
+        s_dmin = s_cmin = 1 << 30;
+        s_dmax = -1;
+        s_out = 0;
+    }
+    __syncthreads();
+    const int32_t cnt = s_off[MP_FAN];
+    int32_t lmin = 1 << 30, lmax = -1, cmin = 1 << 30;
+    for (int t = threadIdx.x; t < ML_CAND; t += ML_TPB) {
+        const int q = t / MP_SLOTS, j = t % MP_SLOTS;
+        if (j >= s_off[q + 1] - s_off[q]) continue;
+        const int64_t sub = blockIdx.x * (int64_t)MP_FAN + q;
+        const int k = s_off[q] + j;
+        const int32_t nd = in.nodes[sub * MP_SLOTS + j];
+        const int32_t d = depth[nd];
+        s_nd[k] = nd;
+        if (crosses(A, nd, P)) {
+            s_dp[k] = -1 - d;   // listed for the next pass
+            cmin = d < cmin ? d : cmin;
+        } else {
+            s_dp[k] = d;
+            lmin = d < lmin ? d : lmin;
+            lmax = d > lmax ? d : lmax;
+            slot[nd] = k;
+            s_meta[k] = A.meta[nd];
+            s_kids[k][0] = ((const uint4*)(A.kids + 8 * (int64_t)nd))[0];
+            s_kids[k][1] = ((const uint4*)(A.kids + 8 * (int64_t)nd))[1];
+        }
+    }
+    if (lmax >= 0) {
+        atomicMin(&s_dmin, lmin);
+        atomicMax(&s_dmax, lmax);
+    }
+    if (cmin < (1 << 30)) atomicMin(&s_cmin, cmin);
+    __syncthreads();
+    const int32_t dmin = s_dmin, dmax = s_dmax, dtop = s_cmin;
+    for (int k = threadIdx.x; k < cnt; k += ML_TPB)
+        if (s_dp[k] < 0) {
+            out.nodes[blockIdx.x * (int64_t)MP_SLOTS + (-1 - s_dp[k]) - dtop] = s_nd[k];
+            atomicAdd(&s_out, 1);
+        }
+    for (int32_t d = dmax; d >= dmin; --d) {
+        for (int k = threadIdx.x; k < cnt; k += ML_TPB) {
+            if (s_dp[k] != d) continue;
+            const uint32_t mt = s_meta[k];
+            const uint4 ka = s_kids[k][0], kb = s_kids[k][1];
+            const uint32_t kr[8] = {ka.x, ka.y, ka.z, ka.w, kb.x, kb.y, kb.z, kb.w};
+            // a node child listed in this block (its slot points back at it) is read
+            // from LDS, one folded by an earlier pass from global memory
+            auto here = [&](uint32_t r, int32_t j) { return j >= 0 && j < cnt && s_nd[j] == (int32_t)r; };
+            NodeFold f{};
+            if (mt == META_BUCKET) {
+                for (uint32_t c = 0; c < kr[1]; ++c) {
+                    const Rec64 p = A.r64[kr[0] + c];
+                    fold_child(f, c == 0, particle_terms(p.m, p.x, p.y, p.z, A.h64[kr[0] + c]));
+                    if constexpr (DRIFT) {
+                        const double x[3] = {p.x, p.y, p.z};
+                        grow_child(f, c == 0, x, x);
+                    }
+                }
+            } else {
+                // all children's data loaded before the fold (a particle: m, x, y, z, h;
+                // a node: its sums), the products formed in the fold
+                // (the load addresses are selected, not the data, so that no load
+                // waits for another; a particle's slot entry is not used)
+                double raw[8][6];
+                int32_t js[8];
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    // slots past the last child load particle 0 (always there)
+                    const uint32_t r = (uint32_t)c < mt ? kr[c] : ITEM_PARTICLE;
+                    const bool pt = (r & ITEM_PARTICLE) != 0;
+                    const uint32_t q = pt ? r & ~ITEM_PARTICLE : 0u, nd = pt ? 0u : r;
+                    const Rec64* pr = A.r64 + q;
+                    const double* src[6] = {pt ? &pr->m : &A.nrec64[nd].m, pt ? &pr->x : A.nS + 3 * nd,
+                                            pt ? &pr->y : A.nS + 3 * nd + 1, pt ? &pr->z : A.nS + 3 * nd + 2,
+                                            pt ? A.h64 + q : A.nhmax + nd, pt ? A.h64 + q : A.nhmin + nd};
+#pragma unroll
+                    for (int e = 0; e < 6; ++e) raw[c][e] = *src[e];
+                    js[c] = slot[nd];
+                }
+#pragma unroll
+                for (int c = 0; c < 8; ++c)
+                    if ((uint32_t)c < mt && !(kr[c] & ITEM_PARTICLE) && here(kr[c], js[c]))
+                        for (int e = 0; e < 6; ++e) raw[c][e] = s_n.v[e][js[c]];
+#pragma unroll
+                for (int c = 0; c < 8; ++c)
+                    if ((uint32_t)c < mt) fold_child(f, c == 0, child_terms(kr[c], raw[c]));
+                if constexpr (DRIFT) {
+                    for (uint32_t c = 0; c < mt; ++c) {
+                        const uint32_t r = kr[c];
+                        double lo[3], hi[3];
+                        if (r & ITEM_PARTICLE) {
+                            const Rec64 p = A.r64[r & ~ITEM_PARTICLE];
+                            lo[0] = hi[0] = p.x;
+                            lo[1] = hi[1] = p.y;
+                            lo[2] = hi[2] = p.z;
+                        } else if (here(r, js[c])) {
+                            s_n.box(js[c], lo, hi);
+                        } else {
+                            for (int e = 0; e < 3; ++e) {
+                                lo[e] = A.nbox[6 * (int64_t)r + e];
+                                hi[e] = A.nbox[6 * (int64_t)r + 3 + e];
+                            }
+                        }
+                        grow_child(f, c == 0, lo, hi);
+                    }
+                }
+            }
+            s_n.put(k, f);
+        }
+        __syncthreads();
+    }
+    for (int k = threadIdx.x; k < cnt; k += ML_TPB)
+        if (s_dp[k] >= 0) node_store<DRIFT>(A, s_nd[k], s_n.fold(k));
+    if (threadIdx.x == 0 && out.count) out.count[blockIdx.x] = s_out;
+}
+
+MomArgs mom_args(const sr_tree* t, double* nbox)
+{
+    return MomArgs{t->box, t->n_first, t->n_level, t->n_count, t->n_parent, t->n_corner, t->n_kids, t->n_meta,
+                   t->prec64, t->ph64, t->nrec64, t->nS, t->ngeo64, t->nhmax, t->nhmin, t->nrec32, t->nhmax32,
+                   t->wrec32, t->wrec64, nbox};
+}
+
+// The moment passes of a tree of n particles.  The lists live in two build
+// scratch arrays of cap >= n words: partition slots in `ucount`, counts in
+// `levelmask`, one region per pass (for n > MP_P1 fewer than n / 15 + 192 and
+// n / 500 + 6 words for all passes together); the later passes' LDS slots of
+// the listed nodes go to a third (`b_lambda`, one word per node), which the
+// topology pass no longer needs.
+template <bool DRIFT>
+int launch_moments_t(const sr_tree* t, int64_t n, double* nbox, hipStream_t st)
+{
+    const MomArgs A = mom_args(t, nbox);
+    int32_t* lists = (int32_t*)t->ucount;
+    int32_t* counts = (int32_t*)t->levelmask;
+    int64_t P = MP_P1, parts = cdiv(n, P);
+    MomList in{lists, counts};
+    hipLaunchKernelGGL(k_moments_leaves<DRIFT>, dim3((unsigned)parts), dim3(MP_TPB), 0, st, A, t->base, t->n_depth,
+                       n, in);
+    while (P < n) {
+        const int64_t Pn = P * MP_FAN, pn = cdiv(n, Pn);
+        MomList out{nullptr, nullptr};
+        if (Pn < n) out = MomList{in.nodes + parts * MP_SLOTS, in.count + parts};
+        hipLaunchKernelGGL(k_moments_list<DRIFT>, dim3((unsigned)pn), dim3(ML_TPB), 0, st, A, t->n_depth,
+                           t->b_lambda, Pn, parts, in, out);
+        in = out;
+        P = Pn;
+        parts = pn;
+    }
+    SR_HIP(hipGetLastError());
+    return SR_OK;
+}
+
+int launch_moments(const sr_tree* t, int64_t n, double* nbox, bool drift, hipStream_t st)
+{
+    return drift ? launch_moments_t<true>(t, n, nbox, st) : launch_moments_t<false>(t, n, nbox, st);
 }
 
 __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v)
@@ -908,12 +1262,21 @@ int sr_build_device(sr_tree* t, const double* pos, const double* mass, const dou
         hipLaunchKernelGGL(k_node_depth, grid_for(n - 1), dim3(TPB), 0, st, t->status + ST_NODES, t->n_parent,
                            t->n_first, t->n_count, t->base, t->n_depth, t->items, t->status);
     }
-    // the build's one synchronisation: input flags, node count and depth histogram go
-    // to pinned host memory, and the host waits for that copy while the particle pass runs
-    SR_HIP(hipMemcpyAsync(t->h_status, t->status, ST_WORDS * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    SR_HIP(hipEventRecord(t->ev_status, st));
     hipLaunchKernelGGL(k_particle_items, grid_for(n), dim3(TPB), 0, st, n, t->leaf_bparent, t->b_parent,
                        t->b_pre, t->base, t->n_depth, t->pparent, t->items);
+    if (n > 1) {
+        // child tables (for the N - 1 node bound, the node count read on the
+        // device), then every node's moments, deepest first, in two launches
+        hipLaunchKernelGGL(k_child_table, grid_for(n - 1), dim3(TPB), 0, st, t->status + ST_NODES, t->items,
+                           t->n_first, t->n_level, t->n_count, t->n_kids, t->n_meta);
+        int rc = launch_moments(t, n, nullptr, false, st);
+        if (rc) return rc;
+    }
+    // the build's one synchronisation, at its end: input flags, node count and the
+    // deepest depth go to pinned host memory
+    SR_HIP(hipMemcpyAsync(t->h_status, t->status, ST_WORDS * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    SR_HIP(hipEventRecord(t->ev_status, st));
+    SR_HIP(hipGetLastError());
     SR_HIP(hipEventSynchronize(t->ev_status));
     const int32_t* hstat = t->h_status;
     if (hstat[ST_FLAGS] & 1) return sr_fail(SR_EINVAL, "tree_build: non-finite position or non-positive / non-finite mass or softening");
@@ -928,29 +1291,6 @@ int sr_build_device(sr_tree* t, const double* pos, const double* mass, const dou
     }
     t->max_depth = hstat[ST_MAXDEPTH];
     if (t->max_depth >= SR_MAX_DEPTH) return sr_fail(SR_EUNSUPPORTED, "tree_build: tree deeper than %d", SR_MAX_DEPTH);
-    int32_t offs[SR_MAX_DEPTH];
-    int32_t acc = 0;
-    for (int d = 0; d < SR_MAX_DEPTH; ++d) {
-        t->depth_hist[d] = hstat[ST_HIST + d];
-        offs[d] = acc;
-        acc += hstat[ST_HIST + d];
-    }
-    hipLaunchKernelGGL(k_fill_i32, grid_for(SR_MAX_DEPTH), dim3(TPB), 0, st, t->depth_cursor,
-                       (int64_t)SR_MAX_DEPTH, 0);
-    hipLaunchKernelGGL(k_depth_scatter, grid_for(m), dim3(TPB), 0, st, m, t->n_depth, t->status + ST_HIST,
-                       t->depth_cursor, t->depth_order);
-    hipLaunchKernelGGL(k_child_table, grid_for(m), dim3(TPB), 0, st, m, t->items, t->n_first, t->n_level,
-                       t->n_count, t->n_kids, t->n_meta);
-    for (int d = t->max_depth; d >= 0; --d) {
-        int64_t cnt = t->depth_hist[d];
-        if (!cnt) continue;
-        hipLaunchKernelGGL(k_moments<false>, dim3((unsigned)cdiv(cnt, MOM_TPB)), dim3(MOM_TPB), 0, st, t->depth_order + offs[d], cnt, box,
-                           t->n_first, t->n_level, t->n_corner, t->prec64, t->ph64, t->nrec64, t->nS, t->ngeo64,
-                           t->nhmax, t->nhmin, t->nrec32, t->nhmax32, t->n_kids, t->n_meta, t->n_count,
-                           t->wrec32, t->wrec64, (double*)nullptr);
-    }
-    for (int d = 0; d < SR_MAX_DEPTH; ++d) t->depth_offs[d] = offs[d];
-    SR_HIP(hipGetLastError());
     return SR_OK;
 }
 
@@ -993,13 +1333,9 @@ int sr_drift_device(sr_tree* t, const double* disp, hipStream_t st)
                        t->prec64, t->prec32, t->status);
     SR_HIP(hipMemcpyAsync(t->h_status, t->status, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     SR_HIP(hipEventRecord(t->ev_status, st));
-    for (int d = t->max_depth; m > 0 && d >= 0; --d) {
-        int64_t cnt = t->depth_hist[d];
-        if (!cnt) continue;
-        hipLaunchKernelGGL(k_moments<true>, dim3((unsigned)cdiv(cnt, MOM_TPB)), dim3(MOM_TPB), 0, st,
-                           t->depth_order + t->depth_offs[d], cnt, t->box, t->n_first, t->n_level, t->n_corner,
-                           t->prec64, t->ph64, t->nrec64, t->nS, t->ngeo64, t->nhmax, t->nhmin, t->nrec32,
-                           t->nhmax32, t->n_kids, t->n_meta, t->n_count, t->wrec32, t->wrec64, t->nbox);
+    if (m > 0) {
+        int rc = launch_moments(t, n, t->nbox, true, st);
+        if (rc) return rc;
     }
     SR_HIP(hipGetLastError());
     SR_HIP(hipEventSynchronize(t->ev_status));

@@ -70,8 +70,7 @@ enum {
     ST_FLAGS = 0,      // bit 0: non-finite / non-positive input
     ST_NODES = 1,      // number of internal nodes
     ST_MAXDEPTH = 2,   // deepest node depth
-    ST_HIST = 3,       // [SR_MAX_DEPTH] nodes per depth
-    ST_WORDS = ST_HIST + SR_MAX_DEPTH
+    ST_WORDS = 3
 };
 
 // What a traversal's lists were made for.  `token` names them: shortrange_accel
@@ -111,8 +110,6 @@ struct sr_tree {
     int32_t* h_status = nullptr;      // ST_WORDS
     int32_t* h_counters = nullptr;    // 8
     hipEvent_t ev_status = nullptr, ev_counters = nullptr;
-    int32_t* depth_order = nullptr;   // node indices grouped by depth
-    int32_t* depth_cursor = nullptr;  // SR_MAX_DEPTH
 
     // tree (particles: cap, nodes: cap - 1, items: 2 cap)
     int32_t *perm = nullptr, *invperm = nullptr, *pparent = nullptr;
@@ -170,8 +167,6 @@ struct sr_tree {
     int64_t n_nodes = 0;
     bool mixed_soft = false;      // softening lengths differ between particles
     int max_depth = 0;
-    int depth_hist[SR_MAX_DEPTH] = {};
-    int32_t depth_offs[SR_MAX_DEPTH] = {};   // start of each depth in depth_order
 };
 
 // error helpers shared by the host files
