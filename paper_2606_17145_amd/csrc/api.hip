@@ -81,6 +81,7 @@ void free_workspace(sr_tree* t)
         release(t->kidx[k]);
     }
     release(t->hist);
+    release(t->rs_status);
     release(t->scan_tmp);
     release(t->levelmask);
     release(t->ucount);
@@ -169,7 +170,14 @@ int allocate_workspace(sr_tree* t, int64_t cap)
     A(t->b_parent, nodes);
     A(t->b_pre, nodes);
     A(t->leaf_bparent, cap);
-    A(t->status, ST_WORDS);
+    A(t->status, ST_ALLOC);
+    A(t->rs_status, sr_tree_sort_status_words(cap));
+    // the look-back words start untagged (tag 0 is never used)
+    if (hipMemset(t->rs_status, 0, sizeof(uint64_t) * sr_tree_sort_status_words(cap)) != hipSuccess) {
+        free_workspace(t);
+        return sr_fail(SR_EHIP, "hipMemset of the sort's look-back words failed");
+    }
+    t->rs_epoch = 0;
     if (hipHostMalloc((void**)&t->h_status, ST_WORDS * sizeof(int32_t), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&t->h_counters, 8 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess ||
         hipEventCreateWithFlags(&t->ev_status, hipEventDisableTiming) != hipSuccess ||

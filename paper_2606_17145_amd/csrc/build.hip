@@ -329,6 +329,187 @@ __global__ void k_rs_scatter(const uint64_t* __restrict__ hi, const uint64_t* __
 }
 
 // ------------------------------------------------------------------------------------
+// single-pass radix sort of the tree keys (decoupled look-back)
+// ------------------------------------------------------------------------------------
+//
+// One launch histograms all 12 digits; then one launch per 8-bit digit, LSD
+// order.  A pass's workgroups take tiles of OS_TILE consecutive keys in ticket
+// order (a device counter) and rank their keys in the tile (stable: wave w holds
+// a contiguous run, rounds in order, lanes in order, per-wave digit counters in
+// LDS).  Per digit, a tile publishes its count, then, once the counts of all
+// earlier tiles are known, its inclusive prefix; it learns its own prefix by
+// reading back over the earlier tiles' words, OS_WIN at a time, adding counts
+// until it meets an inclusive prefix.  A tile only waits for tiles with smaller
+// tickets, which are already running and publish their counts before they wait
+// themselves, so every wait ends; a wait that sees no progress for OS_SPIN_MAX
+// rounds gives up and flags the build as failed.  The words are 64-bit: the
+// pass's tag and state (count or inclusive prefix) in the high half, the value
+// in the low half; the tag changes every pass, so the words need no clearing
+// between sorts.  The tile is then reordered by digit in LDS and written out
+// with consecutive threads on consecutive output positions.
+constexpr int OS_TPB = 1024;
+constexpr int OS_ITEMS = 4;
+constexpr int OS_WAVES = OS_TPB / 64;
+constexpr int OS_TILE = OS_TPB * OS_ITEMS;
+constexpr int OS_WIN = 16;
+constexpr uint32_t OS_AGG = 1u, OS_INC = 2u;
+constexpr int64_t OS_SPIN_MAX = int64_t(1) << 20;
+
+__global__ __launch_bounds__(TPB) void k_os_hist(const uint64_t* __restrict__ hi, const uint64_t* __restrict__ lo,
+                                                 int64_t n, uint32_t* __restrict__ hist)
+{
+    __shared__ uint32_t h[12 * 256];
+    for (int i = threadIdx.x; i < 12 * 256; i += TPB) h[i] = 0;
+    __syncthreads();
+    for (int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB) {
+        const uint64_t H = hi[i], L = lo[i];
+#pragma unroll
+        for (int p = 0; p < 12; ++p) atomicAdd(&h[p * 256 + rs_digit<true>(H, L, p)], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 12 * 256; i += TPB)
+        if (h[i]) atomicAdd(&hist[i], h[i]);
+}
+
+// Exclusive scan over the 256 digits held by threads 0 .. 255 (the others pass
+// 0 and get garbage); every thread of the block must call it.
+__device__ inline uint32_t digit_exclusive_scan(uint32_t v, uint32_t* s_w)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint32_t inc = wave_inclusive_scan(v);
+    if (w < 4 && lane == 63) s_w[w] = inc;
+    __syncthreads();
+    uint32_t off = 0;
+    for (int k = 0; k < 4; ++k)
+        if (k < w) off += s_w[k];
+    __syncthreads();
+    return off + inc - v;
+}
+
+__global__ __launch_bounds__(OS_TPB) void k_os_pass(const uint64_t* __restrict__ hi, const uint64_t* __restrict__ lo,
+                                                    const uint32_t* __restrict__ idx, uint64_t* __restrict__ ohi,
+                                                    uint64_t* __restrict__ olo, uint32_t* __restrict__ oidx,
+                                                    int64_t n, int pass, const uint32_t* __restrict__ hist,
+                                                    uint32_t* __restrict__ ticket, uint64_t* __restrict__ look,
+                                                    uint32_t tag, int32_t* __restrict__ flags)
+{
+    __shared__ uint32_t s_cnt[OS_WAVES][256];   // per wave: digit counts, then offsets in the tile
+    __shared__ uint32_t s_base[256];             // output position of the tile's first key of each digit
+    __shared__ uint32_t s_start[256];            // tile position of the first key of each digit
+    __shared__ uint32_t s_w[4];
+    __shared__ uint64_t s_hi[OS_TILE], s_lo[OS_TILE];
+    __shared__ uint32_t s_ix[OS_TILE];
+    __shared__ int64_t s_tile;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, d = threadIdx.x;
+    if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
+    for (int k = lane; k < 256; k += 64) s_cnt[w][k] = 0;
+    // keys with a smaller digit (threads 0 .. 255)
+    const uint32_t dbase = digit_exclusive_scan(d < 256 ? hist[d] : 0u, s_w);
+    const int64_t tile = s_tile;
+    const int64_t e0 = tile * OS_TILE + (int64_t)w * 64 * OS_ITEMS;
+    const uint64_t lt = (1ull << lane) - 1ull;
+    uint64_t H[OS_ITEMS], L[OS_ITEMS];
+    uint32_t V[OS_ITEMS], R[OS_ITEMS], D[OS_ITEMS];
+#pragma unroll
+    for (int r = 0; r < OS_ITEMS; ++r) {
+        const int64_t i = e0 + r * 64 + lane;
+        const bool valid = i < n;
+        H[r] = valid ? hi[i] : 0;
+        L[r] = valid ? lo[i] : 0;
+        V[r] = valid ? idx[i] : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < OS_ITEMS; ++r) {
+        const bool valid = e0 + r * 64 + lane < n;
+        const uint32_t dg = rs_digit<true>(H[r], L[r], pass);
+        D[r] = dg;
+        uint64_t peers = __ballot(valid);
+        for (int b = 0; b < 8; ++b) {
+            const uint64_t bits = __ballot(valid && ((dg >> b) & 1u));
+            peers &= ((dg >> b) & 1u) ? bits : ~bits;
+        }
+        const uint32_t rank = (uint32_t)__popcll(peers & lt);
+        uint32_t before = 0;
+        if (valid) before = s_cnt[w][dg];
+        R[r] = before + rank;
+        // the lowest lane of each digit group moves the wave's counter on; the
+        // wave's LDS accesses happen in program order
+        if (valid && rank == 0) s_cnt[w][dg] = before + (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    // per digit: the tile's count and each wave's offset among the digit's keys
+    uint32_t cnt = 0;
+    if (d < 256) {
+        for (int k = 0; k < OS_WAVES; ++k) {
+            const uint32_t c = s_cnt[k][d];
+            s_cnt[k][d] = cnt;
+            cnt += c;
+        }
+    }
+    const uint32_t start = digit_exclusive_scan(d < 256 ? cnt : 0u, s_w);
+    if (d < 256) {
+        s_start[d] = start;
+        uint64_t* word = look + tile * 256 + d;
+        const uint64_t hi_agg = (uint64_t)(4u * tag + OS_AGG) << 32, hi_inc = (uint64_t)(4u * tag + OS_INC) << 32;
+        uint32_t prefix = 0;
+        if (tile == 0) {
+            __hip_atomic_store(word, hi_inc | cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            __hip_atomic_store(word, hi_agg | cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            int64_t j = tile - 1, idle = 0;
+            for (;;) {
+                uint64_t v[OS_WIN];
+#pragma unroll
+                for (int k = 0; k < OS_WIN; ++k)
+                    v[k] = j - k >= 0 ? __hip_atomic_load(look + (j - k) * 256 + d, __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT)
+                                      : hi_inc;
+                int k = 0;
+                bool done = false;
+                for (; k < OS_WIN; ++k) {
+                    const uint32_t h = (uint32_t)(v[k] >> 32);
+                    if ((h >> 2) != tag) break;   // not published yet
+                    prefix += (uint32_t)v[k];
+                    if ((h & 3u) == OS_INC) {
+                        done = true;
+                        break;
+                    }
+                }
+                if (done) break;
+                j -= k;
+                if (k == 0 && ++idle > OS_SPIN_MAX) {
+                    atomicOr(flags, 4);
+                    break;
+                }
+            }
+            __hip_atomic_store(word, hi_inc | (prefix + cnt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        s_base[d] = dbase + prefix;
+    }
+    __syncthreads();
+    // the tile in digit order in LDS
+#pragma unroll
+    for (int r = 0; r < OS_ITEMS; ++r) {
+        if (e0 + r * 64 + lane >= n) continue;
+        const uint32_t q = s_start[D[r]] + s_cnt[w][D[r]] + R[r];
+        s_hi[q] = H[r];
+        s_lo[q] = L[r];
+        s_ix[q] = V[r];
+    }
+    __syncthreads();
+    const int64_t rem = n - tile * OS_TILE;
+    const int m = rem < OS_TILE ? (int)rem : OS_TILE;
+    for (int q = threadIdx.x; q < m; q += OS_TPB) {
+        const uint64_t Hq = s_hi[q], Lq = s_lo[q];
+        const uint32_t dg = rs_digit<true>(Hq, Lq, pass);
+        const uint32_t p = s_base[dg] + (uint32_t)q - s_start[dg];
+        ohi[p] = Hq;
+        olo[p] = Lq;
+        oidx[p] = s_ix[q];
+    }
+}
+
+// ------------------------------------------------------------------------------------
 // sorted records
 // ------------------------------------------------------------------------------------
 
@@ -1182,6 +1363,11 @@ int sort_items(int64_t n) { return n <= 384 * 1024 ? 2 : n <= 1536 * 1024 ? 4 : 
 
 }  // namespace
 
+int64_t sr_tree_sort_status_words(int64_t cap)
+{
+    return 256 * cdiv(cap > 0 ? cap : 1, (int64_t)OS_TILE);
+}
+
 int64_t sr_sort_hist_words(int64_t n)
 {
     return 256 * cdiv(n > 0 ? n : 1, (int64_t)TPB * sort_items(n)) + 256 + 1;
@@ -1211,33 +1397,30 @@ int sr_build_device(sr_tree* t, const double* pos, const double* mass, const dou
     const int64_t n = t->n;
     const double box = t->box;
     t->drift_base = false;   // a drift after this build starts from its records
-    hipLaunchKernelGGL(k_fill_i32, grid_for(ST_WORDS), dim3(TPB), 0, st, t->status, (int64_t)ST_WORDS, 0);
+    hipLaunchKernelGGL(k_fill_i32, grid_for(ST_ALLOC), dim3(TPB), 0, st, t->status, (int64_t)ST_ALLOC, 0);
     hipLaunchKernelGGL(k_keys, grid_for(n), dim3(TPB), 0, st, pos, mass, eps, eps_scalar, n, box,
                        t->khi[0], t->klo[0], t->kidx[0], t->status);
     // 12 passes of 8 bits: lo word bits 0..47, then hi word bits 0..47
-    const int items = n <= 384 * 1024 ? 2 : n <= 1536 * 1024 ? 4 : 8;
-    const int64_t nb = cdiv(n, (int64_t)TPB * items);
-    int cur = 0;
-    for (int pass = 0; pass < 12; ++pass) {
-        const dim3 gb((unsigned)nb), tb(TPB);
-        if (items == 2)
-            hipLaunchKernelGGL((k_rs_hist<2, true>), gb, tb, 0, st, t->khi[cur], t->klo[cur], n, pass, t->hist, nb);
-        else if (items == 4)
-            hipLaunchKernelGGL((k_rs_hist<4, true>), gb, tb, 0, st, t->khi[cur], t->klo[cur], n, pass, t->hist, nb);
-        else
-            hipLaunchKernelGGL((k_rs_hist<8, true>), gb, tb, 0, st, t->khi[cur], t->klo[cur], n, pass, t->hist, nb);
-        uint32_t* tot = t->hist + 256 * nb;
-        hipLaunchKernelGGL(k_rs_digit_scan, dim3(256), tb, 0, st, t->hist, nb, tot);
-        if (items == 2)
-            hipLaunchKernelGGL((k_rs_scatter<2, true>), gb, tb, 0, st, t->khi[cur], t->klo[cur], t->kidx[cur],
-                               t->khi[cur ^ 1], t->klo[cur ^ 1], t->kidx[cur ^ 1], n, pass, t->hist, nb, tot);
-        else if (items == 4)
-            hipLaunchKernelGGL((k_rs_scatter<4, true>), gb, tb, 0, st, t->khi[cur], t->klo[cur], t->kidx[cur],
-                               t->khi[cur ^ 1], t->klo[cur ^ 1], t->kidx[cur ^ 1], n, pass, t->hist, nb, tot);
-        else
-            hipLaunchKernelGGL((k_rs_scatter<8, true>), gb, tb, 0, st, t->khi[cur], t->klo[cur], t->kidx[cur],
-                               t->khi[cur ^ 1], t->klo[cur ^ 1], t->kidx[cur ^ 1], n, pass, t->hist, nb, tot);
-        cur ^= 1;
+    {
+        const int64_t tiles = cdiv(n, (int64_t)OS_TILE);
+        if (t->rs_epoch > (1u << 29)) {
+            // tags about to run out: clear the words and start again
+            SR_HIP(hipMemsetAsync(t->rs_status, 0, sizeof(uint64_t) * sr_tree_sort_status_words(t->cap), st));
+            t->rs_epoch = 0;
+        }
+        uint32_t* hist = (uint32_t*)(t->status + ST_RS_HIST);
+        uint32_t* tickets = (uint32_t*)(t->status + ST_RS_TICKET);
+        const int64_t hb = cdiv(n, (int64_t)TPB * 16);
+        hipLaunchKernelGGL(k_os_hist, dim3((unsigned)(hb < 1024 ? hb : 1024)), dim3(TPB), 0, st, t->khi[0],
+                           t->klo[0], n, hist);
+        for (int pass = 0; pass < 12; ++pass) {
+            const int cur = pass & 1;
+            hipLaunchKernelGGL(k_os_pass, dim3((unsigned)tiles), dim3(OS_TPB), 0, st, t->khi[cur], t->klo[cur],
+                               t->kidx[cur], t->khi[cur ^ 1], t->klo[cur ^ 1], t->kidx[cur ^ 1], n, pass,
+                               hist + 256 * pass, tickets + pass, t->rs_status, t->rs_epoch + 1 + (uint32_t)pass,
+                               t->status + ST_FLAGS);
+        }
+        t->rs_epoch += 12;
     }
     // 12 passes leave the sorted keys in buffer 0
     hipLaunchKernelGGL(k_gather, grid_for(n), dim3(TPB), 0, st, pos, mass, eps, eps_scalar, n, box,
@@ -1280,6 +1463,7 @@ int sr_build_device(sr_tree* t, const double* pos, const double* mass, const dou
     SR_HIP(hipEventSynchronize(t->ev_status));
     const int32_t* hstat = t->h_status;
     if (hstat[ST_FLAGS] & 1) return sr_fail(SR_EINVAL, "tree_build: non-finite position or non-positive / non-finite mass or softening");
+    if (hstat[ST_FLAGS] & 4) return sr_fail(SR_EHIP, "tree_build: the key sort's look-back made no progress");
     // softenings that are not all equal select the walk's mixed-softening opening rule
     t->mixed_soft = (hstat[ST_FLAGS] & 2) != 0;
     const int64_t m = n > 1 ? hstat[ST_NODES] : 0;

@@ -70,7 +70,12 @@ enum {
     ST_FLAGS = 0,      // bit 0: non-finite / non-positive input
     ST_NODES = 1,      // number of internal nodes
     ST_MAXDEPTH = 2,   // deepest node depth
-    ST_WORDS = 3
+    ST_WORDS = 3,      // the words read back by the host
+    // tree-key sort: digit totals of its 12 passes (256 each), then its tile tickets
+    ST_RS_HIST = 4,
+    ST_RS_TICKET = ST_RS_HIST + 12 * 256,
+    ST_ALLOC = ST_RS_TICKET + 16   // words allocated and cleared at the start of a build
+
 };
 
 // What a traversal's lists were made for.  `token` names them: shortrange_accel
@@ -104,7 +109,9 @@ struct sr_tree {
     int32_t *b_lo = nullptr, *b_hi = nullptr, *b_lambda = nullptr, *b_parent = nullptr;
     int32_t* b_pre = nullptr;         // pre-order index, -1 if not an octree node
     int32_t* leaf_bparent = nullptr;
-    int32_t* status = nullptr;        // ST_WORDS
+    int32_t* status = nullptr;        // ST_ALLOC
+    uint64_t* rs_status = nullptr;    // tree-key sort: per tile and digit, look-back word
+    uint32_t rs_epoch = 0;            // tags of the look-back words of the last sort
     // pinned host copies of the status words and of the list counters, and the
     // events recorded after those copies: the host waits for these points only
     int32_t* h_status = nullptr;      // ST_WORDS
@@ -185,6 +192,8 @@ int sr_drift_device(sr_tree* t, const double* disp, hipStream_t st);
 int sr_build_device(sr_tree* t, const double* pos, const double* mass, const double* eps,
                     double eps_scalar, hipStream_t st);
 int sr_scan_exclusive(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* tmp, hipStream_t st);
+// build.hip: look-back words the tree-key sort needs for a capacity of cap keys
+int64_t sr_tree_sort_status_words(int64_t cap);
 
 // walk.hip
 int sr_prepare_targets(sr_tree* t, const int32_t* active, int64_t n_active, hipStream_t st);

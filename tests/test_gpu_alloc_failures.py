@@ -43,7 +43,7 @@ def test_tree_build_failures(sg):
     p = w.params("fp64")
     ref_acc, ref_cnt = sg.shortrange_accel(sg.tree_build(pos, mass, eps=eps), p)
     # the first, a middle and the last of the workspace's device allocations
-    for k in (0, 17, 51):
+    for k in (0, 17, 52):
         say(f"alloc failure: tree_build, allocation {k}")
         inject(k)
         with pytest.raises(sg.SrgravError) as ei:
