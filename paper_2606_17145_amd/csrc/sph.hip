@@ -468,23 +468,29 @@ __global__ __launch_bounds__(WAVE) void k_sph_eval(int64_t n, const Rec64* __res
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        for (uint32_t base = 0; base < total; base += WAVE) {
-            // candidate base + lane: the last entry whose offset is at most its index
-            const uint32_t idx = base + (uint32_t)lane;
+        // candidate b + lane: the last entry whose offset is at most its index; the
+        // record of the next block is loaded while this block is evaluated
+        auto fetch = [&](uint32_t b, Rec64& p) __attribute__((always_inline)) {
+            const uint32_t idx = b + (uint32_t)lane;
             if (idx < total) {
                 uint32_t e = 0;
 #pragma unroll
                 for (uint32_t step = 32; step; step >>= 1)
                     if (e + step < (uint32_t)ne && s_off[e + step] <= idx) e += step;
-                const Rec64 p = prec[s_first[e] + (idx - s_off[e])];
-                s_c[lane] = Rec64{min_image(p.x - cx, box, inv_box), min_image(p.y - cy, box, inv_box),
-                                  min_image(p.z - cz, box, inv_box), p.m};
+                p = prec[s_first[e] + (idx - s_off[e])];
             }
+        };
+        Rec64 nxt{0.0, 0.0, 0.0, 0.0};
+        fetch(0, nxt);
+        for (uint32_t base = 0; base < total; base += WAVE) {
+            if (base + (uint32_t)lane < total)
+                s_c[lane] = Rec64{min_image(nxt.x - cx, box, inv_box), min_image(nxt.y - cy, box, inv_box),
+                                  min_image(nxt.z - cz, box, inv_box), nxt.m};
+            fetch(base + WAVE, nxt);
             const int32_t cnt = total - base < (uint32_t)WAVE ? (int32_t)(total - base) : WAVE;
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            auto candidate = [&](const Rec64& p, double dx, double dy, double dz) __attribute__((always_inline)) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");            auto candidate = [&](const Rec64& p, double dx, double dy, double dz) __attribute__((always_inline)) {
                 const double r2 = (dx * dx + dy * dy) + dz * dz;
                 if (r2 < h2) {
                     double wq, qdw;
@@ -494,6 +500,8 @@ __global__ __launch_bounds__(WAVE) void k_sph_eval(int64_t n, const Rec64* __res
                 }
             };
             if (!wide) {
+                // unrolled so that the LDS reads of several candidates are in flight
+#pragma unroll 4
                 for (int32_t e = 0; e < cnt; ++e) {
                     const Rec64 p = s_c[e];
                     candidate(p, p.x - ox, p.y - oy, p.z - oz);
