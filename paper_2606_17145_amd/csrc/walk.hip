@@ -1,11 +1,11 @@
 // Group-wise Barnes-Hut walk (forward and adjoint) of the short-range force,
 // in three phases:
-//   1. traverse: one wavefront per 64 Morton-consecutive targets takes every
-//      lane's depth-first-walk decisions (ballots over the pre-order item
-//      sequence) and writes the interaction list as (source, lane mask)
-//      entries in chunks of 64;
-//   2. evaluate: one wavefront per unit of up to UCH chunks sweeps the entries,
-//      evaluating the pair force for the lanes in each mask;
+//   1. traverse: a workgroup per 64 Morton-consecutive targets (one target per
+//      lane) walks the tree breadth-first, every lane deciding against each
+//      staged node, and writes the interaction list as (source, lane mask)
+//      entries in chunks of 64, the chunks grouped into units of a few;
+//   2. evaluate: one wavefront per unit sweeps the entries, evaluating the
+//      pair force for the lanes in each mask;
 //   3. reduce: the units' partial sums are added per group in a fixed order.
 // The adjoint reuses the forward's lists (the frozen decisions) and scatters
 // source terms with wave sums and FP64 atomics.
@@ -196,7 +196,16 @@ __device__ inline uint64_t wl64(uint64_t v, uint32_t l, uint64_t old)
 // chunk by chunk, its GPU-porting subsection) with chunks of a wavefront's
 // width, decoupled from the walk so that heavy groups spread over many waves.
 
-constexpr int UCH = 8;   // chunks per evaluation unit
+// Chunks per evaluation unit (both entry points: the units' partial sums set the
+// order of the FP32 sums), and unit indices a traversal wave reserves per atomic:
+// 4 on the handle's lists, 1 in the fixed scratch of the allocation-free forward.
+// Against 8 chunks and 1 unit: traversal + forward and adjoint evaluation
+// 1.58 -> 1.47 ms on clustered 262k, the smaller units spreading heavy groups
+// over more waves.
+#ifndef SR_UCH
+#define SR_UCH 2
+#endif
+constexpr int UCH = SR_UCH;
 
 struct ListArgs {
     uint32_t* ent_src;
@@ -214,6 +223,7 @@ struct ListArgs {
     int32_t unit_base;      // evaluation: first unit of this launch
     int32_t unit_end;       // evaluation: one past the last unit of this launch
     int32_t chunk_batch;    // traversal: chunk indices a wave reserves per atomic
+    int32_t unit_batch;     // traversal: unit indices a wave reserves per atomic
 };
 
 // open and accept masks of one decision
@@ -370,7 +380,7 @@ constexpr int DEC_ILP = SR_DEC_ILP;   // decisions interleaved in the traversal
 #define SR_CHUNK_BATCH 64
 #endif
 #ifndef SR_UNIT_BATCH
-#define SR_UNIT_BATCH 1
+#define SR_UNIT_BATCH 4
 #endif
 // chunk indices reserved per atomic: 64 on the handle's lists (16 fewer atomics than
 // one per chunk: 0.47 -> 0.45 ms on clustered 262k against 16), 16 in the fixed
@@ -378,7 +388,8 @@ constexpr int DEC_ILP = SR_DEC_ILP;   // decisions interleaved in the traversal
 // must fit
 constexpr int TRAV_CHUNK_BATCH = SR_CHUNK_BATCH;
 constexpr int TRAV_CHUNK_BATCH_NOALLOC = 16;
-constexpr int TRAV_UNIT_BATCH = SR_UNIT_BATCH;     // unit indices reserved per atomic
+constexpr int TRAV_UNIT_BATCH = SR_UNIT_BATCH;
+constexpr int TRAV_UNIT_BATCH_NOALLOC = 1;
 
 template <bool DEC64, bool REL, bool MIXED>
 __global__ __launch_bounds__(TW * WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_traverse(WalkArgs a, ListArgs L, FrontArgs F)
@@ -421,9 +432,9 @@ __global__ __launch_bounds__(TW * WAVE) __attribute__((amdgpu_waves_per_eu(4, 8)
     auto take_unit = [&]() __attribute__((always_inline)) -> int32_t {
         if (u_next == u_end) {
             uint32_t b = 0;
-            if (lane == 0) b = atomicAdd((uint32_t*)&L.counters[1], (uint32_t)TRAV_UNIT_BATCH);
+            if (lane == 0) b = atomicAdd((uint32_t*)&L.counters[1], (uint32_t)L.unit_batch);
             u_next = rl(b, 0);
-            u_end = u_next + TRAV_UNIT_BATCH;
+            u_end = u_next + (uint32_t)L.unit_batch;
         }
         return (int32_t)u_next++;
     };
@@ -923,7 +934,7 @@ __global__ __launch_bounds__(TW * WAVE) __attribute__((amdgpu_waves_per_eu(4, 8)
 }
 
 // ----------------------------------------------------------------------------------
-// phase 2: evaluation of one unit (up to UCH chunks of one group)
+// phase 2: evaluation of one unit (a few chunks of one group)
 // ----------------------------------------------------------------------------------
 
 // per-unit partial results: acc_t[3][64] then int32[2][64] (forward) or acc_t[3][64] (adjoint)
@@ -1609,6 +1620,7 @@ struct ListStore {
     uint32_t* frontier;
     int64_t cap_chunks, cap_units, cap_front;
     int chunk_batch;   // chunk indices a traversal wave reserves per atomic
+    int unit_batch;    // unit indices a traversal wave reserves per atomic
 };
 
 ListStore handle_store(const sr_tree* t)
@@ -1630,6 +1642,7 @@ ListStore handle_store(const sr_tree* t)
     S.cap_units = t->cap_units;
     S.cap_front = t->cap_front;
     S.chunk_batch = TRAV_CHUNK_BATCH;
+    S.unit_batch = TRAV_UNIT_BATCH;
     return S;
 }
 
@@ -1651,6 +1664,7 @@ ListArgs list_args(const ListStore& S)
     L.unit_base = 0;
     L.unit_end = 0;
     L.chunk_batch = S.chunk_batch;
+    L.unit_batch = S.unit_batch;
     return L;
 }
 
@@ -2008,7 +2022,7 @@ int scratch_address(char** out)
 
 // Lays out a list store for n_t targets and `wgs` traversal workgroups in the
 // buffer at `base`: counters, group heads and the frontier first, then units
-// and chunks in the handle's proportion (UCH chunks per unit, plus the units
+// and chunks in proportion (UCH chunks per unit, plus the units
 // every wave may open or leave reserved).
 int carve_scratch(char* base, int64_t n_t, int64_t wgs, ListStore& S)
 {
@@ -2022,11 +2036,12 @@ int carve_scratch(char* base, int64_t n_t, int64_t wgs, ListStore& S)
     off += up(groups * (int64_t)sizeof(int32_t));
     S.cap_front = NOALLOC_FRONT;
     S.chunk_batch = TRAV_CHUNK_BATCH_NOALLOC;
+    S.unit_batch = TRAV_UNIT_BATCH_NOALLOC;
     S.frontier = (uint32_t*)(base + off);
     off += up(wgs * TW * S.cap_front * 6 * (int64_t)sizeof(uint32_t));
     const int64_t per_chunk = 64 * 4 + 64 * 8 + 2 * 4;   // ent_src, ent_mask, next, count
     const int64_t per_unit = 4 * 4 + PARTIAL_BYTES;       // group, chunk, nch, next, partials
-    const int64_t unit_fixed = TW * groups + TW * wgs * TRAV_UNIT_BATCH + 1;
+    const int64_t unit_fixed = TW * groups + TW * wgs * TRAV_UNIT_BATCH_NOALLOC + 1;
     const int64_t slack = 10 * 256;                       // alignment of the ten arrays below
     const int64_t left = SR_NOALLOC_SCRATCH_BYTES - off - slack - unit_fixed * per_unit;
     const int64_t chunks = left > 0 ? left * UCH / (UCH * per_chunk + per_unit) : 0;
