@@ -951,7 +951,10 @@ constexpr int EVAL_WAVES = SR_EVAL_WAVES;
 #ifndef SR_QL_ADJ
 #define SR_QL_ADJ 16
 #endif
-constexpr int QL_FWD = 8;
+#ifndef SR_QL_FWD
+#define SR_QL_FWD 8
+#endif
+constexpr int QL_FWD = SR_QL_FWD;
 constexpr int QL_ADJ = SR_QL_ADJ;
 static_assert(QL_ADJ == 8 || QL_ADJ == 16, "stream width");
 
