@@ -360,7 +360,7 @@ def main():
         if f and avg[ph] > 0:
             ex = float(f) / (avg[ph] * 1e-3) / 1e12
             valu[ph] = {"executed_tflops": ex, "executed_frac": ex / FP32_PEAK_TFLOPS,
-                        "valu_busy": float(cv[f"{ph}_valu_busy"]),
+                        "valu_insts_per_simd_cycle": float(cv[f"{ph}_valu_insts_per_simd_cycle"]),
                         "algorithmic_tflops": work[ph] / (avg[ph] * 1e-3) / 1e12}
     out["valu_counters"] = valu or None
 
