@@ -918,6 +918,7 @@ constexpr int MP_SLOTS = 32;                             // list slots per parti
 constexpr int MP_FAN = 32;                               // sub-partitions per partition of a later pass
 constexpr int ML_TPB = 512;
 constexpr int ML_CAND = MP_FAN * MP_SLOTS;
+constexpr int ML_POOL = 1024;   // children staged in LDS by a later pass (without DRIFT)
 
 struct MomList {
     int32_t* nodes;    // MP_SLOTS per partition
@@ -1145,8 +1146,16 @@ __global__ __launch_bounds__(ML_TPB) void k_moments_list(MomArgs A, const int32_
     __shared__ uint32_t s_meta[ML_CAND];
     __shared__ uint4 s_kids[ML_CAND][2];
     __shared__ int32_t s_off[MP_FAN + 1];
-    __shared__ int32_t s_dmin, s_dmax, s_cmin, s_out;
+    __shared__ int32_t s_dmin, s_dmax, s_cmin, s_out, s_pool_n;
+    // without DRIFT: the children's data staged once for the folds of every depth --
+    // per child of a listed node, a pool slot (particle or node folded earlier) or
+    // -1 - the listed node's index; nodes whose children do not fit fold from global
+    // memory
+    __shared__ double s_pool[6][DRIFT ? 1 : ML_POOL];
+    __shared__ int16_t s_cref[DRIFT ? 1 : ML_CAND][8];
+    __shared__ uint8_t s_staged[DRIFT ? 1 : ML_CAND];
     if (threadIdx.x == 0) {
+        s_pool_n = 0;
         // candidate offsets: the sub-partitions' lists concatenated (pre-order)
         int32_t o = 0;
         for (int q = 0; q < MP_FAN; ++q) {
@@ -1190,22 +1199,85 @@ __global__ __launch_bounds__(ML_TPB) void k_moments_list(MomArgs A, const int32_
     if (cmin < (1 << 30)) atomicMin(&s_cmin, cmin);
     __syncthreads();
     const int32_t dmin = s_dmin, dmax = s_dmax, dtop = s_cmin;
+    // a node child listed in this block (its slot points back at it) is read from
+    // LDS, one folded by an earlier pass from global memory
+    auto here = [&](uint32_t r, int32_t j) { return j >= 0 && j < cnt && s_nd[j] == (int32_t)r; };
     for (int k = threadIdx.x; k < cnt; k += ML_TPB)
         if (s_dp[k] < 0) {
             out.nodes[blockIdx.x * (int64_t)MP_SLOTS + (-1 - s_dp[k]) - dtop] = s_nd[k];
             atomicAdd(&s_out, 1);
         }
+    if constexpr (!DRIFT) {
+        for (int k = threadIdx.x; k < cnt; k += ML_TPB) {
+            s_staged[k] = 0;
+            const uint32_t mt = s_meta[k];
+            if (s_dp[k] < 0 || mt == META_BUCKET) continue;
+            const uint4 ka = s_kids[k][0], kb = s_kids[k][1];
+            const uint32_t kr[8] = {ka.x, ka.y, ka.z, ka.w, kb.x, kb.y, kb.z, kb.w};
+            // every child's data and slot loaded at once (addresses selected; slots past
+            // the last child load particle 0)
+            double raw[8][6];
+            int32_t js[8];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const uint32_t r = (uint32_t)c < mt ? kr[c] : ITEM_PARTICLE;
+                const bool pt = (r & ITEM_PARTICLE) != 0;
+                const uint32_t q = pt ? r & ~ITEM_PARTICLE : 0u, nd = pt ? 0u : r;
+                const Rec64* pr = A.r64 + q;
+                const double* src[6] = {pt ? &pr->m : &A.nrec64[nd].m, pt ? &pr->x : A.nS + 3 * nd,
+                                        pt ? &pr->y : A.nS + 3 * nd + 1, pt ? &pr->z : A.nS + 3 * nd + 2,
+                                        pt ? A.h64 + q : A.nhmax + nd, pt ? A.h64 + q : A.nhmin + nd};
+#pragma unroll
+                for (int e = 0; e < 6; ++e) raw[c][e] = *src[e];
+                js[c] = slot[nd];
+            }
+            int need = 0;
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+                need += (uint32_t)c < mt && ((kr[c] & ITEM_PARTICLE) || !here(kr[c], js[c])) ? 1 : 0;
+            const int base = atomicAdd(&s_pool_n, need);
+            if (base + need > ML_POOL) continue;
+            int used = 0;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                if ((uint32_t)c >= mt) continue;
+                if (!(kr[c] & ITEM_PARTICLE) && here(kr[c], js[c])) {
+                    s_cref[k][c] = (int16_t)(-1 - js[c]);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 6; ++e) s_pool[e][base + used] = raw[c][e];
+                    s_cref[k][c] = (int16_t)(base + used);
+                    ++used;
+                }
+            }
+            s_staged[k] = 1;
+        }
+        __syncthreads();
+    }
     for (int32_t d = dmax; d >= dmin; --d) {
         for (int k = threadIdx.x; k < cnt; k += ML_TPB) {
             if (s_dp[k] != d) continue;
             const uint32_t mt = s_meta[k];
             const uint4 ka = s_kids[k][0], kb = s_kids[k][1];
             const uint32_t kr[8] = {ka.x, ka.y, ka.z, ka.w, kb.x, kb.y, kb.z, kb.w};
-            // a node child listed in this block (its slot points back at it) is read
-            // from LDS, one folded by an earlier pass from global memory
-            auto here = [&](uint32_t r, int32_t j) { return j >= 0 && j < cnt && s_nd[j] == (int32_t)r; };
             NodeFold f{};
-            if (mt == META_BUCKET) {
+            bool staged = false;
+            if constexpr (!DRIFT) staged = s_staged[k] != 0;
+            if (staged) {
+                if constexpr (!DRIFT) {
+                    double raw[8][6];
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) {
+                        if ((uint32_t)c >= mt) continue;
+                        const int ref = s_cref[k][c];
+#pragma unroll
+                        for (int e = 0; e < 6; ++e) raw[c][e] = *(ref >= 0 ? &s_pool[e][ref] : &s_n.v[e][-1 - ref]);
+                    }
+#pragma unroll
+                    for (int c = 0; c < 8; ++c)
+                        if ((uint32_t)c < mt) fold_child(f, c == 0, child_terms(kr[c], raw[c]));
+                }
+            } else if (mt == META_BUCKET) {
                 for (uint32_t c = 0; c < kr[1]; ++c) {
                     const Rec64 p = A.r64[kr[0] + c];
                     fold_child(f, c == 0, particle_terms(p.m, p.x, p.y, p.z, A.h64[kr[0] + c]));
