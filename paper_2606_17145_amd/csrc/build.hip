@@ -1154,19 +1154,20 @@ __global__ __launch_bounds__(ML_TPB) void k_moments_list(MomArgs A, const int32_
     __shared__ double s_pool[6][DRIFT ? 1 : ML_POOL];
     __shared__ int16_t s_cref[DRIFT ? 1 : ML_CAND][8];
     __shared__ uint8_t s_staged[DRIFT ? 1 : ML_CAND];
-    if (threadIdx.x == 0) {
-        s_pool_n = 0;
-        // candidate offsets: the sub-partitions' lists concatenated (pre-order)
-        int32_t o = 0;
-        for (int q = 0; q < MP_FAN; ++q) {
-            s_off[q] = o;
-            const int64_t sub = blockIdx.x * (int64_t)MP_FAN + q;
-            o += sub < n_sub ? in.count[sub] : 0;
+    if (threadIdx.x < 64) {
+        // candidate offsets: the sub-partitions' lists concatenated (pre-order), an
+        // exclusive scan of their counts over the first wave
+        const int q = threadIdx.x;
+        const int64_t sub = blockIdx.x * (int64_t)MP_FAN + q;
+        const uint32_t c = q < MP_FAN && sub < n_sub ? (uint32_t)in.count[sub] : 0u;
+        const uint32_t inc = wave_inclusive_scan(c);
+        if (q <= MP_FAN) s_off[q] = (int32_t)(inc - c);
+        if (q == 0) {
+            s_pool_n = 0;
+            s_dmin = s_cmin = 1 << 30;
+            s_dmax = -1;
+            s_out = 0;
         }
-        s_off[MP_FAN] = o;
-        s_dmin = s_cmin = 1 << 30;
-        s_dmax = -1;
-        s_out = 0;
     }
     __syncthreads();
     const int32_t cnt = s_off[MP_FAN];
