@@ -154,6 +154,31 @@ def clustered_2m_active() -> Workload:
     return w
 
 
+def deep_chains(levels: int = 25) -> Workload:
+    """A chain of nested cells in every cell of the 8^3 grid: at each of `levels`
+    levels one particle at the centre of seven octants and the eighth octant
+    refined again, down to octree level 27 (exact dyadic positions, 93,696
+    particles for 25 levels).  Sorted, the particles of any 512-particle run end
+    inside a chain, so up to 25 nested nodes reach past the run's end, each with
+    seven particle children; the tree is 28 nodes deep."""
+    pts = []
+    octs = np.array([[(o >> 0) & 1, (o >> 1) & 1, (o >> 2) & 1] for o in range(8)], dtype=np.float64)
+    for ix in range(8):
+        for iy in range(8):
+            for iz in range(8):
+                c = np.array([ix, iy, iz], dtype=np.float64) / 8.0
+                s = 1.0 / 8.0
+                for _ in range(levels):
+                    pts.append(c + s * (0.25 + 0.5 * octs[1:]))
+                    s *= 0.5
+                pts.append(c + s * (0.25 + 0.5 * octs))
+    pos = np.concatenate(pts)
+    n = pos.shape[0]
+    w = Workload("deep_chains", pos, np.full(n, 1.0 / n), np.full(n, 1 / 600.0))
+    w.r_s, w.r_cut = split_scales(48)
+    return w
+
+
 def adjoint_weights(n: int, seed: int = 104) -> np.ndarray:
     """Cotangent w_i ~ N(0, 1)^3 of the loss L = sum_i w_i . a_i."""
     return np.random.default_rng(seed).standard_normal((n, 3))

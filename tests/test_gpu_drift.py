@@ -119,6 +119,26 @@ def test_drift_matches_oracle(sg, oracle, case):
     assert np.allclose(dm.cpu().numpy(), gm, rtol=1e-10, atol=1e-11 * sm)
 
 
+def test_drift_deep_chains(sg, oracle):
+    """A 28-deep tree whose 512-particle runs all end inside nested chains: the
+    refold passes over partition-crossing nodes hold hundreds of nodes per block."""
+    w = WL.deep_chains()
+    rng = np.random.default_rng(34)
+    disp = 1e-4 * rng.standard_normal((w.n, 3))
+    say(f"drift: deep chains N={w.n}")
+    t = gpu_tree(sg, w)
+    d = oracle.Tree(w.pos, w.mass, w.eps).drift(disp)
+    t.drift(torch.tensor(disp, device=DEV))
+    check_tree(t, d)
+    p = w.params("fp64")
+    acc, cnt = sg.shortrange_accel(t, p)
+    acc_ref, cnt_ref = oracle.walk(d, p)
+    assert np.array_equal(cnt.cpu().numpy(), cnt_ref)
+    e = rel_err(acc.cpu().numpy(), acc_ref)
+    say(f"   fp64 max rel err {e.max():.3e}")
+    assert e.max() <= 1e-12
+
+
 def test_drift_active_subset_relative(sg, oracle):
     w = workload("clustered")
     disp = displacement(w, seed=34)

@@ -64,6 +64,8 @@ def edge_case(name):
         pos = rng.uniform(-3.0, 4.0, (2000, 3))
     elif name == "ragged":
         pos = rng.random((5003, 3))
+    elif name == "deep_chains":
+        return WL.deep_chains()
     else:
         raise KeyError(name)
     n = pos.shape[0]
@@ -72,7 +74,7 @@ def edge_case(name):
     return w
 
 
-TREE_CASES = ["n1", "n2", "duplicates", "one_octant", "boundary", "unwrapped", "ragged"]
+TREE_CASES = ["n1", "n2", "duplicates", "one_octant", "boundary", "unwrapped", "ragged", "deep_chains"]
 
 
 @pytest.mark.parametrize("case", TREE_CASES + ["clustered_40k", "uniform_32k", "clustered_262k"])
@@ -105,7 +107,7 @@ def test_tree_bit_exact(sg, oracle, case):
 
 
 @pytest.mark.parametrize("case", ["n1", "n2", "duplicates", "one_octant", "boundary", "unwrapped", "ragged",
-                                  "clustered_20k", "uniform_32k"])
+                                  "deep_chains", "clustered_20k", "uniform_32k"])
 def test_fp64_walk_all_targets(sg, oracle, case):
     if case == "clustered_20k":
         w = WL.clustered(20_000, seed=6, n_spheres=10)
