@@ -1419,16 +1419,43 @@ __global__ __launch_bounds__(WAVE) void k_reduce(WalkArgs a, ListArgs L, const c
     if (t >= a.n_t) return;
     acc_t ax = 0, ay = 0, az = 0;
     int npp = 0, npn = 0;
-    for (int32_t u = L.group_head[g]; u >= 0; u = L.unit_next[u]) {
-        const acc_t* pa = (const acc_t*)(partials + (int64_t)u * PARTIAL_BYTES);
-        ax += pa[lane];
-        ay += pa[64 + lane];
-        az += pa[128 + lane];
-        if constexpr (!ADJ) {
-            const int32_t* pc = (const int32_t*)(pa + 192);
-            npp += pc[lane];
-            npn += pc[64 + lane];
+    // A group's chain mostly runs through consecutive unit indices (a traversal wave
+    // reserves several at a time): the next pointers and partials of units u .. u + 3
+    // are loaded together and used as far as the chain does run consecutively, in
+    // chain order.
+    constexpr int RUN = 4;
+    for (int32_t u = L.group_head[g]; u >= 0;) {
+        int32_t nx[RUN];
+        acc_t px[RUN], py[RUN], pz[RUN];
+        int32_t cp[RUN], cn[RUN];
+#pragma unroll
+        for (int k = 0; k < RUN; ++k) {
+            const int32_t v = u + k < L.cap_units ? u + k : u;
+            nx[k] = L.unit_next[v];
+            const acc_t* pa = (const acc_t*)(partials + (int64_t)v * PARTIAL_BYTES);
+            px[k] = pa[lane];
+            py[k] = pa[64 + lane];
+            pz[k] = pa[128 + lane];
+            if constexpr (!ADJ) {
+                const int32_t* pc = (const int32_t*)(pa + 192);
+                cp[k] = pc[lane];
+                cn[k] = pc[64 + lane];
+            }
         }
+        int32_t next = nx[0];
+#pragma unroll
+        for (int k = 0; k < RUN; ++k) {
+            ax += px[k];
+            ay += py[k];
+            az += pz[k];
+            if constexpr (!ADJ) {
+                npp += cp[k];
+                npn += cn[k];
+            }
+            next = nx[k];
+            if (k == RUN - 1 || nx[k] != u + k + 1) break;
+        }
+        u = next;
     }
     if constexpr (ADJ) {
         const int32_t s_i = a.tgt_sorted[t];
