@@ -333,7 +333,7 @@ __global__ void k_rs_scatter(const uint64_t* __restrict__ hi, const uint64_t* __
 // ------------------------------------------------------------------------------------
 //
 // One launch histograms all 12 digits; then one launch per 8-bit digit, LSD
-// order.  A pass's workgroups take tiles of OS_TILE consecutive keys in ticket
+// order.  A pass's workgroups take tiles of OS_TPB x OS_ITEMS consecutive keys in ticket
 // order (a device counter) and rank their keys in the tile (stable: wave w holds
 // a contiguous run, rounds in order, lanes in order, per-wave digit counters in
 // LDS).  Per digit, a tile publishes its count, then, once the counts of all
@@ -348,10 +348,17 @@ __global__ void k_rs_scatter(const uint64_t* __restrict__ hi, const uint64_t* __
 // between sorts.  The tile is then reordered by digit in LDS and written out
 // with consecutive threads on consecutive output positions.
 constexpr int OS_TPB = 1024;
-constexpr int OS_ITEMS = 4;
+#ifndef SR_OS_WIN
+#define SR_OS_WIN 16
+#endif
+// keys per thread: 2 (tiles of 2048) up to OS_SMALL_N keys, else 4 (tiles of 4096):
+// 0.399 -> 0.389 ms per build on clustered 262k, while 2048-key tiles cost the
+// 2M-particle build 1.31 -> 1.47 ms (twice the tiles to look back over)
+constexpr int64_t OS_SMALL_N = 512 * 1024;
+constexpr int OS_ITEMS_MIN = 2;
 constexpr int OS_WAVES = OS_TPB / 64;
-constexpr int OS_TILE = OS_TPB * OS_ITEMS;
-constexpr int OS_WIN = 16;
+constexpr int OS_TILE_MIN = OS_TPB * OS_ITEMS_MIN;
+constexpr int OS_WIN = SR_OS_WIN;
 constexpr uint32_t OS_AGG = 1u, OS_INC = 2u;
 constexpr int64_t OS_SPIN_MAX = int64_t(1) << 20;
 
@@ -386,6 +393,7 @@ __device__ inline uint32_t digit_exclusive_scan(uint32_t v, uint32_t* s_w)
     return off + inc - v;
 }
 
+template <int OS_ITEMS>
 __global__ __launch_bounds__(OS_TPB) void k_os_pass(const uint64_t* __restrict__ hi, const uint64_t* __restrict__ lo,
                                                     const uint32_t* __restrict__ idx, uint64_t* __restrict__ ohi,
                                                     uint64_t* __restrict__ olo, uint32_t* __restrict__ oidx,
@@ -397,6 +405,7 @@ __global__ __launch_bounds__(OS_TPB) void k_os_pass(const uint64_t* __restrict__
     __shared__ uint32_t s_base[256];             // output position of the tile's first key of each digit
     __shared__ uint32_t s_start[256];            // tile position of the first key of each digit
     __shared__ uint32_t s_w[4];
+    constexpr int OS_TILE = OS_TPB * OS_ITEMS;
     __shared__ uint64_t s_hi[OS_TILE], s_lo[OS_TILE];
     __shared__ uint32_t s_ix[OS_TILE];
     __shared__ int64_t s_tile;
@@ -1438,7 +1447,7 @@ int sort_items(int64_t n) { return n <= 384 * 1024 ? 2 : n <= 1536 * 1024 ? 4 : 
 
 int64_t sr_tree_sort_status_words(int64_t cap)
 {
-    return 256 * cdiv(cap > 0 ? cap : 1, (int64_t)OS_TILE);
+    return 256 * cdiv(cap > 0 ? cap : 1, (int64_t)OS_TILE_MIN);
 }
 
 int64_t sr_sort_hist_words(int64_t n)
@@ -1475,7 +1484,8 @@ int sr_build_device(sr_tree* t, const double* pos, const double* mass, const dou
                        t->khi[0], t->klo[0], t->kidx[0], t->status);
     // 12 passes of 8 bits: lo word bits 0..47, then hi word bits 0..47
     {
-        const int64_t tiles = cdiv(n, (int64_t)OS_TILE);
+        const bool small = n <= OS_SMALL_N;
+        const int64_t tiles = cdiv(n, (int64_t)OS_TPB * (small ? 2 : 4));
         if (t->rs_epoch > (1u << 29)) {
             // tags about to run out: clear the words and start again
             SR_HIP(hipMemsetAsync(t->rs_status, 0, sizeof(uint64_t) * sr_tree_sort_status_words(t->cap), st));
@@ -1488,10 +1498,16 @@ int sr_build_device(sr_tree* t, const double* pos, const double* mass, const dou
                            t->klo[0], n, hist);
         for (int pass = 0; pass < 12; ++pass) {
             const int cur = pass & 1;
-            hipLaunchKernelGGL(k_os_pass, dim3((unsigned)tiles), dim3(OS_TPB), 0, st, t->khi[cur], t->klo[cur],
-                               t->kidx[cur], t->khi[cur ^ 1], t->klo[cur ^ 1], t->kidx[cur ^ 1], n, pass,
-                               hist + 256 * pass, tickets + pass, t->rs_status, t->rs_epoch + 1 + (uint32_t)pass,
-                               t->status + ST_FLAGS);
+            if (small)
+                hipLaunchKernelGGL(k_os_pass<2>, dim3((unsigned)tiles), dim3(OS_TPB), 0, st, t->khi[cur],
+                                   t->klo[cur], t->kidx[cur], t->khi[cur ^ 1], t->klo[cur ^ 1], t->kidx[cur ^ 1], n,
+                                   pass, hist + 256 * pass, tickets + pass, t->rs_status,
+                                   t->rs_epoch + 1 + (uint32_t)pass, t->status + ST_FLAGS);
+            else
+                hipLaunchKernelGGL(k_os_pass<4>, dim3((unsigned)tiles), dim3(OS_TPB), 0, st, t->khi[cur],
+                                   t->klo[cur], t->kidx[cur], t->khi[cur ^ 1], t->klo[cur ^ 1], t->kidx[cur ^ 1], n,
+                                   pass, hist + 256 * pass, tickets + pass, t->rs_status,
+                                   t->rs_epoch + 1 + (uint32_t)pass, t->status + ST_FLAGS);
         }
         t->rs_epoch += 12;
     }
