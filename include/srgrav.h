@@ -249,7 +249,7 @@ enum {
     SR_T_PM_STENCIL = 11,  /* PM adjoint: transposed difference rule on one weight mesh */
     SR_T_PM_ADJ_GATHER = 12, /* PM adjoint: per-particle position and mass gradients */
     SR_T_PM_SORT = 13,     /* PM: particles sorted by mesh cell for the assignment */
-    SR_T_SPH_ITER = 14,    /* SPH density: one iteration (neighbour walk, Newton step) */
+    SR_T_SPH_ITER = 14,    /* SPH density: one iteration (neighbour walk, Halley step) */
     SR_T_DRIFT = 15,       /* tree_drift: moved particle records, refolded moments and cubes */
     SR_T_COUNT = 16
 };
@@ -380,8 +380,11 @@ void pm_free(sr_pm* pm);
  *   N_i(h)   = (4 pi / 3) h^3 rho_i(h) / m_i
  *
  * h_i is the root of N_i(h) = n_ngb (unique: N_i is strictly increasing once a
- * neighbour lies within h), found by safeguarded Newton iterations to
- * |N_i - n_ngb| <= 1e-13 n_ngb or a closed bracket; rho_i = rho_i(h_i).
+ * neighbour lies within h), found by safeguarded Halley iterations (in h^3) to
+ * |N_i - n_ngb| <= 1e-13 n_ngb or a closed bracket, or ended by a bracketed
+ * Halley step taken from |N_i - n_ngb| <= 1e-5 n_ngb (whose error is of the
+ * order of the cube of that); rho_i = rho_i(h_i), which at the root is
+ * 3 n_ngb m_i / (4 pi h_i^3).
  *
  *   tree         built by tree_build; its positions, masses and box are used
  *   n_ngb        the neighbour number, finite and > 32/3 (the particle alone)

@@ -18,9 +18,10 @@
 //           group's active particles, R = a margin times their largest h; the
 //           candidates go to chunks of 64, UCH chunks to a unit;
 //   eval    one wave per unit: the unit's candidates are staged in LDS and
-//           every lane sums m_j w and m_j q w' over those inside its own h;
+//           every lane sums m_j w, m_j q w' and m_j q^2 w'' over those inside
+//           its own h;
 //   update  one wave per group: the units' sums in order, then a safeguarded
-//           Newton step in h^3 inside the bracket found so far.
+//           Halley step in h^3 inside the bracket found so far.
 // The candidates are kept across iterations while every active h stays within
 // the gathered radius (and above half of it, so that the lists do not stay far
 // larger than the balls).
@@ -35,6 +36,9 @@ constexpr int SPH_TPB = 256;
 constexpr int SPH_MAX_ITER = 100;
 constexpr double SPH_INIT_FRACTION = 0.25;   // the initial density from the smallest ancestor with T/4 particles
 constexpr double SPH_GROW = 2.0;             // largest growth of h per step before an upper bound is known
+constexpr double SPH_HALLEY_BAND = 0.1;      // |N - T| / T below which the step is Halley's (else Newton's)
+constexpr double SPH_ACCEPT = 1e-5;          // |N - T| / T below which a bracketed Halley step ends the iteration
+constexpr int SPH_PARTS = 3;                 // per-unit sums per particle
 // Gathered radius / largest active h of the group, and chunks per evaluation
 // unit: 1.2 and 2 (against 1.3 and 8: 10.8 -> 9.6 ms per call on clustered 262k,
 // 58.4 -> 57.8 ms on the 2M active subset; a wider margin gathers more candidates
@@ -56,19 +60,22 @@ enum { SC_CHUNKS = 0, SC_UNITS = 1, SC_OVERFLOW = 2, SC_GROUP = 3, SC_ACTIVE = 4
 
 inline dim3 sph_grid(int64_t n) { return dim3((unsigned)((n + SPH_TPB - 1) / SPH_TPB)); }
 
-// w(q) and q w'(q) of the cubic spline (zero beyond q = 1).
-__device__ inline void spline_w(double q, double& wq, double& qdw)
+// w(q), q w'(q) and q^2 w''(q) of the cubic spline (zero beyond q = 1).
+__device__ inline void spline_w(double q, double& wq, double& qdw, double& q2ddw)
 {
     if (q <= 0.5) {
         wq = 1.0 - 6.0 * q * q + 6.0 * q * q * q;
         qdw = q * (-12.0 * q + 18.0 * q * q);
+        q2ddw = q * q * (-12.0 + 36.0 * q);
     } else if (q <= 1.0) {
         const double u = 1.0 - q;
         wq = 2.0 * u * u * u;
         qdw = -6.0 * q * u * u;
+        q2ddw = 12.0 * q * q * u;
     } else {
         wq = 0.0;
         qdw = 0.0;
+        q2ddw = 0.0;
     }
 }
 
@@ -105,7 +112,7 @@ struct SphLists {
                             // spans more than half the period on some axis
     int32_t* counters;      // SC_WORDS
     uint32_t* front;        // per gather wave: two levels of cap_front node ids
-    double* partials;       // per unit: A[64], D[64]
+    double* partials;       // per unit: A[64], D[64], E[64]
     int64_t cap_chunks, cap_units, cap_front;
 };
 
@@ -453,7 +460,7 @@ __global__ __launch_bounds__(WAVE) void k_sph_eval(int64_t n, const Rec64* __res
     const bool wide = S.gbox[4 * g + 3] != 0.0;
     const double ox = min_image(me.x - cx, box, inv_box), oy = min_image(me.y - cy, box, inv_box),
                  oz = min_image(me.z - cz, box, inv_box);
-    double A = 0.0, D = 0.0;       // sum m_j w(q_j), sum m_j q_j w'(q_j)
+    double A = 0.0, D = 0.0, E = 0.0;   // sums of m_j w(q_j), m_j q_j w'(q_j), m_j q_j^2 w''(q_j)
     int32_t c = S.unit_chunk[u];
     for (int32_t q = 0; q < nch; ++q) {
         // the chunk's entries (ranges of sorted particles) and their offsets in the
@@ -503,10 +510,11 @@ __global__ __launch_bounds__(WAVE) void k_sph_eval(int64_t n, const Rec64* __res
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");            auto candidate = [&](const Rec64& p, double dx, double dy, double dz) __attribute__((always_inline)) {
                 const double r2 = (dx * dx + dy * dy) + dz * dz;
                 if (r2 < h2) {
-                    double wq, qdw;
-                    spline_w(sqrt(r2) * inv_h, wq, qdw);
+                    double wq, qdw, q2ddw;
+                    spline_w(sqrt(r2) * inv_h, wq, qdw, q2ddw);
                     A += p.m * wq;
                     D += p.m * qdw;
+                    E += p.m * q2ddw;
                 }
             };
             if (!wide) {
@@ -529,11 +537,12 @@ __global__ __launch_bounds__(WAVE) void k_sph_eval(int64_t n, const Rec64* __res
         }
         c = cnext;
     }
-    S.partials[(int64_t)u * 2 * WAVE + lane] = A;
-    S.partials[(int64_t)u * 2 * WAVE + WAVE + lane] = D;
+    S.partials[(int64_t)u * SPH_PARTS * WAVE + lane] = A;
+    S.partials[(int64_t)u * SPH_PARTS * WAVE + WAVE + lane] = D;
+    S.partials[(int64_t)u * SPH_PARTS * WAVE + 2 * WAVE + lane] = E;
 }
 
-// One group per wave: its units' sums in unit order, then the Newton step.
+// One group per wave: its units' sums in unit order, then the Halley step.
 __global__ __launch_bounds__(WAVE) void k_sph_update(int64_t n, const Rec64* __restrict__ prec, double target,
                                                      double h_max, double* __restrict__ h, double* __restrict__ lo,
                                                      double* __restrict__ hi, int32_t* __restrict__ state,
@@ -545,10 +554,11 @@ __global__ __launch_bounds__(WAVE) void k_sph_update(int64_t n, const Rec64* __r
     const int64_t s = g * WAVE + lane;
     const bool act = s < n && state[s] == SPH_ACTIVE;
     const double R = S.rad[g];
-    double A = 0.0, D = 0.0;
+    double A = 0.0, D = 0.0, E = 0.0;
     for (int32_t u = S.group_head[g]; u >= 0; u = S.unit_next[u]) {
-        A += S.partials[(int64_t)u * 2 * WAVE + lane];
-        D += S.partials[(int64_t)u * 2 * WAVE + WAVE + lane];
+        A += S.partials[(int64_t)u * SPH_PARTS * WAVE + lane];
+        D += S.partials[(int64_t)u * SPH_PARTS * WAVE + WAVE + lane];
+        E += S.partials[(int64_t)u * SPH_PARTS * WAVE + 2 * WAVE + lane];
     }
     bool still = false;
     double hn = 0.0;
@@ -572,11 +582,22 @@ __global__ __launch_bounds__(WAVE) void k_sph_update(int64_t n, const Rec64* __r
             if (u > 0.0 && u - l <= 4e-16 * u) {     // the bracket has closed
                 state[s] = SPH_DONE;
             } else {
-                // Newton in v = h^3, where N is close to linear: dN/dv = (dN/dh) / (3 h^2)
-                const double dN = -32.0 / 3.0 * D / (mi * hh);
+                // Halley's step in v = h^3, where N is close to linear, within
+                // SPH_HALLEY_BAND of the target, Newton's farther out (just after a
+                // first neighbour enters, N is strongly convex and Halley's steps
+                // are short) or where Halley's denominator is not positive; from
+                // dN/dh = -(32/3) D / (m h) and d2N/dh2 = (32/3) (E + 2 D) / (m h^2)
+                const double Nh = -32.0 / 3.0 * D / (mi * hh);
+                const double Nhh = 32.0 / 3.0 * (E + 2.0 * D) / (mi * hh * hh);
+                const double h2 = hh * hh;
+                const double Nv = Nh / (3.0 * h2);
+                const double Nvv = (Nhh - 2.0 * Nh / hh) / (9.0 * h2 * h2);
                 hn = -1.0;
-                if (dN > 0.0) {
-                    const double v = hh * hh * hh - f * 3.0 * hh * hh / dN;
+                bool halley = false;
+                if (Nv > 0.0) {
+                    const double den = 2.0 * Nv * Nv - f * Nvv;
+                    halley = den > 0.0 && fabs(f) <= SPH_HALLEY_BAND * target;
+                    const double v = hh * h2 - (halley ? 2.0 * f * Nv / den : f / Nv);
                     if (v > 0.0) hn = cbrt(v);
                 }
                 bool failed = false;
@@ -593,8 +614,16 @@ __global__ __launch_bounds__(WAVE) void k_sph_update(int64_t n, const Rec64* __r
                     }
                 } else if (!(hn > l && hn < u)) {
                     hn = 0.5 * (l + u);
+                    halley = false;
                 }
-                if (!failed) {
+                if (!failed && halley && u > 0.0 && fabs(f) <= SPH_ACCEPT * target) {
+                    // Halley's error after the step is of the order of the cube of the
+                    // current one: the step lands within the tolerance and is taken as
+                    // the root, where N = T gives rho = 3 T m / (4 pi h^3)
+                    h[s] = hn;
+                    rho[s] = 3.0 * target * mi / (4.0 * M_PI * hn * hn * hn);
+                    state[s] = SPH_DONE;
+                } else if (!failed) {
                     lo[s] = l;
                     hi[s] = u;
                     h[s] = hn;
@@ -660,7 +689,7 @@ int lists_alloc(SphWork& W, SphLists& S, int64_t groups, int64_t waves, int64_t 
     W.lists = nullptr;
     auto up = [](int64_t b) { return (b + 255) & ~(int64_t)255; };
     const int64_t bytes = up(64 * chunks * 8) + 2 * up(chunks * 4) + 4 * up(units * 4) + 2 * up(groups * 4) +
-                          up(groups * 8) + up(groups * 32) + up(waves * 2 * front * 4) + up(units * 2 * WAVE * 8);
+                          up(groups * 8) + up(groups * 32) + up(waves * 2 * front * 4) + up(units * SPH_PARTS * WAVE * 8);
     if (hipMallocAsync(&W.lists, (size_t)bytes, st) != hipSuccess) {
         W.lists = nullptr;
         (void)hipGetLastError();
@@ -686,7 +715,7 @@ int lists_alloc(SphWork& W, SphLists& S, int64_t groups, int64_t waves, int64_t 
     S.need = (int32_t*)take(groups * 4);
     S.gbox = (double*)take(groups * 32);
     S.front = (uint32_t*)take(waves * 2 * front * 4);
-    S.partials = (double*)take(units * 2 * WAVE * 8);
+    S.partials = (double*)take(units * SPH_PARTS * WAVE * 8);
     S.counters = counters;
     S.cap_chunks = chunks;
     S.cap_units = units;

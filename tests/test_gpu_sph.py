@@ -1,6 +1,6 @@
 """Parity of the SPH density (HIP path through the C ABI) with the SPH oracle.
 Both are FP64 and solve for the same unique root of the neighbour-number
-equation (the GPU by Newton iterations to |N - T| <= 1e-13 T, the oracle by
+equation (the GPU by Halley iterations to |N - T| <= 1e-13 T, the oracle by
 bisection), so h and rho agree to 1e-10 relative."""
 import numpy as np
 import pytest
