@@ -60,23 +60,32 @@ enum { SC_CHUNKS = 0, SC_UNITS = 1, SC_OVERFLOW = 2, SC_GROUP = 3, SC_ACTIVE = 4
 
 inline dim3 sph_grid(int64_t n) { return dim3((unsigned)((n + SPH_TPB - 1) / SPH_TPB)); }
 
-// w(q), q w'(q) and q^2 w''(q) of the cubic spline (zero beyond q = 1).
+// w(q), q w'(q) and q^2 w''(q) of the cubic spline for 0 <= q <= 1, without a
+// branch: as a sum of truncated powers, w(q) = 2 a^3 - 8 b^3 with a = 1 - q and
+// b = max(0, 1/2 - q) (which is 1 - 6 q^2 + 6 q^3 below q = 1/2 and 2 (1 - q)^3
+// above), so w' = -6 a^2 + 24 b^2 and w'' = 12 a - 48 b.
 __device__ inline void spline_w(double q, double& wq, double& qdw, double& q2ddw)
 {
-    if (q <= 0.5) {
-        wq = 1.0 - 6.0 * q * q + 6.0 * q * q * q;
-        qdw = q * (-12.0 * q + 18.0 * q * q);
-        q2ddw = q * q * (-12.0 + 36.0 * q);
-    } else if (q <= 1.0) {
-        const double u = 1.0 - q;
-        wq = 2.0 * u * u * u;
-        qdw = -6.0 * q * u * u;
-        q2ddw = 12.0 * q * q * u;
-    } else {
-        wq = 0.0;
-        qdw = 0.0;
-        q2ddw = 0.0;
-    }
+    const double a = 1.0 - q, b = fmax(0.5 - q, 0.0);
+    const double a2 = a * a, b2 = b * b;
+    wq = 2.0 * (a2 * a) - 8.0 * (b2 * b);
+    qdw = q * (24.0 * b2 - 6.0 * a2);
+    q2ddw = (q * q) * (12.0 * a - 48.0 * b);
+}
+
+// sqrt(x) for x >= 0 finite: v_rsq_f64 (relative error up to 2^-23) refined by a
+// Goldschmidt step and a Newton correction (each squaring the relative error), and
+// 0 for x = 0
+__device__ inline double sqrt_refined(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, hy = 0.5 * y;
+    const double e = fma(-hy, g, 0.5);
+    g = fma(g, e, g);
+    hy = fma(hy, e, hy);
+    const double d = fma(-g, g, x);
+    g = fma(d, hy, g);
+    return x > 0.0 ? g : 0.0;
 }
 
 // Minimum image of a separation; inv_box = 1 / L (a product instead of an FP64
@@ -511,7 +520,7 @@ __global__ __launch_bounds__(WAVE) void k_sph_eval(int64_t n, const Rec64* __res
                 const double r2 = (dx * dx + dy * dy) + dz * dz;
                 if (r2 < h2) {
                     double wq, qdw, q2ddw;
-                    spline_w(sqrt(r2) * inv_h, wq, qdw, q2ddw);
+                    spline_w(sqrt_refined(r2) * inv_h, wq, qdw, q2ddw);
                     A += p.m * wq;
                     D += p.m * qdw;
                     E += p.m * q2ddw;
