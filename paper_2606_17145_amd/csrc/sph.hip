@@ -88,6 +88,22 @@ __device__ inline double sqrt_refined(double x)
     return x > 0.0 ? g : 0.0;
 }
 
+// Inclusive sum over the 64 lanes of a wave by DPP moves (no LDS round trips):
+// shifts by 1, 2, 4 and 8 within each row of 16 lanes (lanes without a source add
+// 0), then the total of row 0 added to row 1 and that of row 2 to row 3 (row
+// broadcast of lane 15), then the total of rows 0-1 added to rows 2 and 3 (row
+// broadcast of lane 31).  Needs the full wave active.
+__device__ inline uint32_t wave_scan_incl(uint32_t v)
+{
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, true);   // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, true);   // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, true);   // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, true);   // row_shr:8
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);  // row_bcast:15, rows 1 and 3
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);  // row_bcast:31, rows 2 and 3
+    return v;
+}
+
 // Minimum image of a separation; inv_box = 1 / L (a product instead of an FP64
 // division; the image can differ from d / L rounding only at an exact half-box
 // tie, where both images are equally far).
@@ -312,19 +328,14 @@ __global__ __launch_bounds__(WAVE) void k_sph_gather(int64_t n, int64_t m, int64
         auto append = [&](uint64_t b, uint64_t p, uint32_t k) __attribute__((always_inline)) {
             while (b && room()) {
                 const uint32_t mine = (b >> lane) & 1 ? k : 0u;
-                uint32_t incl = mine;
-#pragma unroll
-                for (int o = 1; o < WAVE; o <<= 1) {
-                    const uint32_t y = (uint32_t)__shfl_up((int)incl, o, WAVE);
-                    if (lane >= o) incl += y;
-                }
+                const uint32_t incl = wave_scan_incl(mine);
                 const uint32_t rank = (uint32_t)__popcll(b & below);
                 const bool fits = (b >> lane) & 1 && rank < (uint32_t)WAVE - nl && incl - mine < SPH_CHUNK_CAND - ncand;
                 const uint64_t take = __ballot(fits);
                 if (fits) S.ent[64 * (int64_t)cc + nl + rank] = p;
                 // the candidates taken: the prefix at the last lane taken
                 const int last = 63 - __builtin_clzll(take);
-                const uint32_t added = (uint32_t)__shfl((int)incl, last, WAVE);
+                const uint32_t added = (uint32_t)__builtin_amdgcn_readlane((int)incl, last);
                 nl += (uint32_t)__popcll(take);
                 ncand += added;
                 ucand += added;
@@ -367,8 +378,26 @@ __global__ __launch_bounds__(WAVE) void k_sph_gather(int64_t n, int64_t m, int64
                     }
                     // nodes listed whole: their particle ranges
                     append_ranges(whole ? (uint32_t)n_first[nd] : 0u, whole ? (uint32_t)n_count[nd] : 0u);
-                    // opened nodes: node children to the next level, particle children listed
+                    // opened nodes: node children to the next level, particle children listed;
+                    // the particle children's records are read together first (every
+                    // address selected, slots without a particle child read particle 0)
                     const bool open = keep && !whole;
+                    bool near8[8];
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        const bool kid = open && (uint32_t)k < r.meta;
+                        const uint32_t ch = kid ? r.kids[k] : 0u;
+                        const bool isp = kid && (ch & ITEM_PARTICLE);
+                        const Rec64 p = prec[isp ? ch & ~ITEM_PARTICLE : 0u];
+                        const double xp[3] = {p.x, p.y, p.z};
+                        double d2 = 0.0;
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) {
+                            const double t = fmax(fabs(min_image(xp[a] - mid[a], box, inv_box)) - hw[a], 0.0);
+                            d2 += t * t;
+                        }
+                        near8[k] = isp && d2 <= R2;
+                    }
 #pragma unroll
                     for (int k = 0; k < 8; ++k) {
                         const bool kid = open && (uint32_t)k < r.meta;
@@ -384,19 +413,7 @@ __global__ __launch_bounds__(WAVE) void k_sph_gather(int64_t n, int64_t m, int64
                                 nb += cnt;
                             }
                         }
-                        bool near = false;
-                        if (kid && (ch & ITEM_PARTICLE)) {
-                            const Rec64 p = prec[ch & ~ITEM_PARTICLE];
-                            const double xp[3] = {p.x, p.y, p.z};
-                            double d2 = 0.0;
-#pragma unroll
-                            for (int a = 0; a < 3; ++a) {
-                                const double t = fmax(fabs(min_image(xp[a] - mid[a], box, inv_box)) - hw[a], 0.0);
-                                d2 += t * t;
-                            }
-                            near = d2 <= R2;
-                        }
-                        append(__ballot(near), (uint64_t)(ch & ~ITEM_PARTICLE) | (1ull << 32), 1u);
+                        append(__ballot(near8[k]), (uint64_t)(ch & ~ITEM_PARTICLE) | (1ull << 32), 1u);
                     }
                 }
                 // the next level becomes the current one
@@ -482,15 +499,10 @@ __global__ __launch_bounds__(WAVE) void k_sph_eval(int64_t n, const Rec64* __res
             first = (uint32_t)v;
             count = (uint32_t)(v >> 32);
         }
-        uint32_t incl = count;
-#pragma unroll
-        for (int o = 1; o < WAVE; o <<= 1) {
-            const uint32_t y = (uint32_t)__shfl_up((int)incl, o, WAVE);
-            if (lane >= o) incl += y;
-        }
+        const uint32_t incl = wave_scan_incl(count);
         s_off[lane] = incl - count;
         s_first[lane] = first;
-        const uint32_t total = (uint32_t)__shfl((int)incl, WAVE - 1, WAVE);
+        const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, WAVE - 1);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
