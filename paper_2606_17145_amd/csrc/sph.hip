@@ -109,18 +109,39 @@ __device__ inline uint32_t wave_scan_incl(uint32_t v)
 // tie, where both images are equally far).
 __device__ inline double min_image(double d, double box, double inv_box) { return d - box * rint(d * inv_box); }
 
-__device__ inline double wave_max_d(double v)
+// A double moved between lanes by one DPP permutation (both halves; every source
+// lane valid for the permutations used here).
+template <int CTRL>
+__device__ inline double dpp_d(double v)
 {
-#pragma unroll
-    for (int o = 1; o < WAVE; o <<= 1) v = fmax(v, __shfl_xor(v, o, WAVE));
-    return v;
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xF, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
-__device__ inline double wave_min_d(double v)
+__device__ inline double readlane_d(double v, int l)
 {
-#pragma unroll
-    for (int o = 1; o < WAVE; o <<= 1) v = fmin(v, __shfl_xor(v, o, WAVE));
-    return v;
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
+// Wave-wide max / min (exact, so independent of the order): within each row of 16
+// lanes by DPP exchanges (lane pairs 1 and 2 apart in a quad, then the half-row and
+// row mirrors), then over the four rows' values read from lanes 0, 16, 32 and 48.
+// Needs the full wave active.
+template <bool MAX>
+__device__ inline double wave_ext_d(double v)
+{
+    auto f = [](double a, double b) { return MAX ? fmax(a, b) : fmin(a, b); };
+    v = f(v, dpp_d<0xB1>(v));    // quad_perm [1, 0, 3, 2]
+    v = f(v, dpp_d<0x4E>(v));    // quad_perm [2, 3, 0, 1]
+    v = f(v, dpp_d<0x141>(v));   // row_half_mirror
+    v = f(v, dpp_d<0x140>(v));   // row_mirror
+    return f(f(readlane_d(v, 0), readlane_d(v, 16)), f(readlane_d(v, 32), readlane_d(v, 48)));
+}
+__device__ inline double wave_max_d(double v) { return wave_ext_d<true>(v); }
+__device__ inline double wave_min_d(double v) { return wave_ext_d<false>(v); }
 
 struct SphLists {
     uint64_t* ent;          // candidate range: first sorted particle | count (1..64) << 32; 64 per chunk
