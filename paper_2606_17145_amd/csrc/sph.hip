@@ -508,6 +508,16 @@ __global__ __launch_bounds__(WAVE) void k_sph_eval(int64_t n, const Rec64* __res
     const double ox = min_image(me.x - cx, box, inv_box), oy = min_image(me.y - cy, box, inv_box),
                  oz = min_image(me.z - cz, box, inv_box);
     double A = 0.0, D = 0.0, E = 0.0;   // sums of m_j w(q_j), m_j q_j w'(q_j), m_j q_j^2 w''(q_j)
+    // the box of the active lanes' offsets and their largest h: a candidate farther
+    // from that box than the largest h is inside no lane's ball and is not staged (the
+    // bound has a relative margin of 1e-9 over the rounding of the lanes' own
+    // separations, so every candidate a lane would count is kept, in its order)
+    const double blx = wave_min_d(act ? ox : INFINITY), bhx = wave_max_d(act ? ox : -INFINITY);
+    const double bly = wave_min_d(act ? oy : INFINITY), bhy = wave_max_d(act ? oy : -INFINITY);
+    const double blz = wave_min_d(act ? oz : INFINITY), bhz = wave_max_d(act ? oz : -INFINITY);
+    const double hmax = wave_max_d(hh);
+    const double lim2 = hmax * hmax * (1.0 + 1e-9);
+    const uint64_t below = (1ull << lane) - 1ull;
     int32_t c = S.unit_chunk[u];
     for (int32_t q = 0; q < nch; ++q) {
         // the chunk's entries (ranges of sorted particles) and their offsets in the
@@ -542,14 +552,23 @@ __global__ __launch_bounds__(WAVE) void k_sph_eval(int64_t n, const Rec64* __res
         Rec64 nxt{0.0, 0.0, 0.0, 0.0};
         fetch(0, nxt);
         for (uint32_t base = 0; base < total; base += WAVE) {
-            if (base + (uint32_t)lane < total)
-                s_c[lane] = Rec64{min_image(nxt.x - cx, box, inv_box), min_image(nxt.y - cy, box, inv_box),
-                                  min_image(nxt.z - cz, box, inv_box), nxt.m};
+            const Rec64 cand{min_image(nxt.x - cx, box, inv_box), min_image(nxt.y - cy, box, inv_box),
+                             min_image(nxt.z - cz, box, inv_box), nxt.m};
+            bool keep = base + (uint32_t)lane < total && hmax > 0.0;
+            if (keep && !wide) {
+                const double tx = fmax(fmax(blx - cand.x, cand.x - bhx), 0.0);
+                const double ty = fmax(fmax(bly - cand.y, cand.y - bhy), 0.0);
+                const double tz = fmax(fmax(blz - cand.z, cand.z - bhz), 0.0);
+                keep = (tx * tx + ty * ty) + tz * tz <= lim2;
+            }
+            const uint64_t kept = __ballot(keep);
+            if (keep) s_c[__popcll(kept & below)] = cand;
             fetch(base + WAVE, nxt);
-            const int32_t cnt = total - base < (uint32_t)WAVE ? (int32_t)(total - base) : WAVE;
+            const int32_t cnt = (int32_t)__popcll(kept);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");            auto candidate = [&](const Rec64& p, double dx, double dy, double dz) __attribute__((always_inline)) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            auto candidate = [&](const Rec64& p, double dx, double dy, double dz) __attribute__((always_inline)) {
                 const double r2 = (dx * dx + dy * dy) + dz * dz;
                 if (r2 < h2) {
                     double wq, qdw, q2ddw;
