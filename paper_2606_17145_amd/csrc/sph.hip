@@ -199,7 +199,10 @@ __global__ void k_sph_init(int64_t n, int64_t m, const int32_t* __restrict__ ppa
 // The candidates are thus a superset of the particles within R of the box (the
 // evaluation applies each lane's exact r < h).  The group's previous units are
 // marked empty first.
-constexpr uint32_t SPH_WHOLE = 8;    // nodes of at most this many particles are listed whole
+#ifndef SR_SPH_WHOLE
+#define SR_SPH_WHOLE 32
+#endif
+constexpr uint32_t SPH_WHOLE = SR_SPH_WHOLE;   // nodes of at most this many particles are listed whole
 constexpr uint32_t SPH_PIECE = 32;   // largest candidate count of one list entry
 constexpr uint32_t SPH_CHUNK_CAND = 256;    // a chunk closes at this many candidates
 constexpr uint32_t SPH_UNIT_CAND = 1024;    // a unit closes at this many candidates
