@@ -204,8 +204,14 @@ __global__ void k_sph_init(int64_t n, int64_t m, const int32_t* __restrict__ ppa
 #endif
 constexpr uint32_t SPH_WHOLE = SR_SPH_WHOLE;   // nodes of at most this many particles are listed whole
 constexpr uint32_t SPH_PIECE = 32;   // largest candidate count of one list entry
-constexpr uint32_t SPH_CHUNK_CAND = 256;    // a chunk closes at this many candidates
-constexpr uint32_t SPH_UNIT_CAND = 1024;    // a unit closes at this many candidates
+#ifndef SR_SPH_CHUNK_CAND
+#define SR_SPH_CHUNK_CAND 256
+#endif
+#ifndef SR_SPH_UNIT_CAND
+#define SR_SPH_UNIT_CAND 1024
+#endif
+constexpr uint32_t SPH_CHUNK_CAND = SR_SPH_CHUNK_CAND;   // a chunk closes at this many candidates
+constexpr uint32_t SPH_UNIT_CAND = SR_SPH_UNIT_CAND;     // a unit closes at this many candidates
 constexpr int SPH_CHUNK_BATCH = 16;  // chunk indices a wave reserves per atomic
 constexpr int SPH_UNIT_BATCH = 2;    // unit indices a wave reserves per atomic
 
