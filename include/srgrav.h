@@ -394,8 +394,10 @@ void pm_free(sr_pm* pm);
  *
  * Neighbours are gathered per group of 64 Morton-consecutive particles into
  * candidate lists that are kept across iterations while the group's smoothing
- * lengths stay within the gathered radius.  The host waits for the stream once
- * per iteration (at most 100).  The workspace (about 36 bytes per particle plus
+ * lengths stay within the gathered radius.  The host waits once per iteration
+ * (at most 100) for an event behind the copy of a few counters to the handle's
+ * pinned read-back buffer, which the walk entry points use too: calls on one
+ * handle must not overlap.  The workspace (about 36 bytes per particle plus
  * the candidate lists, grown on demand) comes from the stream-ordered allocator
  * and is released before the call returns; the sums are deterministic.
  */

@@ -57,6 +57,7 @@ enum : int32_t { SPH_ACTIVE = 0, SPH_DONE = 1, SPH_FAILED = 2 };
 // list counters: chunks taken, units taken, overflow, next group, active particles,
 // regather request
 enum { SC_CHUNKS = 0, SC_UNITS = 1, SC_OVERFLOW = 2, SC_GROUP = 3, SC_ACTIVE = 4, SC_REGATHER = 5, SC_WORDS = 8 };
+static_assert(SC_WORDS <= 8, "the counters are read back through the handle's 8-word pinned buffer");
 
 inline dim3 sph_grid(int64_t n) { return dim3((unsigned)((n + SPH_TPB - 1) / SPH_TPB)); }
 
@@ -857,12 +858,15 @@ int sph_density(sr_tree* t, double n_ngb, double* h, double* rho, int64_t* uncon
         hipLaunchKernelGGL(k_sph_update, dim3((unsigned)groups), dim3(WAVE), 0, st, n, t->prec64, n_ngb, h_max, hs,
                            lo, hi, state, rs, S);
         sr_timing_mark(SR_T_SPH_ITER, false, st);
+        // the counters go to the handle's pinned read-back buffer; the host waits for
+        // the event behind that copy
         if (hipGetLastError() != hipSuccess ||
-            hipMemcpyAsync(hc, ctr, sizeof(hc), hipMemcpyDeviceToHost, st) != hipSuccess ||
-            hipStreamSynchronize(st) != hipSuccess) {
+            hipMemcpyAsync(t->h_counters, ctr, sizeof(hc), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipEventRecord(t->ev_counters, st) != hipSuccess || hipEventSynchronize(t->ev_counters) != hipSuccess) {
             rc = sr_fail(SR_EHIP, "sph_density: iteration %d failed", it);
             break;
         }
+        for (int k = 0; k < SC_WORDS; ++k) hc[k] = t->h_counters[k];
         if (hc[SC_OVERFLOW]) {
             if (gathered_full) {
                 // the lists or a level of the walk did not fit: grow both
