@@ -5,6 +5,7 @@ bisection), so h and rho agree to 1e-10 relative."""
 import numpy as np
 import pytest
 import torch
+from scipy.spatial import cKDTree
 
 from oracle import sph as OS
 from paper_2606_17145_amd import workloads as WL
@@ -27,6 +28,21 @@ def run(sg, pos, mass, box, n_ngb):
     return h.cpu().numpy(), rho.cpu().numpy(), bad
 
 
+def neighbour_number_at(pos, mass, box, tg, h):
+    """N_i(h_i) of the targets tg at the given h (indexed by particle), from the
+    oracle's kernel shape over every particle within h_i (minimum image)."""
+    x = OS.wrap(pos, box)
+    m = np.broadcast_to(np.asarray(mass, dtype=np.float64), (len(x),))
+    tree = cKDTree(x, boxsize=box)
+    out = np.empty(len(tg))
+    for k, i in enumerate(tg):
+        j = np.asarray(tree.query_ball_point(x[i], r=h[i] * (1 + 1e-9)), dtype=np.int64)
+        d = x[j] - x[i]
+        d -= box * np.rint(d / box)
+        out[k] = OS.neighbour_number(np.sqrt((d * d).sum(1))[None, :], (m[j] / m[i])[None, :], np.array([h[i]]))[0]
+    return out
+
+
 def check(sg, pos, mass, box, n_ngb, tag, targets=None):
     print(f"sph parity: {tag} N={len(pos)} n_ngb={n_ngb}", flush=True)
     h, rho, bad = run(sg, pos, mass, box, n_ngb)
@@ -37,6 +53,13 @@ def check(sg, pos, mass, box, n_ngb, tag, targets=None):
     er = np.abs(rho[tg] / rr - 1).max()
     print(f"   max relative error: h {eh:.2e}, rho {er:.2e}", flush=True)
     assert eh <= 1e-10 and er <= 1e-10
+    # the stopping rule itself: N at the returned h within the stated tolerance of
+    # the target (1e-13 n_ngb, plus the rounding of this FP64 sum), also for the
+    # particles whose last Halley step was accepted without a further evaluation
+    sub = tg[:2048]
+    en = np.abs(neighbour_number_at(pos, mass, box, sub, h) / n_ngb - 1).max()
+    print(f"   max |N(h) - T| / T at the returned h: {en:.2e}", flush=True)
+    assert en <= 3e-13
     return h, rho
 
 
