@@ -204,7 +204,11 @@ __global__ void k_sph_init(int64_t n, int64_t m, const int32_t* __restrict__ ppa
 #define SR_SPH_WHOLE 32
 #endif
 constexpr uint32_t SPH_WHOLE = SR_SPH_WHOLE;   // nodes of at most this many particles are listed whole
-constexpr uint32_t SPH_PIECE = 32;   // largest candidate count of one list entry
+#ifndef SR_SPH_PIECE
+#define SR_SPH_PIECE 64
+#endif
+constexpr uint32_t SPH_PIECE = SR_SPH_PIECE;   // largest candidate count of one list entry
+static_assert(SPH_PIECE >= 1 && SPH_PIECE <= 64, "a list entry holds 1 to 64 candidates");
 #ifndef SR_SPH_CHUNK_CAND
 #define SR_SPH_CHUNK_CAND 256
 #endif
