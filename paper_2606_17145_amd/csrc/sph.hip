@@ -50,6 +50,12 @@ constexpr int SPH_PARTS = 3;                 // per-unit sums per particle
 #define SR_SPH_UCH 2
 #endif
 constexpr double SPH_MARGIN = SR_SPH_MARGIN;
+// margin of a renewed (partial) gather: the groups that ask again, whose h is
+// closer to its root than the initial estimate
+#ifndef SR_SPH_MARGIN_RENEW
+#define SR_SPH_MARGIN_RENEW 1.1
+#endif
+constexpr double SPH_MARGIN_RENEW = SR_SPH_MARGIN_RENEW;
 constexpr int SPH_UCH = SR_SPH_UCH;
 constexpr int SPH_GATHER_WG_PER_CU = 4;      // persistent gather waves per compute unit
 
@@ -220,7 +226,7 @@ constexpr uint32_t SPH_UNIT_CAND = SR_SPH_UNIT_CAND;     // a unit closes at thi
 constexpr int SPH_CHUNK_BATCH = 16;  // chunk indices a wave reserves per atomic
 constexpr int SPH_UNIT_BATCH = 2;    // unit indices a wave reserves per atomic
 
-__global__ __launch_bounds__(WAVE) void k_sph_gather(int64_t n, int64_t m, int64_t groups,
+__global__ __launch_bounds__(WAVE) void k_sph_gather(int64_t n, int64_t m, int64_t groups, double margin,
                                                      const WalkRec64* __restrict__ wrec,
                                                      const int32_t* __restrict__ n_first,
                                                      const int32_t* __restrict__ n_count,
@@ -278,7 +284,7 @@ __global__ __launch_bounds__(WAVE) void k_sph_gather(int64_t n, int64_t m, int64
             }
             continue;
         }
-        const double R = SPH_MARGIN * hmax;
+        const double R = margin * hmax;
         const double R2 = R * R * (1.0 + 1e-6);
         // the box of the active particles: centre and half-width per axis (an axis
         // wider than half the box passes every test)
@@ -854,7 +860,8 @@ int sph_density(sr_tree* t, double n_ngb, double* h, double* rho, int64_t* uncon
             } else {
                 hipLaunchKernelGGL(k_sph_clear, dim3(1), dim3(SC_WORDS), 0, st, ctr, SC_OVERFLOW, SC_GROUP + 1);
             }
-            hipLaunchKernelGGL(k_sph_gather, dim3((unsigned)waves), dim3(WAVE), 0, st, n, m, groups, t->wrec64,
+            hipLaunchKernelGGL(k_sph_gather, dim3((unsigned)waves), dim3(WAVE), 0, st, n, m, groups,
+                               full ? SPH_MARGIN : SPH_MARGIN_RENEW, t->wrec64,
                                t->n_first, t->n_count, t->prec64, box, state, hs, S);
         }
         hipLaunchKernelGGL(k_sph_clear, dim3(1), dim3(SC_WORDS), 0, st, ctr, SC_ACTIVE, SC_REGATHER + 1);
