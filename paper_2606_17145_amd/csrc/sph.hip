@@ -36,7 +36,10 @@ constexpr int SPH_TPB = 256;
 constexpr int SPH_MAX_ITER = 100;
 constexpr double SPH_INIT_FRACTION = 0.25;   // the initial density from the smallest ancestor with T/4 particles
 constexpr double SPH_GROW = 2.0;             // largest growth of h per step before an upper bound is known
-constexpr double SPH_HALLEY_BAND = 0.1;      // |N - T| / T below which the step is Halley's (else Newton's)
+#ifndef SR_SPH_HALLEY_BAND
+#define SR_SPH_HALLEY_BAND 0.1
+#endif
+constexpr double SPH_HALLEY_BAND = SR_SPH_HALLEY_BAND;   // |N - T| / T below which the step is Halley's (else Newton's)
 constexpr double SPH_ACCEPT = 1e-5;          // |N - T| / T below which a bracketed Halley step ends the iteration
 constexpr int SPH_PARTS = 3;                 // per-unit sums per particle
 // Gathered radius / largest active h of the group, and chunks per evaluation
