@@ -407,21 +407,37 @@ __global__ __launch_bounds__(WAVE) void k_sph_gather(int64_t n, int64_t m, int64
             __syncthreads();   // (one wave: orders the frontier's global stores before its loads)
             while (na > 0 && !overflow) {
                 uint32_t nb = 0;
+                // a level's nodes in batches of 64, read ahead: the records of the next
+                // batch and the ids of the one after it are read while a batch is
+                // processed (lanes past the level's end read node 0, the root)
+                auto ids_of = [&](uint32_t b) __attribute__((always_inline)) -> uint32_t {
+                    return cur_ids[b + lane < na ? b + lane : 0u];
+                };
+                uint32_t id_next = ids_of(0);
+                uint32_t nd_n = lane < na ? id_next : 0u;
+                WalkRec64 r_n = wrec[nd_n];
+                uint32_t cnt_n = (uint32_t)n_count[nd_n], first_n = (uint32_t)n_first[nd_n];
+                id_next = ids_of(WAVE);
                 for (uint32_t b0 = 0; b0 < na && !overflow; b0 += WAVE) {
                     const bool has = b0 + lane < na;
-                    WalkRec64 r{};
-                    uint32_t nd = 0;
+                    const WalkRec64 r = r_n;
+                    const uint32_t ncount = cnt_n, nfirst = first_n;
+                    if (b0 + WAVE < na) {
+                        nd_n = b0 + WAVE + lane < na ? id_next : 0u;
+                        r_n = wrec[nd_n];
+                        cnt_n = (uint32_t)n_count[nd_n];
+                        first_n = (uint32_t)n_first[nd_n];
+                        id_next = ids_of(b0 + 2 * WAVE);
+                    }
                     bool keep = false, whole = false;
                     if (has) {
-                        nd = cur_ids[b0 + lane];
-                        r = wrec[nd];
                         double near2, far2;
                         dist2(r, near2, far2);
                         keep = near2 <= R2;
-                        whole = keep && (far2 <= R2 || r.meta == META_BUCKET || (uint32_t)n_count[nd] <= SPH_WHOLE);
+                        whole = keep && (far2 <= R2 || r.meta == META_BUCKET || ncount <= SPH_WHOLE);
                     }
                     // nodes listed whole: their particle ranges
-                    append_ranges(whole ? (uint32_t)n_first[nd] : 0u, whole ? (uint32_t)n_count[nd] : 0u);
+                    append_ranges(whole ? nfirst : 0u, whole ? ncount : 0u);
                     // opened nodes: node children to the next level, particle children listed;
                     // the particle children's records are read together first (every
                     // address selected, slots without a particle child read particle 0)
