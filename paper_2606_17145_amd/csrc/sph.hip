@@ -60,7 +60,10 @@ constexpr double SPH_MARGIN = SR_SPH_MARGIN;
 #endif
 constexpr double SPH_MARGIN_RENEW = SR_SPH_MARGIN_RENEW;
 constexpr int SPH_UCH = SR_SPH_UCH;
-constexpr int SPH_GATHER_WG_PER_CU = 4;      // persistent gather waves per compute unit
+#ifndef SR_SPH_GATHER_WG_PER_CU
+#define SR_SPH_GATHER_WG_PER_CU 4
+#endif
+constexpr int SPH_GATHER_WG_PER_CU = SR_SPH_GATHER_WG_PER_CU;   // persistent gather waves per compute unit
 
 enum : int32_t { SPH_ACTIVE = 0, SPH_DONE = 1, SPH_FAILED = 2 };
 // list counters: chunks taken, units taken, overflow, next group, active particles,
@@ -226,7 +229,10 @@ static_assert(SPH_PIECE >= 1 && SPH_PIECE <= 64, "a list entry holds 1 to 64 can
 #endif
 constexpr uint32_t SPH_CHUNK_CAND = SR_SPH_CHUNK_CAND;   // a chunk closes at this many candidates
 constexpr uint32_t SPH_UNIT_CAND = SR_SPH_UNIT_CAND;     // a unit closes at this many candidates
-constexpr int SPH_CHUNK_BATCH = 16;  // chunk indices a wave reserves per atomic
+#ifndef SR_SPH_CHUNK_BATCH
+#define SR_SPH_CHUNK_BATCH 16
+#endif
+constexpr int SPH_CHUNK_BATCH = SR_SPH_CHUNK_BATCH;  // chunk indices a wave reserves per atomic
 constexpr int SPH_UNIT_BATCH = 2;    // unit indices a wave reserves per atomic
 
 __global__ __launch_bounds__(WAVE) void k_sph_gather(int64_t n, int64_t m, int64_t groups, double margin,
